@@ -1,0 +1,252 @@
+"""ctypes binding of the FP64 CPU oracle (orc.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+CPU-baseline leg of the benchmark.  The product library never loads it.
+
+Array conventions: positions in cell units, SoA ``pos[3, n]``; proper
+velocities ``u[3, n]``; vector mesh fields ``F[3, nz, ny, nx]`` (x fastest),
+scalar mesh fields ``[nz, ny, nx]``.  All float64, C-contiguous.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "orc.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile orc.c into liborc.so with gcc (plain -O2, single thread)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32 * 3),
+        ("d", ctypes.c_double * 3),
+        ("dt", ctypes.c_double),
+        ("c", ctypes.c_double),
+        ("eps0", ctypes.c_double),
+        ("shape_order", ctypes.c_int32),
+        ("field_order", ctypes.c_int32),
+        ("alpha", ctypes.c_double),
+        ("pusher", ctypes.c_int32),
+        ("relax_tol", ctypes.c_double),
+        ("relax_max_iter", ctypes.c_int32),
+        ("rho_background", ctypes.c_double),
+    ]
+
+
+def make_params(n=(16, 16, 16), d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shape_order=2,
+                field_order=2, alpha=0.55, pusher=0, relax_tol=1e-14, relax_max_iter=200,
+                rho_background=0.0) -> Params:
+    p = Params()
+    p.n[:] = [int(v) for v in n]
+    p.d[:] = [float(v) for v in d]
+    p.dt, p.c, p.eps0 = float(dt), float(c), float(eps0)
+    p.shape_order, p.field_order = int(shape_order), int(field_order)
+    p.alpha, p.pusher = float(alpha), int(pusher)
+    p.relax_tol, p.relax_max_iter = float(relax_tol), int(relax_max_iter)
+    p.rho_background = float(rho_background)
+    return p
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_P = ctypes.POINTER(Params)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        L = _lib
+        L.orc_W.restype = ctypes.c_double
+        L.orc_W.argtypes = [ctypes.c_int, ctypes.c_double]
+        L.orc_gather.argtypes = [_P, _D, _D, _D, _D, _D]
+        L.orc_push.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, _D, _D, _D]
+        L.orc_step_species.restype = ctypes.c_int
+        L.orc_step_species.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_int64, _D, _D, _D, _D, _D]
+        L.orc_deposit_current.argtypes = [_P, ctypes.c_double, ctypes.c_double, _D, _D, _D]
+        L.orc_deposit_rho.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int64, _D, _D]
+        L.orc_fd_coeffs.argtypes = [ctypes.c_int, _D]
+        L.orc_deriv.argtypes = [_P, _D, _D, ctypes.c_int, ctypes.c_int]
+        for name in ("orc_curl_up", "orc_curl_down", "orc_div_down", "orc_div_up", "orc_laplacian_B"):
+            getattr(L, name).argtypes = [_P, _D, _D]
+        L.orc_field_step.restype = ctypes.c_int
+        L.orc_field_step.argtypes = [_P, _D, _D, _D, _D]
+        L.orc_current_high_order.argtypes = [_P, _D]
+        L.orc_species_moments.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int64, _D, _D, _D]
+        L.orc_field_energy.argtypes = [_P, _D, _D, _D]
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], (a.dtype, a.flags)
+    return a.ctypes.data_as(_D)
+
+
+def _vec(P: Params):
+    nx, ny, nz = P.n[0], P.n[1], P.n[2]
+    return (3, nz, ny, nx)
+
+
+def _scal(P: Params):
+    return (P.n[2], P.n[1], P.n[0])
+
+
+# -- single-particle pieces ------------------------------------------------------------------
+def W(order: int, delta: float) -> float:
+    return lib().orc_W(int(order), float(delta))
+
+
+def gather(P: Params, E: np.ndarray, B: np.ndarray, X) -> tuple[np.ndarray, np.ndarray]:
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Ep = np.zeros(3)
+    Bp = np.zeros(3)
+    lib().orc_gather(ctypes.byref(P), _ptr(E), _ptr(B), _ptr(X), _ptr(Ep), _ptr(Bp))
+    return Ep, Bp
+
+
+def push(pusher: int, q: float, m: float, dt: float, c: float, E, B, u) -> np.ndarray:
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    uu = np.array(u, dtype=np.float64)
+    lib().orc_push(int(pusher), q, m, dt, c, _ptr(E), _ptr(B), _ptr(uu))
+    return uu
+
+
+def deposit_current(P: Params, q: float, w: float, X0, X1, J: np.ndarray | None = None) -> np.ndarray:
+    if J is None:
+        J = np.zeros(_vec(P))
+    X0 = np.ascontiguousarray(X0, dtype=np.float64)
+    X1 = np.ascontiguousarray(X1, dtype=np.float64)
+    lib().orc_deposit_current(ctypes.byref(P), q, w, _ptr(X0), _ptr(X1), _ptr(J))
+    return J
+
+
+# -- whole-array steps -----------------------------------------------------------------------
+def step_species(P: Params, q, m, w, pos: np.ndarray, u: np.ndarray, E, B, J) -> int:
+    """Steps 1-3 for one species, in place on pos/u, accumulating into J."""
+    n = pos.shape[1]
+    return lib().orc_step_species(ctypes.byref(P), q, m, w, n, _ptr(pos), _ptr(u), _ptr(E), _ptr(B), _ptr(J))
+
+
+def deposit_rho(P: Params, q, w, pos: np.ndarray, rho: np.ndarray | None = None) -> np.ndarray:
+    if rho is None:
+        rho = np.zeros(_scal(P))
+    lib().orc_deposit_rho(ctypes.byref(P), q, w, pos.shape[1], _ptr(pos), _ptr(rho))
+    return rho
+
+
+def fd_coeffs(order: int) -> np.ndarray:
+    a = np.zeros(3)
+    lib().orc_fd_coeffs(int(order), _ptr(a))
+    return a
+
+
+def deriv(P: Params, f: np.ndarray, dim: int, up: bool) -> np.ndarray:
+    out = np.zeros_like(f)
+    lib().orc_deriv(ctypes.byref(P), _ptr(f), _ptr(out), int(dim), int(bool(up)))
+    return out
+
+
+def curl_up(P: Params, F):
+    out = np.zeros(_vec(P))
+    lib().orc_curl_up(ctypes.byref(P), _ptr(F), _ptr(out))
+    return out
+
+
+def curl_down(P: Params, F):
+    out = np.zeros(_vec(P))
+    lib().orc_curl_down(ctypes.byref(P), _ptr(F), _ptr(out))
+    return out
+
+
+def div_down(P: Params, F):
+    out = np.zeros(_scal(P))
+    lib().orc_div_down(ctypes.byref(P), _ptr(F), _ptr(out))
+    return out
+
+
+def div_up(P: Params, F):
+    out = np.zeros(_scal(P))
+    lib().orc_div_up(ctypes.byref(P), _ptr(F), _ptr(out))
+    return out
+
+
+def laplacian_B(P: Params, B):
+    out = np.zeros(_vec(P))
+    lib().orc_laplacian_B(ctypes.byref(P), _ptr(B), _ptr(out))
+    return out
+
+
+def field_step(P: Params, E: np.ndarray, B: np.ndarray, J: np.ndarray) -> tuple[int, float]:
+    res = np.zeros(1)
+    it = lib().orc_field_step(ctypes.byref(P), _ptr(E), _ptr(B), _ptr(J), _ptr(res))
+    return it, float(res[0])
+
+
+def current_high_order(P: Params, J: np.ndarray) -> np.ndarray:
+    lib().orc_current_high_order(ctypes.byref(P), _ptr(J))
+    return J
+
+
+def species_moments(P: Params, m, w, u: np.ndarray):
+    kin = np.zeros(1)
+    mom = np.zeros(3)
+    lib().orc_species_moments(ctypes.byref(P), m, w, u.shape[1], _ptr(u), _ptr(kin), _ptr(mom))
+    return float(kin[0]), mom
+
+
+def field_energy(P: Params, E, B):
+    out = np.zeros(3)
+    lib().orc_field_energy(ctypes.byref(P), _ptr(E), _ptr(B), _ptr(out))
+    return out  # (U_E, U_B, U_Ex)
+
+
+# -- one full time step (paper Sec. III order) -------------------------------------------------
+class Run:
+    """Oracle state for a whole run: species + mesh, stepped in the paper's order:
+    particles (gather, push, move, charge-conserving J), high-order current, fields."""
+
+    def __init__(self, P: Params, species, E=None, B=None):
+        self.P = P
+        self.species = [dict(q=float(s["q"]), m=float(s["m"]), w=float(s["w"]),
+                             pos=np.ascontiguousarray(s["pos"], dtype=np.float64).copy(),
+                             u=np.ascontiguousarray(s["u"], dtype=np.float64).copy()) for s in species]
+        self.E = np.zeros(_vec(P)) if E is None else np.ascontiguousarray(E, dtype=np.float64).copy()
+        self.B = np.zeros(_vec(P)) if B is None else np.ascontiguousarray(B, dtype=np.float64).copy()
+        self.J = np.zeros(_vec(P))
+        self.flags = 0
+        self.relax = (0, 0.0)
+
+    def particles_step(self):
+        self.J[:] = 0.0
+        for s in self.species:
+            self.flags |= step_species(self.P, s["q"], s["m"], s["w"], s["pos"], s["u"], self.E, self.B, self.J)
+        current_high_order(self.P, self.J)
+
+    def fields_step(self):
+        self.relax = field_step(self.P, self.E, self.B, self.J)
+
+    def step(self):
+        self.particles_step()
+        self.fields_step()
+
+    def rho(self):
+        r = np.zeros(_scal(self.P))
+        for s in self.species:
+            deposit_rho(self.P, s["q"], s["w"], s["pos"], r)
+        return r + self.P.rho_background
