@@ -1,0 +1,198 @@
+/*
+ * pp.h -- C ABI of libpp, the MI355X (gfx950) particle step of the Photon-Plasma
+ * relativistic particle-in-cell method (Haugboelle, Frederiksen & Nordlund,
+ * arXiv:1211.4575).
+ *
+ * One time step, in the paper's order (Sec. III, numbered list of the five updates;
+ * the sort sits between the particle and field updates):
+ *
+ *     pp_gather_push_deposit(run);   steps 1-3: E^n,B^n,x^n,u^{n-1/2} -> x^{n+1},u^{n+1/2},J^{n+1}
+ *     pp_sort_particles(run, -1);    particles re-ordered by cell
+ *     pp_field_step(run);            steps 4-5: B^{n+1} (implicit), E^{n+1} (explicit)
+ *     pp_diagnostics(run, ...);      optional, FP64 sums and residuals
+ *
+ * Conventions (all calls):
+ *   - Periodic box of n[0] x n[1] x n[2] cells of size d[0..2].  Positions are in
+ *     cell units.  Mesh arrays are FP64 device arrays, x fastest:
+ *     idx = i + n0*(j + n1*k).  A vector field is three consecutive blocks of
+ *     ncell = n0*n1*n2 values (x, y, z components).
+ *   - Yee staggering (Sec. III): rho at (i,j,k); E_x and J_x at (i+1/2,j,k);
+ *     B_x at (i,j+1/2,k+1/2); other components cyclic.  Element [i] of a
+ *     staggered array holds the value at i+1/2 along its staggered axes.
+ *   - Units: mu0 = 1/(eps0 c^2).  u is the proper velocity gamma*v.
+ *   - Memory: every pointer passed in is a device pointer owned by the caller
+ *     (in practice torch tensors).  The library keeps non-owning views and
+ *     never frees caller memory; it owns only internal scratch allocated in
+ *     pp_create and released in pp_destroy.
+ *   - Streams: all work is enqueued asynchronously on the HIP stream given to
+ *     pp_create; a call returns once its kernels are enqueued, except
+ *     pp_diagnostics, which synchronises the stream before it returns.
+ *   - Errors: calls return a pp_status; host-side validation happens before
+ *     anything is enqueued, and a failing call enqueues nothing.  Device-side
+ *     faults of the data (a particle moving a cell or more in a step, non-finite
+ *     state, a particle outside the tile it was sorted into) set bits in a
+ *     device flag word reported by pp_diagnostics; the offending particle is
+ *     left unchanged and deposits nothing.  No call aborts, throws or exits.
+ *   - Threads: one host thread per pp_run handle at a time.
+ */
+#ifndef PP_H
+#define PP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pp_status;
+enum {
+    PP_OK = 0,
+    PP_E_ARG = -1,       /* invalid argument or parameter                         */
+    PP_E_CFL = -2,       /* c dt >= min cell size: a particle could cross a cell  */
+    PP_E_NONFINITE = -3, /* non-finite parameter                                  */
+    PP_E_NOCONV = -4,    /* field relaxation did not reach its tolerance          */
+    PP_E_CAPACITY = -5,  /* too many species / size limits                        */
+    PP_E_HIP = -6,       /* a HIP runtime call failed (see pp_last_hip_error)     */
+    PP_E_STATE = -7      /* call order violated (e.g. push of unsorted particles) */
+};
+
+enum { PP_PREC_FP64 = 0, PP_PREC_FP32_SPLIT = 1 };
+enum { PP_PUSH_VAY = 0, PP_PUSH_BORIS = 1 };
+enum { PP_MAX_SPECIES = 8 };
+
+/* device flag bits reported in pp_diag.flags */
+enum { PP_FLAG_CFL = 1, PP_FLAG_NONFINITE = 2, PP_FLAG_OUT_OF_TILE = 4 };
+
+/* diagnostics selection bits for pp_diagnostics */
+enum {
+    PP_DIAG_MOMENTS = 1,  /* kinetic energy and momentum per species            */
+    PP_DIAG_FIELDS = 2,   /* field energies                                      */
+    PP_DIAG_RHO = 4,      /* deposit rho^{n}; Gauss residual; CC residual        */
+    PP_DIAG_DIVB = 8,     /* max |div B|                                         */
+    PP_DIAG_ALL = 15
+};
+
+/* Run parameters (Sec. II weight order, Sec. III.A pusher, Sec. III.B alpha and
+ * difference order, Sec. IV current scheme).  Host validation rejects:
+ * shape_order not in {2,3} (TSC, PCS), field_order not in {2,4,6}, alpha outside
+ * [1/2, 1), any n < 1, d <= 0, dt <= 0, c <= 0, eps0 <= 0, non-finite values, and
+ * c*dt >= min(d) (PP_E_CFL: the fixed O+2 node current stencil needs every
+ * displacement under one cell). */
+typedef struct pp_params {
+    int32_t n[3];          /* cells per dimension (1 allowed)                        */
+    double d[3];           /* cell sizes                                              */
+    double dt, c, eps0;    /* time step, speed of light, vacuum permittivity          */
+    int32_t shape_order;   /* 2 = TSC, 3 = PCS (cubic)                                */
+    int32_t field_order;   /* 2, 4 or 6 (staggered differences and current order)     */
+    double alpha;          /* implicit de-centering, 1/2 <= alpha < 1                 */
+    int32_t pusher;        /* PP_PUSH_VAY (default) or PP_PUSH_BORIS                  */
+    int32_t precision;     /* PP_PREC_FP64 or PP_PREC_FP32_SPLIT                      */
+    double relax_tol;      /* target error reduction of the B relaxation, e.g. 1e-14 */
+    int32_t relax_max_iter;/* upper bound on relaxation sweeps                        */
+    double rho_background; /* fixed neutralising charge density (0 if none)          */
+} pp_params;
+
+/* Caller-owned FP64 mesh (device pointers, 3*ncell doubles each). */
+typedef struct pp_mesh {
+    double* E;
+    double* B;
+    double* J;
+} pp_mesh;
+
+/* Caller-owned particle storage of one species, structure of arrays (device).
+ *  PP_PREC_FP64:       pos[d] -> double X_d in cell units, [0, n_d);  cell unused.
+ *  PP_PREC_FP32_SPLIT: cell   -> int32 linear index i + n0*(j + n1*k) of the cell
+ *                                 whose centre is nearest (i = floor(X + 1/2) mod n0);
+ *                      pos[d] -> float offset X_d - i in [-1/2, 1/2).
+ *  u[d]: proper velocity (double for FP64, float for FP32_SPLIT).
+ *  id:   optional int64 tag per particle carried along by the sort (NULL = none).
+ *  *_alt: a second buffer of the same types and length (the sort writes there and
+ *         the two buffers swap roles; pp_get_particles returns the current one). */
+typedef struct pp_particles {
+    int64_t n;
+    int32_t* cell;
+    void* pos[3];
+    void* u[3];
+    int64_t* id;
+    int32_t* cell_alt;
+    void* pos_alt[3];
+    void* u_alt[3];
+    int64_t* id_alt;
+} pp_particles;
+
+typedef struct pp_diag {
+    double kinetic[PP_MAX_SPECIES];     /* sum w V m c^2 (gamma - 1), u at n+1/2     */
+    double momentum[PP_MAX_SPECIES][3]; /* sum w V m u                              */
+    double field_E, field_B, field_Ex;  /* sum eps0 E^2 V/2, B^2 V/(2 mu0), x part   */
+    double gauss_max;  /* max |div E - (rho + rho_bg)/eps0|, field-order divergence   */
+    double cc_max;     /* max |rho^{n} - rho^{n-1} + dt div J^{n}| (NaN if no rho^{n-1}) */
+    double rho_ref;    /* max_s |q_s| n_s (mean number density): normalisation       */
+    double divB_max;   /* max |div B| (up-shifted divergence)                         */
+    double relax_resid;/* estimated relative error bound of the last B relaxation    */
+    int32_t relax_iters;
+    int32_t flags;     /* PP_FLAG_* bits accumulated since the last pp_diagnostics    */
+    int64_t step;      /* number of completed pp_field_step calls                    */
+} pp_diag;
+
+typedef struct pp_run pp_run;
+
+/* Create a run: validates params, records the mesh views and the stream
+ * (a hipStream_t; NULL = default stream) and allocates internal scratch of
+ * O(ncell) doubles.  *out receives the handle. */
+pp_status pp_create(const pp_params* params, const pp_mesh* mesh, void* hip_stream, pp_run** out);
+
+/* Register species s (0 <= s < PP_MAX_SPECIES) with charge q, mass m and weight w
+ * (number density contributed per macro-particle, so rho = sum q w W, eq. "rho2")
+ * and its particle storage (Sec. II macro-particles).  Host-side checks: m > 0,
+ * w >= 0, finite q, non-null arrays for the run's precision.  For
+ * PP_PREC_FP32_SPLIT the particles are sorted by cell immediately (enqueued). */
+pp_status pp_init_species(pp_run* run, int32_t s, double q, double m, double w, const pp_particles* parts);
+
+/* Steps 1-3 of Sec. III for every registered species: gather E^n and B^n to each
+ * particle with the B-spline weights of the run's order (eq. "pfields"), push
+ * u^{n-1/2} -> u^{n+1/2} (Vay or Boris, Sec. III.A), move x^{n+1} = x^n +
+ * dt u/gamma, and deposit the charge-conserving current (Sec. IV: Esirkepov's
+ * split with per-particle prefix sums, then for field order 4/6 the line solve of
+ * eqs. "jj6d"/"penta").  J is overwritten with J^{n+1}.  FP32_SPLIT requires the
+ * particles to be sorted since their last push (PP_E_STATE otherwise). */
+pp_status pp_gather_push_deposit(pp_run* run);
+
+/* Steps 4-5 of Sec. III: B^{n+1} from the elliptic equation "EllipticB" (with
+ * the J term's sign derived from "bnplus1"/"enplus1") by Jacobi relaxation from
+ * B^n, then E^{n+1} from "enplus1".  E and B are updated in place. */
+pp_status pp_field_step(pp_run* run);
+
+/* Counting sort of species s (-1 = all) by tile-major cell key (Sec. III: the
+ * particle arrays are sorted by cell between steps 3 and 4).  The order inside a
+ * cell is unspecified.  The current and alternate buffers swap roles. */
+pp_status pp_sort_particles(pp_run* run, int32_t s);
+
+/* FP64 diagnostics selected by `what` (PP_DIAG_* bits) written to *out (host
+ * memory).  Also reports and clears the device flag word.  Synchronises the
+ * run's stream. */
+pp_status pp_diagnostics(pp_run* run, uint32_t what, pp_diag* out);
+
+/* Current buffer assignment of species s after sorts (host struct). */
+pp_status pp_get_particles(pp_run* run, int32_t s, pp_particles* out);
+
+/* Time of the gather/push/deposit kernels: when enabled, HIP events bracket every
+ * launch of the main particle kernel on the run's stream; pp_timing_read returns
+ * the accumulated milliseconds and the number of launches timed, then resets. */
+pp_status pp_timing_enable(pp_run* run, int32_t enable);
+pp_status pp_timing_read(pp_run* run, double* ms_total, int64_t* launches);
+
+/* Release internal scratch.  Caller memory is untouched. */
+pp_status pp_destroy(pp_run* run);
+
+/* Static description of a status code. */
+const char* pp_status_str(pp_status st);
+
+/* Last HIP error string recorded by the library in this process ("" if none). */
+const char* pp_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PP_H */

@@ -1,0 +1,106 @@
+// Internal declarations of libpp (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/pp.h"
+
+namespace pp {
+
+// Tile-major cell keys: the box is cut into tiles of TILE_CELLS cells (tx*ty*tz = 64,
+// one cell per lane of a wavefront); key = tile * 64 + local cell.  Tiles at the upper
+// edge may be partial (cells outside the box never receive particles).
+constexpr int TILE_CELLS = 64;
+// LDS halo of the field tile (nodes below / above the tile) and of the current tile.
+constexpr int FLD_LO = 2, FLD_HI = 2;
+constexpr int CUR_LO = 3, CUR_HI = 3;
+
+struct Geom {
+    int n[3];       // cells
+    int t[3];       // tile dims
+    int nt[3];      // tiles per dim
+    int64_t ncell;  // n0*n1*n2
+    int64_t ntiles;
+    int64_t nbins;  // ntiles * 64
+};
+
+struct Species {
+    bool active = false;
+    double q = 0, m = 1, w = 0;
+    int64_t n = 0;
+    pp_particles cur{};  // buffers read by the next push
+    bool sorted = false;
+    int32_t* offsets = nullptr;  // nbins + 1 bin starts (device), valid when sorted
+};
+
+// Line-solve stencil of one axis: out[i] = sum_j coef[j] * in[(i + off + j) mod n].
+struct LineStencil {
+    double* coef = nullptr;  // device
+    int len = 0;
+    int off = 0;
+};
+
+}  // namespace pp
+
+struct pp_run {
+    pp_params p{};
+    pp_mesh mesh{};
+    hipStream_t stream = nullptr;
+    pp::Geom g{};
+    pp::Species sp[PP_MAX_SPECIES];
+
+    double* J2 = nullptr;      // second-order current (field order > 2)
+    double* Bn = nullptr;      // copy of B^n during the field step
+    double* Bw = nullptr;      // relaxation ping-pong partner
+    double* R = nullptr;       // right-hand side of the elliptic equation
+    double* rho = nullptr;     // charge density (diagnostics)
+    double* rho_prev = nullptr;
+    int64_t rho_prev_step = -1;
+    int32_t* sort_count = nullptr;   // nbins + 1
+    int32_t* sort_cursor = nullptr;  // nbins
+    int32_t* scan_tmp = nullptr;     // block sums of the scan
+    int32_t* flags = nullptr;        // device error flags
+    double* dacc = nullptr;          // device accumulators for diagnostics
+    pp::LineStencil line[3];
+
+    // field-step constants
+    double lap[3][16] = {};  // Laplacian stencil per axis, offsets -R..R (1/d^2 folded)
+    int lap_r = 0;
+    double diagA = 1.0;      // diagonal of (1 - alpha^2 c^2 dt^2 lap) on this grid
+    double jac_rho = 0.0;    // spectral radius of the Jacobi iteration
+    int jac_sweeps = 0;
+    double jac_bound = 0.0;  // jac_rho^sweeps
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timing = false;
+    bool t_pending = false;
+    double t_ms = 0.0;
+    int64_t t_launches = 0;
+
+    int64_t step = 0;
+};
+
+namespace pp {
+
+void set_hip_error(hipError_t e, const char* where);
+inline bool ok(hipError_t e, const char* where) {
+    if (e != hipSuccess) {
+        set_hip_error(e, where);
+        return false;
+    }
+    return true;
+}
+
+// kernels launchers (defined in the kernel translation units)
+hipError_t launch_gpd64(pp_run* r, int s, double* J);
+hipError_t launch_gpd32(pp_run* r, double* J);
+hipError_t launch_line_solve(pp_run* r, const double* J2, double* J);
+hipError_t launch_field_step(pp_run* r);
+hipError_t launch_sort(pp_run* r, int s);
+hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+
+}  // namespace pp

@@ -1,0 +1,217 @@
+"""GPU parity: libpp (through its C ABI) against the FP64 CPU oracle, from identical states.
+
+FP64 form: one step, max-norm error relative to the oracle's max <= 1e-12 for u, J, E, B and
+|dX| <= 1e-12 cell.  Split FP32 form: one step from the FP32-rounded state, fields within 1e-5
+(L2, relative to the oracle's change of the field), normalised Gauss residual <= 1e-6,
+offsets within 1e-6 cell, u within 1e-5 relative.  Grids span several tiles with ragged
+edges and single-cell axes."""
+import sys
+
+import numpy as np
+import pytest
+
+from _state import periodic_diff, random_state, rel_inf, rel_l2
+from paper_1211_4575_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ppm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1211_4575_amd import pp
+    pp.lib()
+    return pp
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _orc_run(orc, P, species, E, B):
+    return orc.Run(P, [dict(q=s["q"], m=s["m"], w=s["w"], pos=s["pos"], u=s["u"]) for s in species], E=E, B=B)
+
+
+def _by_id(parts):
+    order = np.argsort(parts["id"])
+    out = {k: (v[..., order] if k != "id" else v[order]) for k, v in parts.items()}
+    return out
+
+
+FP64_CASES = [
+    # n, ppc, shape order, field order, pusher, cell size
+    ((8, 8, 8), 4, 2, 2, 0, (1.0, 1.0, 1.0)),
+    ((12, 8, 6), 3, 3, 6, 0, (1.0, 0.8, 1.2)),
+    ((10, 6, 5), 3, 3, 4, 1, (1.0, 1.0, 1.0)),
+    ((20, 6, 1), 4, 3, 6, 0, (1.0, 1.0, 1.0)),
+    ((5, 3, 2), 6, 2, 6, 1, (0.7, 1.0, 0.9)),
+]
+
+
+@pytest.mark.parametrize("ci", range(len(FP64_CASES)), ids=[str(c[:4]) for c in FP64_CASES])
+def test_fp64_one_step_matches_oracle(ppm, orc, ci):
+    case = FP64_CASES[ci]
+    n, ppc, O, fo, pusher, d = case
+    _say("fp64 one step", case)
+    species, E, B = random_state(orc, n, ppc, seed=100 + ci, d=d)
+    kw = dict(n=n, d=d, dt=0.35 * min(d), shape_order=O, field_order=fo, pusher=pusher, relax_tol=1e-14,
+              relax_max_iter=200)
+    P = orc.make_params(**kw)
+    ref = _orc_run(orc, P, species, E, B)
+    ref.step()
+    run = ppm.Run(ppm.make_params(precision=ppm.PP_PREC_FP64, **kw), species, E=E, B=B)
+    run.step()
+    Eg, Bg, Jg = run.fields()
+    assert rel_inf(Jg, ref.J) < 1e-12
+    assert rel_inf(Bg - B, ref.B - B) < 1e-11
+    assert rel_inf(Eg - E, ref.E - E) < 1e-11
+    assert rel_inf(Eg, ref.E) < 1e-12 and rel_inf(Bg, ref.B) < 1e-12
+    for s, sp in enumerate(ref.species):
+        g = _by_id(run.particles(s))
+        assert np.max(np.abs(periodic_diff(g["pos"], sp["pos"], n))) < 1e-12
+        assert rel_inf(g["u"], sp["u"]) < 1e-12
+    dg = run.diagnostics()
+    assert dg.flags == 0
+    run.close()
+
+
+def _split_species(species, n):
+    out = []
+    for s in species:
+        cell, off = I.to_split(s["pos"], n)
+        u32 = s["u"].astype(np.float32)
+        out.append(dict(q=s["q"], m=s["m"], w=s["w"], cell=cell, off=off, u=u32,
+                        pos=I.from_split(cell, off, n), u64=u32.astype(np.float64)))
+    return out
+
+
+FP32_CASES = [
+    ((8, 8, 8), 4, 2, 2),
+    ((12, 8, 6), 3, 3, 6),
+    ((20, 6, 1), 4, 3, 6),
+    ((9, 7, 5), 3, 3, 4),
+    ((64, 1, 1), 16, 3, 6),
+]
+
+
+@pytest.mark.parametrize("ci", range(len(FP32_CASES)), ids=[str(c) for c in FP32_CASES])
+def test_fp32_split_one_step_matches_oracle(ppm, orc, ci):
+    case = FP32_CASES[ci]
+    n, ppc, O, fo = case
+    _say("fp32 one step", case)
+    species, E, B = random_state(orc, n, ppc, seed=200 + ci, uth=0.2)
+    sp32 = _split_species(species, n)
+    kw = dict(n=n, dt=0.4, shape_order=O, field_order=fo, relax_tol=1e-14, relax_max_iter=200)
+    P = orc.make_params(**kw)
+    ref = _orc_run(orc, P, [dict(s, u=s["u64"]) for s in sp32], E, B)
+    ref.step()
+    run = ppm.Run(ppm.make_params(precision=ppm.PP_PREC_FP32_SPLIT, **kw), sp32, E=E, B=B)
+    run.step()
+    Eg, Bg, Jg = run.fields()
+    assert rel_l2(Jg, ref.J) < 1e-5
+    assert rel_l2(Eg - E, ref.E - E) < 1e-5
+    assert rel_l2(Bg - B, ref.B - B) < 1e-5
+    for s, sp in enumerate(ref.species):
+        g = _by_id(run.particles(s))
+        X = I.from_split(g["cell"], g["pos"], n)
+        assert np.max(np.abs(periodic_diff(X, sp["pos"], n))) < 1e-6
+        assert rel_inf(g["u"].astype(np.float64), sp["u"]) < 1e-5
+        assert np.all(g["pos"] >= -0.5) and np.all(g["pos"] < 0.5)
+    dg = run.diagnostics()
+    assert dg.flags == 0
+    run.close()
+
+
+def test_fp32_gauss_residual_one_step(ppm, orc):
+    # pair-loaded plasma (rho = 0) and a divergence-free E: Gauss holds at t = 0; after a step
+    # the normalised residual stays below 1e-6
+    n = (16, 12, 8)
+    _say("fp32 gauss", n)
+    species, E, B = random_state(orc, n, 8, seed=3, uth=0.2)
+    P = orc.make_params(n=n, field_order=6)
+    E = orc.curl_down(P, E)  # divergence free: the 6th-order down divergence of a down curl vanishes
+    sp32 = _split_species(species, n)
+    for s in sp32[1:]:  # keep the pair exactly co-located after rounding
+        s["cell"], s["off"] = sp32[0]["cell"], sp32[0]["off"]
+    run = ppm.Run(ppm.make_params(n=n, shape_order=3, field_order=6, precision=ppm.PP_PREC_FP32_SPLIT), sp32, E=E,
+                  B=B)
+    d0 = run.diagnostics(ppm.PP_DIAG_RHO)
+    assert d0.gauss_max / d0.rho_ref < 1e-12
+    run.step()
+    d1 = run.diagnostics(ppm.PP_DIAG_ALL)
+    assert d1.gauss_max / d1.rho_ref < 1e-6
+    assert d1.cc_max / d1.rho_ref < 1e-6
+    run.close()
+
+
+def test_fp64_whole_run_plain_heating(ppm, orc):
+    # the plain-method workload at full size (16^3, 8 particles per cell per species, TSC,
+    # second-order fields), 20 steps: energies and the final state track the oracle
+    wl = I.plain_heating()
+    _say("fp64 plain heating 20 steps")
+    P = orc.make_params(**wl.params())
+    species = [dict(q=s.q, m=s.m, w=s.w, pos=s.pos, u=s.u) for s in wl.species]
+    ref = _orc_run(orc, P, species, None, None)
+    run = ppm.Run(ppm.make_params(precision=ppm.PP_PREC_FP64, **wl.params()), species)
+    for st in range(20):
+        ref.step()
+        run.step()
+        dg = run.diagnostics()
+        UE, UB, _ = orc.field_energy(P, ref.E, ref.B)
+        assert abs(dg.field_E - UE) <= 1e-9 * max(UE, 1e-30)
+        assert abs(dg.field_B - UB) <= 1e-9 * max(UB, 1e-30)
+        assert dg.gauss_max < 1e-12 and (st == 0 or dg.cc_max < 1e-12)
+        for s, sp in enumerate(ref.species):
+            K, mom = orc.species_moments(P, sp["m"], sp["w"], sp["u"])
+            assert abs(dg.kinetic[s] - K) <= 1e-11 * K
+    Eg, Bg, _ = run.fields()
+    assert rel_inf(Eg, ref.E) < 1e-9 and rel_inf(Bg, ref.B) < 1e-9
+    for s, sp in enumerate(ref.species):
+        g = _by_id(run.particles(s))
+        assert np.max(np.abs(periodic_diff(g["pos"], sp["pos"], wl.n))) < 1e-10
+    run.close()
+
+
+def test_sort_is_a_permutation_by_cell(ppm, orc):
+    n = (12, 8, 4)
+    _say("sort", n)
+    species, E, B = random_state(orc, n, 5, seed=11)
+    sp32 = _split_species(species, n)
+    run = ppm.Run(ppm.make_params(n=n, shape_order=3, field_order=2, precision=ppm.PP_PREC_FP32_SPLIT), sp32, E=E,
+                  B=B)
+    run.step()
+    for s in range(2):
+        g = run.particles(s)
+        assert np.array_equal(np.sort(g["id"]), np.arange(len(g["id"])))
+        cells = g["cell"]
+        # tile-major key must be non-decreasing along the array
+        # every cell's particles are contiguous (the tile-major key order is internal)
+        change = np.flatnonzero(np.diff(cells) != 0)
+        assert len(change) + 1 == len(np.unique(cells))
+    run.close()
+
+
+def test_host_validation_rejects_bad_params(ppm):
+    import torch
+    mesh_t = torch.zeros((3, 4, 4, 4), dtype=torch.float64, device="cuda")
+    mesh = ppm.pp_mesh(mesh_t.data_ptr(), mesh_t.data_ptr(), mesh_t.data_ptr())
+    bad = [dict(dt=1.0), dict(shape_order=1), dict(field_order=3), dict(alpha=0.4), dict(alpha=1.0),
+           dict(d=(1.0, 0.0, 1.0)), dict(dt=float("nan"))]
+    codes = [ppm.PP_E_CFL, ppm.PP_E_ARG, ppm.PP_E_ARG, ppm.PP_E_ARG, ppm.PP_E_ARG, ppm.PP_E_ARG, ppm.PP_E_NONFINITE]
+    for kw, code in zip(bad, codes):
+        p = ppm.make_params((4, 4, 4), **kw)
+        with pytest.raises(ppm.PPError) as ei:
+            ppm.pp_create(p, mesh, 0)
+        assert ei.value.status == code, kw
+
+
+def test_fp32_push_requires_sort(ppm, orc):
+    n = (8, 8, 4)
+    species, E, B = random_state(orc, n, 2, seed=5)
+    run = ppm.Run(ppm.make_params(n=n, precision=ppm.PP_PREC_FP32_SPLIT), _split_species(species, n))
+    run.gather_push_deposit()
+    with pytest.raises(ppm.PPError) as ei:
+        run.gather_push_deposit()
+    assert ei.value.status == ppm.PP_E_STATE
+    run.close()
