@@ -1,0 +1,211 @@
+"""Benchmark of the particle step on one MI355X.
+
+Workload (default): relativistic pair plasma, 256^3 periodic cells, 32 particles per cell per
+species (1,073,741,824 particles), Maxwell-Juettner momenta at kT = m c^2, cubic weights,
+6th-order fields, dt = 0.4, generated in device memory.  A step is one pass of the whole
+particle step: gather/push/deposit (+ high-order line solve), sort by cell, field step.
+
+Prints one JSON line: value = particle updates/s of the split-precision FP32 path over the
+timed steps (inputs resident in HBM before timing starts); the FP64 plain form is timed on
+the same workload for comparison; ``roofline`` describes the dominant kernel (the tiled
+gather/push/deposit kernel) with its launch time measured by HIP events on its own stream;
+``cpu_baseline`` times the FP64 CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+SEED = 12114575
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_pair_mj_run(pp, ind, torch, n, ppc, theta, split, with_id=False):
+    """Build a pp.Run for the pair-plasma workload with particles generated on the device.
+    Returns the run and the number of particles per species."""
+    npart = n[0] * n[1] * n[2] * ppc
+    dev = torch.device("cuda:0")
+    rt = torch.float32 if split else torch.float64
+    cells = [torch.empty(npart, dtype=torch.int32, device=dev) for _ in range(2)] if split else None
+    offs = [torch.empty((3, npart), dtype=rt, device=dev) for _ in range(2)]
+    us = [torch.empty((3, npart), dtype=rt, device=dev) for _ in range(2)]
+    st = torch.cuda.current_stream().cuda_stream
+    chunk = 1 << 26
+    for start in range(0, npart, chunk):
+        cnt = min(chunk, npart - start)
+        ind.pair_maxwell_juttner(SEED, n, start, cnt, theta, split,
+                                 [c[start:] for c in cells] if split else None,
+                                 [[o[d, start:] for d in range(3)] for o in offs],
+                                 [[u[d, start:] for d in range(3)] for u in us], st)
+    torch.cuda.synchronize()
+    params = pp.make_params(n, shape_order=3, field_order=6, dt=0.4, alpha=0.55,
+                            precision=pp.PP_PREC_FP32_SPLIT if split else pp.PP_PREC_FP64,
+                            relax_tol=1e-8 if split else 1e-14, relax_max_iter=100)
+    species = []
+    for s, q in enumerate((-1.0, 1.0)):
+        sp = dict(q=q, m=1.0, w=1.0 / ppc, u=us[s])
+        if split:
+            sp.update(cell=cells[s], off=offs[s])
+        else:
+            sp.update(pos=offs[s])
+        species.append(sp)
+    run = pp.Run(params, species, with_id=with_id)
+    del cells, offs, us
+    return run, npart
+
+
+def time_steps(run, torch, steps, warmup):
+    for _ in range(warmup):
+        run.step()
+    torch.cuda.synchronize()
+    run.timing(True)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        run.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_gpd, launches = run.timing_read()
+    run.timing(False)
+    return (t1 - t0), ms_gpd / max(launches, 1)
+
+
+def cpu_baseline(n_sample=(16, 16, 16), ppc=32, steps=4):
+    """FP64 CPU oracle (single thread, as it stands) on a bounded sample of the workload:
+    the same particles-per-cell, momenta, shapes and field order on a 16^3 box."""
+    from oracle import orc
+    from paper_1211_4575_amd import inputs as I
+    orc.build()
+    wl = I.pair_maxwell_juttner(n=n_sample, ppc=ppc, theta=1.0)
+    P = orc.make_params(**wl.params())
+    run = orc.Run(P, [dict(q=s.q, m=s.m, w=s.w, pos=s.pos, u=s.u) for s in wl.species])
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run.step()
+    dt = time.perf_counter() - t0
+    return dict(value=wl.n_particles * steps / dt, unit="particle updates/s", cores=1, kind="oracle",
+                sample=f"{n_sample[0]}x{n_sample[1]}x{n_sample[2]} box of the same workload "
+                       f"({wl.n_particles} particles), {steps} full steps, {dt:.1f} s")
+
+
+def flops_per_update(O=3):
+    """Algorithmic FP32 operations of one particle update in the tiled kernel's formulation
+    (FMA = 2): weights, factored gather, Vay push, move, Esirkepov current."""
+    n1 = O + 1
+    n2 = O + 2
+    weights = 3 * 2 * (4 * n1) + 3 * 2 * (4 * n1)  # gather sets (2/axis) + old/new current sets (2/axis)
+    gather = 6 * 2 * (n1 ** 3 + n1 ** 2 + n1)
+    push = 80
+    move = 3 * 4
+    esirkepov = 3 * (3 * n2 + n2 * n2 * 7 + n2 * n2 * n1 * 3)  # dS, F(b,e), prefix + scale
+    return weights + gather + push + move + esirkepov
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--grid", type=int, default=256)
+    ap.add_argument("--ppc", type=int, default=32)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
+              f"of this path is described in DESIGN.md and not built.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1211_4575_amd import inputs_device as ind
+    from paper_1211_4575_amd import pp
+
+    n = (args.grid, args.grid, args.grid)
+    log(f"[bench] FP32 split: generating {n} x {args.ppc} ppc x 2 species on the device")
+    run, npart = make_pair_mj_run(pp, ind, torch, n, args.ppc, 1.0, split=True)
+    npart *= 2  # electrons and positrons
+    log(f"[bench] FP32 split: {npart} particles; warmup {args.warmup}, timing {args.steps} steps")
+    wall, gpd_ms = time_steps(run, torch, args.steps, args.warmup)
+    ms_step = 1e3 * wall / args.steps
+    value = npart * args.steps / wall
+    gpd_rate = npart / (gpd_ms * 1e-3)
+    log(f"[bench] FP32: {ms_step:.2f} ms/step, gpd kernel {gpd_ms:.2f} ms -> {gpd_rate:.3e} updates/s")
+    # per-step charge conservation and Gauss residual (FP64), outside the timed region
+    run.diagnostics(pp.PP_DIAG_RHO)
+    run.step()
+    dg = run.diagnostics(pp.PP_DIAG_ALL)
+    diag32 = dict(cc_rel=dg.cc_max / dg.rho_ref, gauss_rel=dg.gauss_max / dg.rho_ref, flags=dg.flags,
+                  relax_sweeps=dg.relax_iters, relax_bound=dg.relax_resid)
+    log(f"[bench] FP32 diagnostics {diag32}")
+    run.close()
+    del run
+    torch.cuda.empty_cache()
+
+    fp64 = None
+    if not args.no_fp64:
+        log(f"[bench] FP64 plain: generating")
+        run, _ = make_pair_mj_run(pp, ind, torch, n, args.ppc, 1.0, split=False)
+        log(f"[bench] FP64 plain: warmup 1, timing {args.fp64_steps} steps")
+        wall64, gpd64_ms = time_steps(run, torch, args.fp64_steps, 1)
+        fp64 = dict(value=npart * args.fp64_steps / wall64, ms_per_step=1e3 * wall64 / args.fp64_steps,
+                    gpd_updates_per_s=npart / (gpd64_ms * 1e-3), gpd_ms=gpd64_ms)
+        log(f"[bench] FP64 plain {fp64}")
+        run.close()
+        del run
+        torch.cuda.empty_cache()
+
+    bytes_per_update = 56.0  # split state read + written: int32 cell + 3 FP32 offsets + 3 FP32 u
+    achieved_gbs = npart * bytes_per_update / (gpd_ms * 1e-3) / 1e9
+    fl = flops_per_update(3)
+    achieved_tf = npart * fl / (gpd_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved_tf / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "k_gpd32<3>", "flop_per_update": fl, "hbm_gbs_algorithmic": round(achieved_gbs, 1),
+                "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "gpd_ms": round(gpd_ms, 3)}
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU baseline (oracle, bounded sample)")
+        cpu = cpu_baseline()
+        log(f"[bench] CPU {cpu}")
+
+    out = {
+        "metric": "particle updates/s (gather+push+deposit) FP32 vs FP64; ensemble p50/p99",
+        "value": value,
+        "unit": "particle updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"pair plasma {n[0]}x{n[1]}x{n[2]}, {args.ppc} ppc/species, Maxwell-Juttner kT=mc^2, "
+                               f"cubic weights, 6th-order fields, FP32 split positions",
+                   "particles": npart, "step": "gather/push/deposit + line solve + sort + field step",
+                   "gpd_updates_per_s": gpd_rate, "fp64_plain": fp64,
+                   "fp32_over_fp64": (value / fp64["value"]) if fp64 else None, "diagnostics": diag32},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

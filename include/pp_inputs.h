@@ -1,0 +1,44 @@
+/*
+ * pp_inputs.h -- on-device seeded particle loaders (libpp_inputs.so).
+ *
+ * Input generation only: these calls draw positions and momenta for benchmark-size
+ * workloads directly in device memory; they hold none of the particle-in-cell method's
+ * arithmetic.  They reproduce, particle by particle, the host generators of
+ * paper_1211_4575_amd/inputs.py: Philox-4x32-10 (Salmon et al., SC'11) keyed by the
+ * seed, counter (particle index, draw block, stream); uniforms from 53 random bits;
+ * Maxwell-Juettner proper speeds by Sobol's rejection method; isotropic directions.
+ * Transcendental functions are the device's, so values can differ from the host
+ * generator in the last bits (and, rarely, in a rejection decision).
+ *
+ * Memory: all pointers are caller-owned device arrays; the calls only enqueue kernels on
+ * the given HIP stream.  Returns 0 on success, -1 on invalid arguments, -6 on a HIP error.
+ */
+#ifndef PP_INPUTS_H
+#define PP_INPUTS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Raw Philox-4x32-10 blocks: for i in [0, count): out[4i..4i+3] = philox(ctr, key) with
+ * ctr = (i + ctr0, 0, block, stream).  Used to check the device generator. */
+int ppi_philox_blocks(uint64_t seed, uint32_t block, uint32_t stream, int64_t ctr0, int64_t count, uint32_t* out,
+                      void* hip_stream);
+
+/* Pair-loaded relativistic pair plasma (electron = species 0, positron = species 1 at the
+ * same positions), Maxwell-Juettner momenta at kT/mc^2 = theta, for particle indices
+ * [start, start + count) of a box of n[0] x n[1] x n[2] cells with ppc particles per cell per
+ * species.  split = 1: cell (int32, x-fastest index of the nearest cell centre), off[3]
+ * (float offsets in [-1/2,1/2)), u[3] (float).  split = 0: off[3] are double positions in
+ * cell units and u[3] double; cell is unused.  Arrays of species s are cell[s], off[s][d],
+ * u[s][d] (device pointers to element 0 of the slice). */
+int ppi_pair_maxwell_juttner(uint64_t seed, const int32_t n[3], int64_t start, int64_t count, double theta,
+                             int32_t split, int32_t* const cell[2], void* const off[2][3], void* const u[2][3],
+                             void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

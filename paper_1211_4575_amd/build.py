@@ -14,6 +14,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpp.so")
+SRC_INPUTS = os.path.join(HERE, "csrc_inputs")
+OUT_INPUTS = os.path.join(HERE, "libpp_inputs.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("PP_OFFLOAD_ARCH", "gfx950")
 
@@ -38,19 +40,26 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None) -> str:
-    """Compile every HIP source and link libpp.so; returns its path.  Always rebuilds."""
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(SRC, "*.hip")))
-    jobs = jobs or min(8, len(srcs))
-    with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = OUT + ".tmp"
+def _link(objs, out):
+    tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
+
+
+def build(jobs: int | None = None) -> str:
+    """Compile every HIP source and link libpp.so (the method) and libpp_inputs.so (the
+    on-device input generator); returns the path of libpp.so.  Always rebuilds."""
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(SRC, "*.hip")))
+    srcs_in = sorted(glob.glob(os.path.join(SRC_INPUTS, "*.hip")))
+    jobs = jobs or min(8, len(srcs) + len(srcs_in))
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(_compile, srcs + srcs_in))
+    _link(objs[: len(srcs)], OUT)
+    _link(objs[len(srcs):], OUT_INPUTS)
     return OUT
 
 

@@ -90,9 +90,14 @@ static void release(pp_run* r) {
     f(r->rho);
     f(r->rho_prev);
     f(r->sort_cursor);
+    f(r->sort_count);
     f(r->scan_tmp);
     f(r->flags);
     f(r->dacc);
+    f(r->round_T);
+    f(r->round_M);
+    f(r->tile_ovf);
+    f(r->Jq);
     for (int d = 0; d < 3; ++d) f(r->line[d].coef);
     for (int s = 0; s < PP_MAX_SPECIES; ++s) f(r->sp[s].offsets);
     if (r->ev0) (void)hipEventDestroy(r->ev0);
@@ -159,8 +164,12 @@ pp_status pp_create(const pp_params* params, const pp_mesh* mesh, void* hip_stre
     if (params->field_order > 2) okk = okk && dmalloc(&r->J2, n3);
     okk = okk && dmalloc(&r->Bn, n3) && dmalloc(&r->Bw, n3) && dmalloc(&r->R, n3);
     okk = okk && dmalloc(&r->rho, (size_t)g.ncell) && dmalloc(&r->rho_prev, (size_t)g.ncell);
-    okk = okk && dmalloc(&r->sort_cursor, (size_t)g.nbins) && dmalloc(&r->scan_tmp, (size_t)scan_tmp_size(g.nbins + 1));
+    okk = okk && dmalloc(&r->sort_cursor, (size_t)g.nbins) && dmalloc(&r->sort_count, (size_t)g.nbins) &&
+          dmalloc(&r->scan_tmp, (size_t)scan_tmp_size(g.nbins + 1));
     okk = okk && dmalloc(&r->flags, 1) && dmalloc(&r->dacc, (size_t)diag_acc_count() + 8);
+    if (params->precision == PP_PREC_FP32_SPLIT) {
+        okk = okk && dmalloc(&r->Jq, n3) && dmalloc(&r->tile_ovf, (size_t)g.ntiles);
+    }
     if (okk && params->field_order > 2) {
         for (int d = 0; d < 3; ++d) {
             double host[1024 + 128];
@@ -221,6 +230,24 @@ pp_status pp_init_species(pp_run* r, int32_t s, double q, double m, double w, co
     }
     Species& S = r->sp[s];
     if (!S.offsets && !dmalloc(&S.offsets, (size_t)r->g.nbins + 1)) return PP_E_HIP;
+    if (split) {
+        // rounds held in the per-tile tables: twice the mean occupancy plus a margin (ranks
+        // beyond it still sort correctly, into a per-tile overflow segment)
+        int64_t mean = (parts->n + r->g.ncell - 1) / r->g.ncell;
+        int64_t want = 2 * mean + 64;
+        if (want > 4096) want = 4096;
+        if (want > r->rcap) {
+            if (r->round_T) (void)hipFree(r->round_T);
+            if (r->round_M) (void)hipFree(r->round_M);
+            r->round_T = nullptr;
+            r->round_M = nullptr;
+            r->rcap = 0;
+            if (!dmalloc(&r->round_T, (size_t)r->g.ntiles * (size_t)(want + 1)) ||
+                !dmalloc(&r->round_M, (size_t)r->g.ntiles * (size_t)want))
+                return PP_E_HIP;
+            r->rcap = (int)want;
+        }
+    }
     S.active = true;
     S.q = q;
     S.m = m;
@@ -246,8 +273,11 @@ pp_status pp_gather_push_deposit(pp_run* r) {
         if (split && r->sp[s].active && !r->sp[s].sorted) return PP_E_STATE;
     if (flush_timing(r) != PP_OK) return PP_E_HIP;
     double* target = r->p.field_order > 2 ? r->J2 : r->mesh.J;
-    hipError_t e = launch_fill(target, 3 * r->g.ncell, 0.0, r->stream);
-    if (!ok(e, "fill")) return PP_E_HIP;
+    hipError_t e = hipSuccess;
+    if (!split) {  // the split kernel overwrites its target
+        e = launch_fill(target, 3 * r->g.ncell, 0.0, r->stream);
+        if (!ok(e, "fill")) return PP_E_HIP;
+    }
     if (r->timing && !ok(hipEventRecord(r->ev0, r->stream), "hipEventRecord")) return PP_E_HIP;
     if (split) {
         e = launch_gpd32(r, target);

@@ -1,25 +1,28 @@
 // Split-precision form of steps 1-3 (Sec. III), tiled.  Particles: int32 cell index +
 // FP32 offset from the cell centre in [-1/2, 1/2) + FP32 proper velocity (the paper's
-// integer cell + fraction storage, Sec. V.B), sorted by tile-major cell key.
+// integer cell + fraction storage, Sec. V.B), stored per tile in round-major order (see
+// pp_sort.hip): 64 consecutive particles sit in 64 different cells of the tile.
 //
 // One workgroup (4 wavefronts) per tile of 64 cells:
 //   1. stage E and B of the tile plus a 2-node halo from the FP64 mesh into LDS as FP32;
-//   2. every lane owns one cell of the tile and walks that cell's particles; the four
-//      wavefronts take every fourth particle of the cell.  A wavefront's 64 lanes therefore
-//      work in 64 different cells, so the LDS atomics of one instruction never collide on
-//      an address.  Per particle: gather (LDS) -> push (registers) -> move and
-//      renormalise the split position -> Esirkepov current (registers) -> FP32 LDS
-//      atomics into the tile's current block (3-node halo);
-//   3. flush the current block to the FP64 mesh with global FP64 atomics (halo nodes
-//      overlap neighbouring tiles), skipping untouched nodes.
-// All species are processed by the same workgroup, so the fields are staged once.
+//   2. each wavefront takes 64 consecutive particles at a time (coalesced loads and
+//      stores): gather (LDS) -> push (registers) -> move and renormalise the split
+//      position -> Esirkepov current (registers) -> LDS accumulation of the tile's current
+//      block (3-node halo);
+//   3. flush the current block to the global accumulator with 64-bit integer atomics.
+// Current accumulation is exact 64-bit fixed point: each FP32 contribution c is rounded to
+// an integer multiple of 2^-e (one FP64 fused multiply-add with the 1.5*2^52 rounding
+// constant) and added with integer atomics, which run at full LDS rate where FP32 LDS
+// atomics do not.  The scale 2^e is chosen so that no sum can overflow; the result is the
+// exact sum of the rounded contributions, independent of summation order (bitwise
+// deterministic).  All species are processed by the same workgroup.
 #include "pp_device.hpp"
 #include "pp_internal.hpp"
 
 namespace pp {
 
 struct Sp32 {
-    const int32_t* off;  // bin starts
+    const int32_t* start;  // tile starts (ntiles + 1)
     int32_t* cell;
     float* pos[3];
     float* u[3];
@@ -33,10 +36,8 @@ struct Gpd32Args {
     int nt[3];
     int64_t ntiles;
     int64_t nc;
-    int fe[3];     // field LDS extents (1 on axes with a single cell)
-    int ce[3];     // current LDS extents
-    int flo[3];    // field halo below (0 on single-cell axes)
-    int clo[3];    // current halo below
+    int fe[3], ce[3];  // LDS extents (runtime-shape kernel)
+    int flo[3], clo[3];
     float dt;
     float inv_d[3];
     float ic;
@@ -45,18 +46,69 @@ struct Gpd32Args {
     Sp32 sp[PP_MAX_SPECIES];
     const double* E;
     const double* B;
-    double* J;
+    unsigned long long* Jq;  // fixed-point current accumulator (3 * nc)
+    double qscale;           // 2^e
     int32_t* flags;
-    int per_xcd;   // tiles per XCD slot group
+    int per_xcd;
 };
 
 constexpr int GPD32_BS = 256;
+constexpr double ROUND_MAGIC = 6755399441055744.0;  // 1.5 * 2^52
+constexpr long long ROUND_MAGIC_BITS = 0x4338000000000000LL;
+
+// LDS layout of a tile: compile-time for the common shapes, runtime otherwise.  A
+// single-cell axis is collapsed (extent 1, stride 0): every node offset maps to plane 0.
+template <int TX, int TY, int TZ, bool CZ>
+struct TileCT {
+    static constexpr int tx = TX, ty = TY, tz = TZ;
+    static constexpr int flox = FLD_LO, floy = FLD_LO, floz = CZ ? 0 : FLD_LO;
+    static constexpr int clox = CUR_LO, cloy = CUR_LO, cloz = CZ ? 0 : CUR_LO;
+    static constexpr int fex = TX + 4, fey = TY + 4, fez = CZ ? 1 : TZ + 4;
+    static constexpr int cex = TX + 6, cey = TY + 6, cez = CZ ? 1 : TZ + 6;
+    static constexpr int fsx = 1, fsy = fex, fsz = CZ ? 0 : fex * fey;
+    static constexpr int csx = 1, csy = cex, csz = CZ ? 0 : cex * cey;
+    static constexpr int fvol = fex * fey * fez, cvol = cex * cey * cez;
+    __device__ TileCT(const Gpd32Args&) {}
+};
+
+struct TileRT {
+    int tx, ty, tz;
+    int flox, floy, floz, clox, cloy, cloz;
+    int fex, fey, fez, cex, cey, cez;
+    int fsx, fsy, fsz, csx, csy, csz;
+    int fvol, cvol;
+    __device__ TileRT(const Gpd32Args& A) {
+        tx = A.t[0];
+        ty = A.t[1];
+        tz = A.t[2];
+        flox = A.flo[0];
+        floy = A.flo[1];
+        floz = A.flo[2];
+        clox = A.clo[0];
+        cloy = A.clo[1];
+        cloz = A.clo[2];
+        fex = A.fe[0];
+        fey = A.fe[1];
+        fez = A.fe[2];
+        cex = A.ce[0];
+        cey = A.ce[1];
+        cez = A.ce[2];
+        fsx = A.n[0] > 1 ? 1 : 0;
+        fsy = A.n[1] > 1 ? fex : 0;
+        fsz = A.n[2] > 1 ? fex * fey : 0;
+        csx = A.n[0] > 1 ? 1 : 0;
+        csy = A.n[1] > 1 ? cex : 0;
+        csz = A.n[2] > 1 ? cex * cey : 0;
+        fvol = fex * fey * fez;
+        cvol = cex * cey * cez;
+    }
+};
 
 // weights of the centred and staggered node sets for offset f in [-1/2, 1/2) of a
 // particle in cell c; returned base offsets are relative to c.
 template <int O>
 __device__ __forceinline__ void split_weights(float f, float* wc, int& bc, float* ws, int& bs) {
-    const float fl = floorf(f);  // -1 or 0
+    const float fl = f < 0.0f ? -1.0f : 0.0f;
     if (O == 2) {
         weights_frac<2, float>(f, wc);  // nodes c-1..c+1
         bc = -1;
@@ -70,7 +122,7 @@ __device__ __forceinline__ void split_weights(float f, float* wc, int& bc, float
     }
 }
 
-// centred weights of a position c + x, x in [-3/2, 3/2): first node offset and weights
+// centred weights of a position c + x, x in (-3/2, 3/2): first node offset and weights
 template <int O>
 __device__ __forceinline__ int centred_weights(float x, float* w) {
     if (O == 2) {
@@ -84,9 +136,30 @@ __device__ __forceinline__ int centred_weights(float x, float* w) {
     }
 }
 
-template <int O>
+template <int O, class TL>
+__device__ __forceinline__ float gather_comp(const float* __restrict__ F, const TL& L, int bx, int by, int bz,
+                                             const float* wx, const float* wy, const float* wz) {
+    float acc = 0.f;
+#pragma unroll
+    for (int c = 0; c <= O; ++c) {
+        float accy = 0.f;
+#pragma unroll
+        for (int b = 0; b <= O; ++b) {
+            const float* row = F + (bz + c) * L.fsz + (by + b) * L.fsy + bx * L.fsx;
+            float s = 0.f;
+#pragma unroll
+            for (int a = 0; a <= O; ++a) s += row[a * L.fsx] * wx[a];
+            accy += s * wy[b];
+        }
+        acc += accy * wz[c];
+    }
+    return acc;
+}
+
+template <int O, class TL>
 __global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const TL L(A);
     // XCD-aware tile order: consecutive workgroups go round-robin over the 8 XCDs, so give
     // each XCD a contiguous run of tiles (neighbouring tiles share halos in that XCD's L2).
     const int64_t b = blockIdx.x;
@@ -95,105 +168,88 @@ __global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
     const int ti = (int)(tile % A.nt[0]);
     const int tj = (int)((tile / A.nt[0]) % A.nt[1]);
     const int tk = (int)(tile / ((int64_t)A.nt[0] * A.nt[1]));
-    const int org[3] = {ti * A.t[0], tj * A.t[1], tk * A.t[2]};
+    const int org[3] = {ti * L.tx, tj * L.ty, tk * L.tz};
+    const int n0 = A.n[0], n1 = A.n[1], n2 = A.n[2];
+    const int nxy = n0 * n1;
 
-    const int fsx = A.fe[0], fsy = A.fe[0] * A.fe[1];
-    const int fvol = fsy * A.fe[2];
-    const int csx = A.ce[0], csy = A.ce[0] * A.ce[1];
-    const int cvol = csy * A.ce[2];
-    float* fld = lds;               // 6 * fvol: Ex Ey Ez Bx By Bz
-    float* cur = lds + 6 * fvol;    // 3 * cvol: Jx Jy Jz
+    unsigned long long* cur = (unsigned long long*)lds_raw;  // 3 * cvol
+    float* fld = (float*)(lds_raw + 3 * L.cvol * sizeof(unsigned long long));  // 6 * fvol
 
-    // 1. stage fields
-    for (int q = threadIdx.x; q < 6 * fvol; q += GPD32_BS) {
-        const int comp = q / fvol;
-        const int r = q - comp * fvol;
-        const int a = r % A.fe[0];
-        const int bb = (r / A.fe[0]) % A.fe[1];
-        const int c = r / fsy;
-        const int gi = wrap(org[0] - A.flo[0] + a, A.n[0]);
-        const int gj = wrap(org[1] - A.flo[1] + bb, A.n[1]);
-        const int gk = wrap(org[2] - A.flo[2] + c, A.n[2]);
-        const int64_t gq = (int64_t)gi + (int64_t)A.n[0] * (gj + (int64_t)A.n[1] * gk);
+    // 1. stage fields, clear the current block
+    for (int q = threadIdx.x; q < 6 * L.fvol; q += GPD32_BS) {
+        const int comp = q / L.fvol;
+        const int r = q - comp * L.fvol;
+        const int a = r % L.fex;
+        const int bb = (r / L.fex) % L.fey;
+        const int c = r / (L.fex * L.fey);
+        const int gi = wrap(org[0] - L.flox + a, n0);
+        const int gj = wrap(org[1] - L.floy + bb, n1);
+        const int gk = wrap(org[2] - L.floz + c, n2);
+        const int64_t gq = (int64_t)gi + (int64_t)n0 * (gj + (int64_t)n1 * gk);
         const double* src = comp < 3 ? A.E + comp * A.nc : A.B + (comp - 3) * A.nc;
         fld[q] = (float)src[gq];
     }
-    for (int q = threadIdx.x; q < 3 * cvol; q += GPD32_BS) cur[q] = 0.f;
+    for (int q = threadIdx.x; q < 3 * L.cvol; q += GPD32_BS) cur[q] = 0ull;
     __syncthreads();
 
-    // collapsed axes (a single cell) use stride 0 so every node offset maps to plane 0
-    const int fst[3] = {A.n[0] > 1 ? 1 : 0, A.n[1] > 1 ? fsx : 0, A.n[2] > 1 ? fsy : 0};
-    const int cst[3] = {A.n[0] > 1 ? 1 : 0, A.n[1] > 1 ? csx : 0, A.n[2] > 1 ? csy : 0};
-
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int lc[3] = {lane % A.t[0], (lane / A.t[0]) % A.t[1], lane / (A.t[0] * A.t[1])};
-    const int64_t key0 = tile * TILE_CELLS;
+    const int64_t base_cell = (int64_t)org[0] + (int64_t)n0 * (org[1] + (int64_t)n1 * org[2]);
+    const double qs = A.qscale;
     int bad_all = 0;
 
     for (int s = 0; s < A.nsp; ++s) {
         const Sp32& S = A.sp[s];
-        const int32_t start = S.off[key0 + lane];
-        const int32_t cnt = S.off[key0 + lane + 1] - start;
-        for (int k = wv; k < cnt; k += 4) {
-            const int32_t p = start + k;
+        const int32_t start = S.start[tile];
+        const int32_t end = S.start[tile + 1];
+        const double facq[3] = {(double)S.fac[0] * qs, (double)S.fac[1] * qs, (double)S.fac[2] * qs};
+        for (int32_t p = start + threadIdx.x; p < end; p += GPD32_BS) {
             const int32_t cell = S.cell[p];
             float f[3] = {S.pos[0][p], S.pos[1][p], S.pos[2][p]};
             V3<float> u{S.u[0][p], S.u[1][p], S.u[2][p]};
-            // decode and check the particle really lies in this tile's cell `lane`
-            const int gi = cell % A.n[0];
-            const int rr = cell / A.n[0];
-            const int gj = rr % A.n[1];
-            const int gk = rr / A.n[1];
-            const int loc[3] = {gi - org[0], gj - org[1], gk - org[2]};
-            if (loc[0] != lc[0] || loc[1] != lc[1] || loc[2] != lc[2] || !(f[0] >= -0.5f && f[0] < 0.5f) ||
-                !(f[1] >= -0.5f && f[1] < 0.5f) || !(f[2] >= -0.5f && f[2] < 0.5f)) {
+            // position inside the tile: rel = li + n0 lj + n0 n1 lk with l < t, found by
+            // comparisons (no division)
+            int64_t rel = (int64_t)cell - base_cell;
+            int lk = 0, lj = 0;
+            while (lk < L.tz - 1 && rel >= (int64_t)nxy) {
+                rel -= nxy;
+                ++lk;
+            }
+            while (lj < L.ty - 1 && rel >= (int64_t)n0) {
+                rel -= n0;
+                ++lj;
+            }
+            const int li = (int)rel;
+            const int loc[3] = {li, lj, lk};
+            // the particle must lie in this tile: local indices in range and the cell index
+            // rebuilt from them equal to the stored one
+            const bool inside = rel >= 0 && li < L.tx && org[0] + li < n0 && org[1] + lj < n1 && org[2] + lk < n2 &&
+                                (int64_t)(org[0] + li) + (int64_t)n0 * ((org[1] + lj) + (int64_t)n1 * (org[2] + lk)) ==
+                                    (int64_t)cell;
+            if (!inside || !(f[0] >= -0.5f && f[0] < 0.5f) || !(f[1] >= -0.5f && f[1] < 0.5f) ||
+                !(f[2] >= -0.5f && f[2] < 0.5f)) {
                 bad_all |= PP_FLAG_OUT_OF_TILE;
                 continue;
             }
 
             // gather (eq. "pfields") from the LDS field tile
             float wc[3][O + 1], ws[3][O + 1];
-            int fc[3], fs[3];  // first LDS node index per axis (centred, staggered)
+            int fc[3], fs[3];
+            {
+                const int flo[3] = {L.flox, L.floy, L.floz};
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                int bc, bs;
-                split_weights<O>(f[d], wc[d], bc, ws[d], bs);
-                fc[d] = loc[d] + A.flo[d] + bc;
-                fs[d] = loc[d] + A.flo[d] + bs;
+                for (int d = 0; d < 3; ++d) {
+                    int bc, bs;
+                    split_weights<O>(f[d], wc[d], bc, ws[d], bs);
+                    fc[d] = loc[d] + flo[d] + bc;
+                    fs[d] = loc[d] + flo[d] + bs;
+                }
             }
             V3<float> E, B;
-            {
-                auto G = [&](int comp, bool sx, bool sy, bool sz) {
-                    const float* F = fld + comp * fvol;
-                    const int bx = sx ? fs[0] : fc[0], by = sy ? fs[1] : fc[1], bz = sz ? fs[2] : fc[2];
-                    const float* wx = sx ? ws[0] : wc[0];
-                    const float* wy = sy ? ws[1] : wc[1];
-                    const float* wz = sz ? ws[2] : wc[2];
-                    // collapsed axes: nodes all at plane 0
-                    float acc = 0.f;
-#pragma unroll
-                    for (int c = 0; c <= O; ++c) {
-                        float accy = 0.f;
-#pragma unroll
-                        for (int b2 = 0; b2 <= O; ++b2) {
-                            const float* row = F + (bz + c) * fst[2] + (by + b2) * fst[1] + bx * fst[0];
-                            float sm = 0.f;
-#pragma unroll
-                            for (int a = 0; a <= O; ++a) sm += row[a * fst[0]] * wx[a];
-                            accy += sm * wy[b2];
-                        }
-                        acc += accy * wz[c];
-                    }
-                    return acc;
-                };
-                E.x = G(0, true, false, false);
-                E.y = G(1, false, true, false);
-                E.z = G(2, false, false, true);
-                B.x = G(3, false, true, true);
-                B.y = G(4, true, false, true);
-                B.z = G(5, true, true, false);
-            }
+            E.x = gather_comp<O>(fld + 0 * L.fvol, L, fs[0], fc[1], fc[2], ws[0], wc[1], wc[2]);
+            E.y = gather_comp<O>(fld + 1 * L.fvol, L, fc[0], fs[1], fc[2], wc[0], ws[1], wc[2]);
+            E.z = gather_comp<O>(fld + 2 * L.fvol, L, fc[0], fc[1], fs[2], wc[0], wc[1], ws[2]);
+            B.x = gather_comp<O>(fld + 3 * L.fvol, L, fc[0], fs[1], fs[2], wc[0], ws[1], ws[2]);
+            B.y = gather_comp<O>(fld + 4 * L.fvol, L, fs[0], fc[1], fs[2], ws[0], wc[1], ws[2]);
+            B.z = gather_comp<O>(fld + 5 * L.fvol, L, fs[0], fs[1], fc[2], ws[0], ws[1], wc[2]);
 
             if (A.pusher == PP_PUSH_BORIS)
                 push_boris<float>(S.h, A.ic, E, B, u);
@@ -219,41 +275,61 @@ __global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
             // Esirkepov current on the common window of O+2 centred nodes per axis
             float S0[3][O + 2], DS[3][O + 2];
             int wb[3];
+            {
+                const int clo[3] = {L.clox, L.cloy, L.cloz};
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                float w0[O + 1], w1[O + 1];
-                const int a0 = centred_weights<O>(f[d], w0);
-                const int a1 = centred_weights<O>(x1[d], w1);
-                const int bmin = a0 < a1 ? a0 : a1;
-                const int o0 = a0 - bmin, o1 = a1 - bmin;
+                for (int d = 0; d < 3; ++d) {
+                    float w0[O + 1], w1[O + 1];
+                    const int a0 = centred_weights<O>(f[d], w0);
+                    const int a1 = centred_weights<O>(x1[d], w1);
+                    const bool lo1 = a1 < a0;  // the new support starts one node lower
+                    const bool hi1 = a1 > a0;
+                    const int bmin = lo1 ? a1 : a0;
 #pragma unroll
-                for (int kk = 0; kk < O + 2; ++kk) {
-                    const int k0 = kk - o0, k1 = kk - o1;
-                    const float s0 = (k0 >= 0 && k0 <= O) ? w0[k0 < 0 ? 0 : (k0 > O ? O : k0)] : 0.f;
-                    const float s1 = (k1 >= 0 && k1 <= O) ? w1[k1 < 0 ? 0 : (k1 > O ? O : k1)] : 0.f;
-                    S0[d][kk] = s0;
-                    DS[d][kk] = s1 - s0;
+                    for (int kk = 0; kk < O + 2; ++kk) {
+                        // old weights sit at window offset (a0 - bmin), new at (a1 - bmin)
+                        const float s0 = lo1 ? (kk >= 1 ? w0[kk - 1 < O ? kk - 1 : O] : 0.f)
+                                             : (kk <= O ? w0[kk <= O ? kk : O] : 0.f);
+                        const float s1 = hi1 ? (kk >= 1 ? w1[kk - 1 < O ? kk - 1 : O] : 0.f)
+                                             : (kk <= O ? w1[kk <= O ? kk : O] : 0.f);
+                        S0[d][kk] = s0;
+                        DS[d][kk] = s1 - s0;
+                    }
+                    wb[d] = loc[d] + clo[d] + bmin;
                 }
-                wb[d] = loc[d] + A.clo[d] + bmin;  // first LDS current node
             }
+            const int cst[3] = {L.csx, L.csy, L.csz};
 #pragma unroll
             for (int comp = 0; comp < 3; ++comp) {
                 const int d1 = comp == 0 ? 1 : (comp == 1 ? 2 : 0);
                 const int d2 = comp == 0 ? 2 : (comp == 1 ? 0 : 1);
-                float* Jc = cur + comp * cvol;
-                const float fac = S.fac[comp];
+                unsigned long long* Jc = cur + comp * L.cvol;
+                const int off0 = wb[0] * L.csx + wb[1] * L.csy + wb[2] * L.csz;
+                // prefix sums of DS along the component's own axis (the last one vanishes)
+                float P[O + 1];
+                float acc = 0.f;
+#pragma unroll
+                for (int a = 0; a <= O; ++a) {
+                    acc += DS[comp][a];
+                    P[a] = acc;
+                }
 #pragma unroll
                 for (int bq = 0; bq < O + 2; ++bq) {
+                    // F = S0_1 (S0_2 + DS_2/2) + DS_1 (S0_2/2 + DS_2/3)
+                    const float g1 = S0[d1][bq], h1 = DS[d1][bq];
 #pragma unroll
                     for (int e = 0; e < O + 2; ++e) {
-                        const float Fq = S0[d1][bq] * S0[d2][e] + 0.5f * DS[d1][bq] * S0[d2][e] +
-                                         0.5f * S0[d1][bq] * DS[d2][e] + DS[d1][bq] * DS[d2][e] * (1.0f / 3.0f);
-                        const int rowo = (wb[d1] + bq) * cst[d1] + (wb[d2] + e) * cst[d2];
-                        float acc = 0.f;
+                        const float Fq = g1 * (S0[d2][e] + 0.5f * DS[d2][e]) +
+                                         h1 * (0.5f * S0[d2][e] + (1.0f / 3.0f) * DS[d2][e]);
+                        const int rowo = off0 + bq * cst[d1] + e * cst[d2];
 #pragma unroll
                         for (int a = 0; a <= O; ++a) {
-                            acc += DS[comp][a] * Fq;
-                            atomicAdd(Jc + rowo + (wb[comp] + a) * cst[comp], fac * acc);
+                            const float v = P[a] * Fq;
+                            // exact fixed point: round(v * fac * 2^e) as a 64-bit integer
+                            const double dq = fma((double)v, facq[comp], ROUND_MAGIC);
+                            const unsigned long long iq =
+                                (unsigned long long)(__double_as_longlong(dq) - ROUND_MAGIC_BITS);
+                            atomicAdd(Jc + rowo + a * cst[comp], iq);
                         }
                     }
                 }
@@ -262,7 +338,7 @@ __global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
             // renormalise: new cell = old cell + round(x1), offset back into [-1/2, 1/2)
             int nc3[3];
             float fn[3];
-            const int gc[3] = {gi, gj, gk};
+            const int gc[3] = {org[0] + li, org[1] + lj, org[2] + lk};
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 float sh = floorf(x1[d] + 0.5f);
@@ -281,7 +357,7 @@ __global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
                 if (v >= A.n[d]) v -= A.n[d];
                 nc3[d] = v;
             }
-            S.cell[p] = nc3[0] + A.n[0] * (nc3[1] + A.n[1] * nc3[2]);
+            S.cell[p] = nc3[0] + n0 * (nc3[1] + n1 * nc3[2]);
             S.pos[0][p] = fn[0];
             S.pos[1][p] = fn[1];
             S.pos[2][p] = fn[2];
@@ -293,43 +369,95 @@ __global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
     if (bad_all) atomic_or_flag(A.flags, bad_all);
     __syncthreads();
 
-    // 3. flush the current block
-    for (int q = threadIdx.x; q < 3 * cvol; q += GPD32_BS) {
-        const float v = cur[q];
-        if (v == 0.f) continue;
-        const int comp = q / cvol;
-        const int r = q - comp * cvol;
-        const int a = r % A.ce[0];
-        const int bb = (r / A.ce[0]) % A.ce[1];
-        const int c = r / csy;
-        const int gi = wrap(org[0] - A.clo[0] + a, A.n[0]);
-        const int gj = wrap(org[1] - A.clo[1] + bb, A.n[1]);
-        const int gk = wrap(org[2] - A.clo[2] + c, A.n[2]);
-        atomic_add_f64(A.J + comp * A.nc + (int64_t)gi + (int64_t)A.n[0] * (gj + (int64_t)A.n[1] * gk), (double)v);
+    // 3. flush the current block (integer adds commute: the sum is order-independent)
+    for (int q = threadIdx.x; q < 3 * L.cvol; q += GPD32_BS) {
+        const unsigned long long v = cur[q];
+        if (v == 0ull) continue;
+        const int comp = q / L.cvol;
+        const int r = q - comp * L.cvol;
+        const int a = r % L.cex;
+        const int bb = (r / L.cex) % L.cey;
+        const int c = r / (L.cex * L.cey);
+        const int gi = wrap(org[0] - L.clox + a, n0);
+        const int gj = wrap(org[1] - L.cloy + bb, n1);
+        const int gk = wrap(org[2] - L.cloz + c, n2);
+        atomicAdd(A.Jq + comp * A.nc + (int64_t)gi + (int64_t)n0 * (gj + (int64_t)n1 * gk), v);
+    }
+}
+
+// J (FP64) = fixed-point accumulator * 2^-e
+__global__ void __launch_bounds__(256) k_fixed_to_f64(const long long* __restrict__ Jq, double* __restrict__ J,
+                                                      int64_t n, double inv_scale) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        J[q] = (double)Jq[q] * inv_scale;
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        p[q] = 0ull;
+}
+
+enum TileKind { TILE_444 = 0, TILE_881_FLAT = 1, TILE_RT = 2 };
+
+static int tile_kind(const pp_run* r) {
+    const int* t = r->g.t;
+    const int* n = r->p.n;
+    if (t[0] == 4 && t[1] == 4 && t[2] == 4 && n[0] > 1 && n[1] > 1 && n[2] > 1) return TILE_444;
+    if (t[0] == 8 && t[1] == 8 && t[2] == 1 && n[0] > 1 && n[1] > 1 && n[2] == 1) return TILE_881_FLAT;
+    return TILE_RT;
+}
+
+static void lds_extents(const pp_run* r, int fe[3], int ce[3], int flo[3], int clo[3]) {
+    for (int d = 0; d < 3; ++d) {
+        const bool single = r->p.n[d] == 1;
+        fe[d] = single ? 1 : r->g.t[d] + FLD_LO + FLD_HI;
+        ce[d] = single ? 1 : r->g.t[d] + CUR_LO + CUR_HI;
+        flo[d] = single ? 0 : FLD_LO;
+        clo[d] = single ? 0 : CUR_LO;
     }
 }
 
 size_t gpd32_lds_bytes(const pp_run* r) {
-    int fv = 1, cv = 1;
-    for (int d = 0; d < 3; ++d) {
-        const bool single = r->p.n[d] == 1;
-        fv *= single ? 1 : r->g.t[d] + FLD_LO + FLD_HI;
-        cv *= single ? 1 : r->g.t[d] + CUR_LO + CUR_HI;
+    int fe[3], ce[3], flo[3], clo[3];
+    lds_extents(r, fe, ce, flo, clo);
+    const size_t fv = (size_t)fe[0] * fe[1] * fe[2], cv = (size_t)ce[0] * ce[1] * ce[2];
+    return 3 * cv * sizeof(unsigned long long) + 6 * fv * sizeof(float);
+}
+
+// Scale 2^e of the fixed-point current: every contribution is at most |fac| in magnitude
+// (|prefix of DS| <= 1, |F| <= 1), so any node's sum is below 2^62 when
+// 2^e * max|fac| * (number of particles) < 2^62; and a single contribution must stay
+// below 2^51 for the rounding constant.
+double gpd32_scale(const pp_run* r) {
+    double fmax = 0.0, ntot = 0.0;
+    for (int s = 0; s < PP_MAX_SPECIES; ++s) {
+        const Species& S = r->sp[s];
+        if (!S.active) continue;
+        ntot += (double)S.n;
+        for (int d = 0; d < 3; ++d) {
+            const double f = fabs(S.q * S.w * r->p.d[d] / r->p.dt);
+            fmax = f > fmax ? f : fmax;
+        }
     }
-    return (size_t)(6 * fv + 3 * cv) * sizeof(float);
+    if (!(fmax > 0.0) || !(ntot > 0.0)) return 1.0;
+    int e1 = (int)floor(62.0 - log2(fmax * ntot));
+    int e2 = (int)floor(50.0 - log2(fmax));
+    int e = e1 < e2 ? e1 : e2;
+    return ldexp(1.0, e);
 }
 
 hipError_t launch_gpd32(pp_run* r, double* J) {
     Gpd32Args A;
+    int fe[3], ce[3], flo[3], clo[3];
+    lds_extents(r, fe, ce, flo, clo);
     for (int d = 0; d < 3; ++d) {
         A.n[d] = r->p.n[d];
         A.t[d] = r->g.t[d];
         A.nt[d] = r->g.nt[d];
-        const bool single = r->p.n[d] == 1;
-        A.fe[d] = single ? 1 : r->g.t[d] + FLD_LO + FLD_HI;
-        A.ce[d] = single ? 1 : r->g.t[d] + CUR_LO + CUR_HI;
-        A.flo[d] = single ? 0 : FLD_LO;
-        A.clo[d] = single ? 0 : CUR_LO;
+        A.fe[d] = fe[d];
+        A.ce[d] = ce[d];
+        A.flo[d] = flo[d];
+        A.clo[d] = clo[d];
         A.inv_d[d] = (float)(1.0 / r->p.d[d]);
     }
     A.ntiles = r->g.ntiles;
@@ -342,7 +470,7 @@ hipError_t launch_gpd32(pp_run* r, double* J) {
         const Species& S = r->sp[s];
         if (!S.active) continue;
         Sp32& D = A.sp[A.nsp++];
-        D.off = S.offsets;
+        D.start = S.offsets;
         D.cell = S.cur.cell;
         for (int d = 0; d < 3; ++d) {
             D.pos[d] = (float*)S.cur.pos[d];
@@ -353,15 +481,41 @@ hipError_t launch_gpd32(pp_run* r, double* J) {
     }
     A.E = r->mesh.E;
     A.B = r->mesh.B;
-    A.J = J;
+    A.Jq = (unsigned long long*)r->Jq;
+    A.qscale = gpd32_scale(r);
     A.flags = r->flags;
     A.per_xcd = (int)((r->g.ntiles + 7) / 8);
+    const int64_t n3 = 3 * r->g.ncell;
+    int64_t zg = (n3 + 255) / 256;
+    if (zg > 16384) zg = 16384;
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)zg), dim3(256), 0, r->stream, (unsigned long long*)r->Jq, n3);
     const size_t lds = gpd32_lds_bytes(r);
     const unsigned grid = (unsigned)(8 * (int64_t)A.per_xcd);
-    if (r->p.shape_order == 2)
-        hipLaunchKernelGGL(k_gpd32<2>, dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
-    else
-        hipLaunchKernelGGL(k_gpd32<3>, dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
+    const int kind = tile_kind(r);
+    if (r->p.shape_order == 2) {
+        if (kind == TILE_444)
+            hipLaunchKernelGGL((k_gpd32<2, TileCT<4, 4, 4, false>>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
+        else if (kind == TILE_881_FLAT)
+            hipLaunchKernelGGL((k_gpd32<2, TileCT<8, 8, 1, true>>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
+        else
+            hipLaunchKernelGGL((k_gpd32<2, TileRT>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
+    } else {
+        if (kind == TILE_444)
+            hipLaunchKernelGGL((k_gpd32<3, TileCT<4, 4, 4, false>>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
+        else if (kind == TILE_881_FLAT)
+            hipLaunchKernelGGL((k_gpd32<3, TileCT<8, 8, 1, true>>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
+        else
+            hipLaunchKernelGGL((k_gpd32<3, TileRT>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the FP64 current the rest of the step uses
+    if (J) {
+        int64_t g = (n3 + 255) / 256;
+        if (g > 16384) g = 16384;
+        hipLaunchKernelGGL(k_fixed_to_f64, dim3((unsigned)g), dim3(256), 0, r->stream, (const long long*)r->Jq, J, n3,
+                           1.0 / A.qscale);
+    }
     return hipGetLastError();
 }
 

@@ -33,7 +33,9 @@ struct Species {
     int64_t n = 0;
     pp_particles cur{};  // buffers read by the next push
     bool sorted = false;
-    int32_t* offsets = nullptr;  // nbins + 1 bin starts (device), valid when sorted
+    // FP64 form: nbins + 1 cell-bin starts.  Split form: ntiles + 1 tile starts of the
+    // round-major order (valid when sorted).
+    int32_t* offsets = nullptr;
 };
 
 // Line-solve stencil of one axis: out[i] = sum_j coef[j] * in[(i + off + j) mod n].
@@ -59,9 +61,14 @@ struct pp_run {
     double* rho = nullptr;     // charge density (diagnostics)
     double* rho_prev = nullptr;
     int64_t rho_prev_step = -1;
-    int32_t* sort_count = nullptr;   // nbins + 1
-    int32_t* sort_cursor = nullptr;  // nbins
+    int32_t* sort_count = nullptr;   // nbins: particles per cell
+    int32_t* sort_cursor = nullptr;  // nbins: rank cursors per cell
     int32_t* scan_tmp = nullptr;     // block sums of the scan
+    int32_t* round_T = nullptr;      // ntiles * (rcap + 1): start of round r inside the tile
+    uint64_t* round_M = nullptr;     // ntiles * rcap: cells of the tile taking part in round r
+    int32_t* tile_ovf = nullptr;     // ntiles: cursor of ranks beyond rcap
+    int rcap = 0;                    // rounds held in the tables
+    long long* Jq = nullptr;         // split form: current in 64-bit fixed point (3*ncell)
     int32_t* flags = nullptr;        // device error flags
     double* dacc = nullptr;          // device accumulators for diagnostics
     pp::LineStencil line[3];

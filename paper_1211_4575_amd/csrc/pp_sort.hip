@@ -1,9 +1,21 @@
 // Per-cell particle sort (Sec. III: between the particle and field updates the particle
-// arrays are sorted by cell for cache locality).  Counting sort by tile-major cell key:
-// histogram (atomics) -> exclusive scan -> scatter into the alternate buffers (atomic
-// cursors, so the order inside a cell is unspecified) -> the buffers swap roles.  The
-// scanned bin starts stay with the species: the tiled particle kernel reads each tile's
-// range from them.
+// arrays are sorted by cell for cache locality).
+//
+// FP64 form: counting sort by tile-major cell key (histogram -> exclusive scan -> scatter
+// with atomic cursors; order inside a cell unspecified).
+//
+// Split form: "round-major" order inside each tile of 64 cells.  Every particle gets a
+// rank r inside its cell; the tile's particles are laid out round by round (all rank-0
+// particles of the tile's cells, then all rank-1 particles, ...), cells ascending inside a
+// round.  A wavefront reading 64 consecutive particles therefore reads coalesced memory and
+// its lanes sit in (almost always) 64 different cells, which keeps the LDS current
+// accumulation of the particle kernel free of same-address collisions; every wavefront
+// also gets a full 64 particles whatever the cell occupancy is.
+//   histogram per cell -> per tile (one wavefront): round starts T[r] and the bit mask of
+//   cells taking part M[r] (ballot over the 64 cells), tile totals -> scan over tiles ->
+//   scatter: r = atomic rank in the cell, position = tile start + T[r] + popcount(M[r]
+//   below the cell).  Ranks at or beyond the table capacity go to a per-tile overflow
+//   segment at the end of the tile.
 #include "pp_device.hpp"
 #include "pp_internal.hpp"
 
@@ -74,6 +86,40 @@ __global__ void __launch_bounds__(256) k_hist_cell(KeyGeom G, const int32_t* __r
     atomicAdd(count + key_cell(G, cell[p]), 1);
 }
 
+// One wavefront per tile: lane c holds the count of cell c of the tile.
+__global__ void __launch_bounds__(64) k_tile_rounds(const int32_t* __restrict__ count, int64_t ntiles, int rcap,
+                                                    int32_t* __restrict__ T, uint64_t* __restrict__ M,
+                                                    int32_t* __restrict__ tile_total, int32_t* __restrict__ ovf) {
+    const int64_t tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const int lane = threadIdx.x;
+    const int cnt = count[tile * TILE_CELLS + lane];
+    int tot = cnt, mx = cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        tot += __shfl_xor(tot, o, 64);
+        int other = __shfl_xor(mx, o, 64);
+        mx = other > mx ? other : mx;
+    }
+    const int rmax = mx < rcap ? mx : rcap;
+    int32_t* Tt = T + tile * (int64_t)(rcap + 1);
+    uint64_t* Mt = M + tile * (int64_t)rcap;
+    int run = 0;
+    for (int r = 0; r < rmax; ++r) {
+        const uint64_t m = __ballot(cnt > r);
+        if (lane == 0) {
+            Tt[r] = run;
+            Mt[r] = m;
+        }
+        run += __popcll(m);
+    }
+    if (lane == 0) {
+        Tt[rcap] = run;  // start of the overflow segment
+        tile_total[tile] = tot;
+        ovf[tile] = 0;
+    }
+}
+
 template <typename T>
 struct ScatterArgs {
     KeyGeom G;
@@ -86,24 +132,40 @@ struct ScatterArgs {
     T* pos_o[3];
     T* u_o[3];
     int64_t* id_o;
-    int32_t* cursor;
-    int split;  // 1: key from the cell index; 0: key from the FP64 position
+    int32_t* cursor;        // FP64 form: bin starts (consumed); split form: per-cell rank cursors
+    const int32_t* tstart;  // split form: tile starts
+    const int32_t* rT;
+    const uint64_t* rM;
+    int32_t* ovf;
+    int rcap;
+    int split;  // 1: round-major order from the cell index; 0: cell order from the FP64 position
 };
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_scatter(ScatterArgs<T> A) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= A.n) return;
-    int32_t key;
+    int32_t dst;
     int32_t c = 0;
     if (A.split) {
         c = A.cell[p];
-        key = key_cell(A.G, c);
+        const int32_t key = key_cell(A.G, c);
+        const int32_t tile = key / TILE_CELLS;
+        const int lc = key - tile * TILE_CELLS;
+        const int32_t r = atomicAdd(A.cursor + key, 1);
+        const int32_t base = A.tstart[tile];
+        if (r < A.rcap) {
+            const uint64_t m = A.rM[(int64_t)tile * A.rcap + r];
+            const uint64_t below = lc == 0 ? 0ull : (m & ((1ull << lc) - 1ull));
+            dst = base + A.rT[(int64_t)tile * (A.rcap + 1) + r] + __popcll(below);
+        } else {
+            dst = base + A.rT[(int64_t)tile * (A.rcap + 1) + A.rcap] + atomicAdd(A.ovf + tile, 1);
+        }
+        A.cell_o[dst] = c;
     } else {
-        key = key_f64(A.G, (double)A.pos[0][p], (double)A.pos[1][p], (double)A.pos[2][p]);
+        const int32_t key = key_f64(A.G, (double)A.pos[0][p], (double)A.pos[1][p], (double)A.pos[2][p]);
+        dst = atomicAdd(A.cursor + key, 1);
     }
-    const int32_t dst = atomicAdd(A.cursor + key, 1);
-    if (A.split) A.cell_o[dst] = c;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         A.pos_o[d][dst] = A.pos[d][p];
@@ -184,28 +246,44 @@ static KeyGeom key_geom(const pp_run* r) {
     return G;
 }
 
+static unsigned grid_for(int64_t n, int bs, int64_t cap = 65535) {
+    int64_t g = (n + bs - 1) / bs;
+    if (g > cap) g = cap;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
 template <typename T>
 static hipError_t sort_species(pp_run* r, int s) {
     Species& S = r->sp[s];
     const KeyGeom G = key_geom(r);
     const int64_t nbins = r->g.nbins;
+    const int64_t ntiles = r->g.ntiles;
     const bool split = r->p.precision == PP_PREC_FP32_SPLIT;
-    int32_t* off = S.offsets;
     const int bs = 256;
-    const unsigned fill_grid = (unsigned)((nbins + 1 + bs - 1) / bs < 65535 ? (nbins + 1 + bs - 1) / bs : 65535);
-    hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid), dim3(bs), 0, r->stream, off, nbins + 1, 0);
+    int32_t* count = split ? r->sort_count : S.offsets;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nbins + 1, bs)), dim3(bs), 0, r->stream, count, split ? nbins : nbins + 1, 0);
     if (S.n > 0) {
         const unsigned pg = (unsigned)((S.n + bs - 1) / bs);
         if (split)
-            hipLaunchKernelGGL(k_hist_cell, dim3(pg), dim3(bs), 0, r->stream, G, (const int32_t*)S.cur.cell, S.n, off);
+            hipLaunchKernelGGL(k_hist_cell, dim3(pg), dim3(bs), 0, r->stream, G, (const int32_t*)S.cur.cell, S.n, count);
         else
             hipLaunchKernelGGL(k_hist_f64, dim3(pg), dim3(bs), 0, r->stream, G, (const double*)S.cur.pos[0],
-                               (const double*)S.cur.pos[1], (const double*)S.cur.pos[2], S.n, off);
+                               (const double*)S.cur.pos[1], (const double*)S.cur.pos[2], S.n, count);
     }
-    scan_inplace(off, nbins + 1, r->scan_tmp, r->stream);
+    if (split) {
+        // per-tile round tables and totals; then tile starts
+        hipLaunchKernelGGL(k_tile_rounds, dim3((unsigned)ntiles), dim3(64), 0, r->stream, (const int32_t*)count, ntiles,
+                           r->rcap, r->round_T, r->round_M, S.offsets, r->tile_ovf);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, r->stream, S.offsets + ntiles, (int64_t)1, 0);
+        scan_inplace(S.offsets, ntiles + 1, r->scan_tmp, r->stream);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nbins, bs)), dim3(bs), 0, r->stream, r->sort_cursor, nbins, 0);
+    } else {
+        scan_inplace(S.offsets, nbins + 1, r->scan_tmp, r->stream);
+        if (S.n > 0)
+            hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(nbins, bs)), dim3(bs), 0, r->stream, r->sort_cursor,
+                               (const int32_t*)S.offsets, nbins);
+    }
     if (S.n > 0) {
-        hipLaunchKernelGGL(k_copy_i32, dim3(fill_grid), dim3(bs), 0, r->stream, r->sort_cursor, (const int32_t*)off,
-                           nbins);
         ScatterArgs<T> A;
         A.G = G;
         A.n = S.n;
@@ -220,6 +298,11 @@ static hipError_t sort_species(pp_run* r, int s) {
             A.u_o[d] = (T*)S.cur.u_alt[d];
         }
         A.cursor = r->sort_cursor;
+        A.tstart = S.offsets;
+        A.rT = r->round_T;
+        A.rM = r->round_M;
+        A.ovf = r->tile_ovf;
+        A.rcap = r->rcap;
         A.split = split ? 1 : 0;
         hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((S.n + bs - 1) / bs)), dim3(bs), 0, r->stream, A);
         // swap roles of the two buffers

@@ -1,0 +1,180 @@
+// On-device twin of the host particle loaders (inputs.py): input generation only.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/pp_inputs.h"
+
+namespace {
+
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+// Philox-4x32-R block function (Salmon, Moraes, Dror & Shaw 2011): R rounds of two 32x32->64
+// multiplies, key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t p0 = (uint64_t)M0 * c.x;
+        const uint64_t p1 = (uint64_t)M1 * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    }
+    return c;
+}
+
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
+    const double hi = (double)(a >> 5), lo = (double)(b >> 6);
+    return (hi * 67108864.0 + lo + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+__device__ __forceinline__ void uniform_pair(uint64_t seed, uint64_t idx, uint32_t blk, uint32_t stream, double& a,
+                                             double& b) {
+    U4 r = philox10(U4{(uint32_t)idx, (uint32_t)(idx >> 32), blk, stream}, (uint32_t)seed, (uint32_t)(seed >> 32));
+    a = u53(r.x, r.y);
+    b = u53(r.z, r.w);
+}
+
+__device__ __forceinline__ uint32_t stream_id(int wl, int sp, int purpose) {
+    return (uint32_t)((wl << 8) | (sp << 4) | purpose);
+}
+
+__global__ void k_philox_blocks(uint64_t seed, uint32_t block, uint32_t stream, int64_t ctr0, int64_t count,
+                                uint32_t* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint64_t c = (uint64_t)(i + ctr0);
+    U4 r = philox10(U4{(uint32_t)c, (uint32_t)(c >> 32), block, stream}, (uint32_t)seed, (uint32_t)(seed >> 32));
+    out[4 * i + 0] = r.x;
+    out[4 * i + 1] = r.y;
+    out[4 * i + 2] = r.z;
+    out[4 * i + 3] = r.w;
+}
+
+struct MJArgs {
+    uint64_t seed;
+    int n[3];
+    int64_t start, count;
+    double theta;
+    int split;
+    int32_t* cell[2];
+    void* off[2][3];
+    void* u[2][3];
+};
+
+__global__ void __launch_bounds__(256) k_pair_mj(MJArgs A) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= A.count) return;
+    const uint64_t idx = (uint64_t)(A.start + l);
+    double U[4];
+    uniform_pair(A.seed, idx, 0, stream_id(3, 0, 0), U[0], U[1]);
+    uniform_pair(A.seed, idx, 1, stream_id(3, 0, 0), U[2], U[3]);
+    double pos[3];
+    for (int d = 0; d < 3; ++d) {
+        double x = U[d] * A.n[d];
+        pos[d] = x >= A.n[d] ? 0.0 : x;
+    }
+    int32_t cellv = 0;
+    float offf[3];
+    if (A.split) {
+        int64_t ijk[3];
+        for (int d = 0; d < 3; ++d) {
+            double c = floor(pos[d] + 0.5);
+            float o = (float)(pos[d] - c);
+            if (o >= 0.5f) {
+                c += 1.0;
+                o = (float)(pos[d] - c);
+            }
+            offf[d] = o;
+            int64_t ci = (int64_t)c % A.n[d];
+            ijk[d] = ci < 0 ? ci + A.n[d] : ci;
+        }
+        cellv = (int32_t)(ijk[0] + (int64_t)A.n[0] * (ijk[1] + (int64_t)A.n[1] * ijk[2]));
+    }
+    for (int s = 0; s < 2; ++s) {
+        // Sobol rejection: attempt t uses draw blocks 2t, 2t+1
+        double mag = 0.0;
+        for (int t = 0; t < 64; ++t) {
+            double x1, x2, x3, x4;
+            uniform_pair(A.seed, idx, 2 * t, stream_id(3, s, 1), x1, x2);
+            uniform_pair(A.seed, idx, 2 * t + 1, stream_id(3, s, 1), x3, x4);
+            const double uu = -A.theta * log(x1 * x2 * x3);
+            const double eta = -A.theta * log(x1 * x2 * x3 * x4);
+            if (eta * eta - uu * uu > 1.0) {
+                mag = uu;
+                break;
+            }
+        }
+        double a, b;
+        uniform_pair(A.seed, idx, 0, stream_id(3, s, 2), a, b);
+        const double cz = 2.0 * a - 1.0;
+        const double ph = 2.0 * M_PI * b;
+        const double sz = sqrt(fmax(0.0, 1.0 - cz * cz));
+        const double uv[3] = {sz * cos(ph) * mag, sz * sin(ph) * mag, cz * mag};
+        if (A.split) {
+            A.cell[s][l] = cellv;
+            for (int d = 0; d < 3; ++d) {
+                ((float*)A.off[s][d])[l] = offf[d];
+                ((float*)A.u[s][d])[l] = (float)uv[d];
+            }
+        } else {
+            for (int d = 0; d < 3; ++d) {
+                ((double*)A.off[s][d])[l] = pos[d];
+                ((double*)A.u[s][d])[l] = uv[d];
+            }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int ppi_philox_blocks(uint64_t seed, uint32_t block, uint32_t stream, int64_t ctr0, int64_t count, uint32_t* out,
+                      void* hip_stream) {
+    if (count < 0 || (count > 0 && !out)) return -1;
+    if (count == 0) return 0;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_philox_blocks, dim3((unsigned)((count + bs - 1) / bs)), dim3(bs), 0, (hipStream_t)hip_stream,
+                       seed, block, stream, ctr0, count, out);
+    return hipGetLastError() == hipSuccess ? 0 : -6;
+}
+
+int ppi_pair_maxwell_juttner(uint64_t seed, const int32_t n[3], int64_t start, int64_t count, double theta,
+                             int32_t split, int32_t* const cell[2], void* const off[2][3], void* const u[2][3],
+                             void* hip_stream) {
+    if (!n || count < 0 || start < 0 || !(theta > 0.0)) return -1;
+    for (int d = 0; d < 3; ++d)
+        if (n[d] < 1) return -1;
+    if (count == 0) return 0;
+    MJArgs A;
+    A.seed = seed;
+    for (int d = 0; d < 3; ++d) A.n[d] = n[d];
+    A.start = start;
+    A.count = count;
+    A.theta = theta;
+    A.split = split ? 1 : 0;
+    for (int s = 0; s < 2; ++s) {
+        A.cell[s] = cell ? cell[s] : nullptr;
+        if (split && !A.cell[s]) return -1;
+        for (int d = 0; d < 3; ++d) {
+            A.off[s][d] = off[s][d];
+            A.u[s][d] = u[s][d];
+            if (!A.off[s][d] || !A.u[s][d]) return -1;
+        }
+    }
+    const int bs = 256;
+    hipLaunchKernelGGL(k_pair_mj, dim3((unsigned)((count + bs - 1) / bs)), dim3(bs), 0, (hipStream_t)hip_stream, A);
+    return hipGetLastError() == hipSuccess ? 0 : -6;
+}
+
+}  // extern "C"

@@ -226,13 +226,21 @@ class Run:
     def _add_species(self, s, sp, with_id):
         torch = self.torch
         rt = torch.float32 if self.split else torch.float64
-        if self.split:
+        if isinstance(sp.get("u"), torch.Tensor):
+            # device tensors handed over as they are
+            cell = sp.get("cell")
+            pos = sp["off"] if self.split else sp["pos"]
+            u = sp["u"]
+            assert u.dtype == rt and pos.dtype == rt and u.is_contiguous() and pos.is_contiguous()
+            assert cell is None or (cell.dtype == torch.int32 and cell.is_contiguous())
+        elif self.split:
             cell = torch.as_tensor(np.ascontiguousarray(sp["cell"], dtype=np.int32)).to(self.dev)
             pos = torch.as_tensor(np.ascontiguousarray(sp["off"], dtype=np.float32)).to(self.dev)
+            u = torch.as_tensor(np.ascontiguousarray(sp["u"])).to(dtype=rt, device=self.dev).contiguous()
         else:
             cell = None
             pos = torch.as_tensor(np.ascontiguousarray(sp["pos"], dtype=np.float64)).to(self.dev)
-        u = torch.as_tensor(np.ascontiguousarray(sp["u"])).to(dtype=rt, device=self.dev).contiguous()
+            u = torch.as_tensor(np.ascontiguousarray(sp["u"])).to(dtype=rt, device=self.dev).contiguous()
         n = pos.shape[1]
         ids = torch.arange(n, dtype=torch.int64, device=self.dev) if with_id else None
         alt = dict(pos=torch.empty_like(pos), u=torch.empty_like(u),

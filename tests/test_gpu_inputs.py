@@ -1,0 +1,50 @@
+"""GPU: the on-device loader reproduces the host loader (input generation only): identical
+Philox-4x32-10 integers, identical positions, momenta equal to rounding except for rare
+rejection decisions taken on the other side of the threshold."""
+import numpy as np
+import pytest
+
+from paper_1211_4575_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def test_device_philox_matches_host():
+    import torch
+    from paper_1211_4575_amd import inputs_device as ind
+    out = torch.zeros(4 * 1000, dtype=torch.int32, device="cuda")
+    ind.philox_blocks(I.SEED_BASE, 3, 0x301, 123456, 1000, out, torch.cuda.current_stream().cuda_stream)
+    got = out.cpu().numpy().view(np.uint32).reshape(1000, 4)
+    idx = np.arange(123456, 124456, dtype=np.uint64)
+    lo = (idx & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    hi = (idx >> np.uint64(32)).astype(np.uint32)
+    ref = I.philox4x32(lo, hi, np.uint32(3), np.uint32(0x301), I.SEED_BASE & 0xFFFFFFFF, I.SEED_BASE >> 32)
+    assert np.array_equal(got, np.stack(ref, axis=1))
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_device_pair_mj_matches_host(split):
+    import torch
+    from paper_1211_4575_amd import inputs_device as ind
+    n = (16, 8, 12)
+    start, cnt = 5000, 20000
+    rt = torch.float32 if split else torch.float64
+    cells = [torch.empty(cnt, dtype=torch.int32, device="cuda") for _ in range(2)] if split else None
+    offs = [torch.empty((3, cnt), dtype=rt, device="cuda") for _ in range(2)]
+    us = [torch.empty((3, cnt), dtype=rt, device="cuda") for _ in range(2)]
+    ind.pair_maxwell_juttner(I.SEED_BASE, n, start, cnt, 1.0, split, cells, [[o[d] for d in range(3)] for o in offs],
+                             [[u[d] for d in range(3)] for u in us], torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    wl = I.pair_maxwell_juttner(n=n, ppc=32, index_range=(start, start + cnt))
+    for s in range(2):
+        u = us[s].cpu().numpy().astype(np.float64)
+        uref = wl.species[s].u
+        if split:
+            cell, off = I.to_split(wl.species[s].pos, n)
+            assert np.array_equal(cells[s].cpu().numpy(), cell)
+            assert np.array_equal(offs[s].cpu().numpy(), off)
+            close = np.all(np.abs(u - uref) <= 1e-6 * (1 + np.abs(uref)), axis=0)
+        else:
+            assert np.array_equal(offs[s].cpu().numpy(), wl.species[s].pos)
+            close = np.all(np.abs(u - uref) <= 1e-12 * (1 + np.abs(uref)), axis=0)
+        assert close.mean() > 0.999

@@ -174,9 +174,21 @@ def test_fp64_whole_run_plain_heating(ppm, orc):
 
 
 def test_sort_is_a_permutation_by_cell(ppm, orc):
+    # FP64 form: every cell's particles contiguous.  Split form: round-major order inside
+    # each tile (neighbouring particles sit in different cells); both are permutations.
     n = (12, 8, 4)
     _say("sort", n)
     species, E, B = random_state(orc, n, 5, seed=11)
+    run = ppm.Run(ppm.make_params(n=n, shape_order=3, field_order=2, precision=ppm.PP_PREC_FP64), species, E=E, B=B)
+    run.step()
+    for s in range(2):
+        g = run.particles(s)
+        assert np.array_equal(np.sort(g["id"]), np.arange(len(g["id"])))
+        ijk = np.floor(g["pos"] + 0.5).astype(np.int64) % np.array(n)[:, None]
+        cells = ijk[0] + n[0] * (ijk[1] + n[1] * ijk[2])
+        change = np.flatnonzero(np.diff(cells) != 0)
+        assert len(change) + 1 == len(np.unique(cells))
+    run.close()
     sp32 = _split_species(species, n)
     run = ppm.Run(ppm.make_params(n=n, shape_order=3, field_order=2, precision=ppm.PP_PREC_FP32_SPLIT), sp32, E=E,
                   B=B)
@@ -184,11 +196,8 @@ def test_sort_is_a_permutation_by_cell(ppm, orc):
     for s in range(2):
         g = run.particles(s)
         assert np.array_equal(np.sort(g["id"]), np.arange(len(g["id"])))
-        cells = g["cell"]
-        # tile-major key must be non-decreasing along the array
-        # every cell's particles are contiguous (the tile-major key order is internal)
-        change = np.flatnonzero(np.diff(cells) != 0)
-        assert len(change) + 1 == len(np.unique(cells))
+        same = np.mean(np.diff(g["cell"]) == 0)
+        assert same < 0.05, same
     run.close()
 
 
