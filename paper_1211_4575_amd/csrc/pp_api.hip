@@ -90,14 +90,13 @@ static void release(pp_run* r) {
     f(r->rho);
     f(r->rho_prev);
     f(r->sort_cursor);
-    f(r->sort_count);
+    f(r->sort_scratch);
     f(r->scan_tmp);
     f(r->flags);
     f(r->dacc);
-    f(r->round_T);
-    f(r->round_M);
-    f(r->tile_ovf);
     f(r->Jq);
+    f(r->tile_max);
+    f(r->qscale);
     for (int d = 0; d < 3; ++d) f(r->line[d].coef);
     for (int s = 0; s < PP_MAX_SPECIES; ++s) f(r->sp[s].offsets);
     if (r->ev0) (void)hipEventDestroy(r->ev0);
@@ -164,11 +163,11 @@ pp_status pp_create(const pp_params* params, const pp_mesh* mesh, void* hip_stre
     if (params->field_order > 2) okk = okk && dmalloc(&r->J2, n3);
     okk = okk && dmalloc(&r->Bn, n3) && dmalloc(&r->Bw, n3) && dmalloc(&r->R, n3);
     okk = okk && dmalloc(&r->rho, (size_t)g.ncell) && dmalloc(&r->rho_prev, (size_t)g.ncell);
-    okk = okk && dmalloc(&r->sort_cursor, (size_t)g.nbins) && dmalloc(&r->sort_count, (size_t)g.nbins) &&
-          dmalloc(&r->scan_tmp, (size_t)scan_tmp_size(g.nbins + 1));
+    okk = okk && dmalloc(&r->sort_cursor, (size_t)g.nbins) && dmalloc(&r->scan_tmp, (size_t)scan_tmp_size(g.nbins + 1));
     okk = okk && dmalloc(&r->flags, 1) && dmalloc(&r->dacc, (size_t)diag_acc_count() + 8);
     if (params->precision == PP_PREC_FP32_SPLIT) {
-        okk = okk && dmalloc(&r->Jq, n3) && dmalloc(&r->tile_ovf, (size_t)g.ntiles);
+        okk = okk && dmalloc(&r->Jq, n3) && dmalloc(&r->tile_max, PP_MAX_SPECIES) && dmalloc(&r->qscale, 1) &&
+              ok(hipMemset(r->tile_max, 0, PP_MAX_SPECIES * sizeof(int32_t)), "hipMemset");
     }
     if (okk && params->field_order > 2) {
         for (int d = 0; d < 3; ++d) {
@@ -230,23 +229,12 @@ pp_status pp_init_species(pp_run* r, int32_t s, double q, double m, double w, co
     }
     Species& S = r->sp[s];
     if (!S.offsets && !dmalloc(&S.offsets, (size_t)r->g.nbins + 1)) return PP_E_HIP;
-    if (split) {
-        // rounds held in the per-tile tables: twice the mean occupancy plus a margin (ranks
-        // beyond it still sort correctly, into a per-tile overflow segment)
-        int64_t mean = (parts->n + r->g.ncell - 1) / r->g.ncell;
-        int64_t want = 2 * mean + 64;
-        if (want > 4096) want = 4096;
-        if (want > r->rcap) {
-            if (r->round_T) (void)hipFree(r->round_T);
-            if (r->round_M) (void)hipFree(r->round_M);
-            r->round_T = nullptr;
-            r->round_M = nullptr;
-            r->rcap = 0;
-            if (!dmalloc(&r->round_T, (size_t)r->g.ntiles * (size_t)(want + 1)) ||
-                !dmalloc(&r->round_M, (size_t)r->g.ntiles * (size_t)want))
-                return PP_E_HIP;
-            r->rcap = (int)want;
-        }
+    if (split && parts->n > r->sort_scratch_n) {
+        if (r->sort_scratch) (void)hipFree(r->sort_scratch);
+        r->sort_scratch = nullptr;
+        r->sort_scratch_n = 0;
+        if (!dmalloc(&r->sort_scratch, 2 * (size_t)parts->n)) return PP_E_HIP;
+        r->sort_scratch_n = parts->n;
     }
     S.active = true;
     S.q = q;
@@ -261,7 +249,7 @@ pp_status pp_init_species(pp_run* r, int32_t s, double q, double m, double w, co
     if (!parts->id) S.cur.id_alt = nullptr;
     S.sorted = false;
     // initial sort: the split form needs it before its first push
-    hipError_t e = launch_sort(r, s);
+    hipError_t e = launch_sort(r, s, true);
     if (!ok(e, "sort")) return PP_E_HIP;
     return PP_OK;
 }
@@ -317,9 +305,11 @@ pp_status pp_sort_particles(pp_run* r, int32_t s) {
             if (s >= 0) return PP_E_STATE;
             continue;
         }
-        hipError_t e = launch_sort(r, k);
+        const bool reorder = (r->sorts_done % REORDER_EVERY) == REORDER_EVERY - 1;
+        hipError_t e = launch_sort(r, k, reorder);
         if (!ok(e, "sort")) return PP_E_HIP;
     }
+    r->sorts_done += 1;
     return PP_OK;
 }
 

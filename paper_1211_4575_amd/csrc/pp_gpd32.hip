@@ -10,12 +10,17 @@
 //      position -> Esirkepov current (registers) -> LDS accumulation of the tile's current
 //      block (3-node halo);
 //   3. flush the current block to the global accumulator with 64-bit integer atomics.
-// Current accumulation is exact 64-bit fixed point: each FP32 contribution c is rounded to
-// an integer multiple of 2^-e (one FP64 fused multiply-add with the 1.5*2^52 rounding
-// constant) and added with integer atomics, which run at full LDS rate where FP32 LDS
-// atomics do not.  The scale 2^e is chosen so that no sum can overflow; the result is the
-// exact sum of the rounded contributions, independent of summation order (bitwise
-// deterministic).  All species are processed by the same workgroup.
+// Current accumulation is exact 64-bit fixed point.  Each contribution P_a * F * fac is
+// formed in FP64 by one fused multiply-add with the rounding constant 1.5*2^52, whose bit
+// pattern is then (constant bits + round(contribution * 2^e)); that pattern is added to the
+// LDS block with an integer atomic (integer LDS atomics run at full rate on gfx950, FP32 LDS
+// atomics at a small fraction of it).  The constant's share of a node's sum only touches bit
+// 51 and above, so the sum of the rounded contributions is the sign-extended low 51 bits,
+// recovered when the block is flushed; the scale 2^e (from the largest particle count of any
+// tile) keeps every node's sum below 2^50 in magnitude.  The global accumulator adds the
+// recovered integers, so the current is the exact sum of the rounded contributions,
+// independent of summation order (bitwise deterministic).  All species are processed by the
+// same workgroup.
 #include "pp_device.hpp"
 #include "pp_internal.hpp"
 
@@ -26,8 +31,8 @@ struct Sp32 {
     int32_t* cell;
     float* pos[3];
     float* u[3];
-    float h;       // q dt / m
-    float fac[3];  // -q w d_c / dt
+    float h;        // q dt / m
+    double fac[3];  // -q w d_c / dt
 };
 
 struct Gpd32Args {
@@ -47,14 +52,20 @@ struct Gpd32Args {
     const double* E;
     const double* B;
     unsigned long long* Jq;  // fixed-point current accumulator (3 * nc)
-    double qscale;           // 2^e
+    const double* qscale;    // 2^e (device, set by k_fixed_scale)
     int32_t* flags;
     int per_xcd;
 };
 
 constexpr int GPD32_BS = 256;
 constexpr double ROUND_MAGIC = 6755399441055744.0;  // 1.5 * 2^52
-constexpr long long ROUND_MAGIC_BITS = 0x4338000000000000LL;
+constexpr unsigned long long LOW51 = (1ull << 51) - 1ull;
+constexpr long long BIT50 = 1ll << 50;
+
+// sum of rounded contributions held in the low 51 bits of an accumulated bit pattern
+__device__ __forceinline__ long long fixed_sum(unsigned long long v) {
+    return (long long)((v & LOW51) ^ (unsigned long long)BIT50) - BIT50;
+}
 
 // LDS layout of a tile: compile-time for the common shapes, runtime otherwise.  A
 // single-cell axis is collapsed (extent 1, stride 0): every node offset maps to plane 0.
@@ -172,8 +183,9 @@ __global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
     const int n0 = A.n[0], n1 = A.n[1], n2 = A.n[2];
     const int nxy = n0 * n1;
 
-    unsigned long long* cur = (unsigned long long*)lds_raw;  // 3 * cvol
-    float* fld = (float*)(lds_raw + 3 * L.cvol * sizeof(unsigned long long));  // 6 * fvol
+    // fields first: the gather's LDS reads then use small immediate offsets
+    float* fld = (float*)lds_raw;  // 6 * fvol
+    unsigned long long* cur = (unsigned long long*)(lds_raw + ((6 * L.fvol * sizeof(float) + 15) & ~(size_t)15));
 
     // 1. stage fields, clear the current block
     for (int q = threadIdx.x; q < 6 * L.fvol; q += GPD32_BS) {
@@ -193,14 +205,14 @@ __global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
     __syncthreads();
 
     const int64_t base_cell = (int64_t)org[0] + (int64_t)n0 * (org[1] + (int64_t)n1 * org[2]);
-    const double qs = A.qscale;
+    const double qs = *A.qscale;
     int bad_all = 0;
 
     for (int s = 0; s < A.nsp; ++s) {
         const Sp32& S = A.sp[s];
         const int32_t start = S.start[tile];
         const int32_t end = S.start[tile + 1];
-        const double facq[3] = {(double)S.fac[0] * qs, (double)S.fac[1] * qs, (double)S.fac[2] * qs};
+        const double facq[3] = {S.fac[0] * qs, S.fac[1] * qs, S.fac[2] * qs};
         for (int32_t p = start + threadIdx.x; p < end; p += GPD32_BS) {
             const int32_t cell = S.cell[p];
             float f[3] = {S.pos[0][p], S.pos[1][p], S.pos[2][p]};
@@ -305,13 +317,14 @@ __global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
                 const int d2 = comp == 0 ? 2 : (comp == 1 ? 0 : 1);
                 unsigned long long* Jc = cur + comp * L.cvol;
                 const int off0 = wb[0] * L.csx + wb[1] * L.csy + wb[2] * L.csz;
-                // prefix sums of DS along the component's own axis (the last one vanishes)
-                float P[O + 1];
+                // prefix sums of DS along the component's own axis (the last one vanishes),
+                // scaled to fixed-point units: P_a * fac * 2^e in FP64
+                double Pq[O + 1];
                 float acc = 0.f;
 #pragma unroll
                 for (int a = 0; a <= O; ++a) {
                     acc += DS[comp][a];
-                    P[a] = acc;
+                    Pq[a] = (double)acc * facq[comp];
                 }
 #pragma unroll
                 for (int bq = 0; bq < O + 2; ++bq) {
@@ -321,15 +334,13 @@ __global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
                     for (int e = 0; e < O + 2; ++e) {
                         const float Fq = g1 * (S0[d2][e] + 0.5f * DS[d2][e]) +
                                          h1 * (0.5f * S0[d2][e] + (1.0f / 3.0f) * DS[d2][e]);
+                        const double Fd = (double)Fq;
                         const int rowo = off0 + bq * cst[d1] + e * cst[d2];
 #pragma unroll
                         for (int a = 0; a <= O; ++a) {
-                            const float v = P[a] * Fq;
-                            // exact fixed point: round(v * fac * 2^e) as a 64-bit integer
-                            const double dq = fma((double)v, facq[comp], ROUND_MAGIC);
-                            const unsigned long long iq =
-                                (unsigned long long)(__double_as_longlong(dq) - ROUND_MAGIC_BITS);
-                            atomicAdd(Jc + rowo + a * cst[comp], iq);
+                            // bits of (1.5*2^52 + round(P_a F fac 2^e)): see the header
+                            const double dq = fma(Pq[a], Fd, ROUND_MAGIC);
+                            atomicAdd(Jc + rowo + a * cst[comp], (unsigned long long)__double_as_longlong(dq));
                         }
                     }
                 }
@@ -371,8 +382,8 @@ __global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
 
     // 3. flush the current block (integer adds commute: the sum is order-independent)
     for (int q = threadIdx.x; q < 3 * L.cvol; q += GPD32_BS) {
-        const unsigned long long v = cur[q];
-        if (v == 0ull) continue;
+        const long long v = fixed_sum(cur[q]);
+        if (v == 0) continue;
         const int comp = q / L.cvol;
         const int r = q - comp * L.cvol;
         const int a = r % L.cex;
@@ -381,15 +392,27 @@ __global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
         const int gi = wrap(org[0] - L.clox + a, n0);
         const int gj = wrap(org[1] - L.cloy + bb, n1);
         const int gk = wrap(org[2] - L.cloz + c, n2);
-        atomicAdd(A.Jq + comp * A.nc + (int64_t)gi + (int64_t)n0 * (gj + (int64_t)n1 * gk), v);
+        atomicAdd(A.Jq + comp * A.nc + (int64_t)gi + (int64_t)n0 * (gj + (int64_t)n1 * gk), (unsigned long long)v);
     }
 }
 
 // J (FP64) = fixed-point accumulator * 2^-e
 __global__ void __launch_bounds__(256) k_fixed_to_f64(const long long* __restrict__ Jq, double* __restrict__ J,
-                                                      int64_t n, double inv_scale) {
+                                                      int64_t n, const double* __restrict__ scale) {
+    const double inv = 1.0 / *scale;  // exact: a power of two
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
-        J[q] = (double)Jq[q] * inv_scale;
+        J[q] = (double)Jq[q] * inv;
+}
+
+// 2^e with e = e0 - ceil(log2(N)), N the sum over species of the largest particle count of
+// any tile: then |one contribution| <= 2^(50 - ceil log2 N) and |a node's LDS sum| <= 2^50.
+__global__ void k_fixed_scale(const int32_t* __restrict__ tile_max, int nsp, int e0, double* scale) {
+    if (threadIdx.x != 0) return;
+    long long nb = 0;
+    for (int s = 0; s < nsp; ++s) nb += tile_max[s];
+    int lg = 0;
+    while ((1ll << lg) < nb) ++lg;
+    *scale = ldexp(1.0, e0 - lg);
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
@@ -421,29 +444,28 @@ size_t gpd32_lds_bytes(const pp_run* r) {
     int fe[3], ce[3], flo[3], clo[3];
     lds_extents(r, fe, ce, flo, clo);
     const size_t fv = (size_t)fe[0] * fe[1] * fe[2], cv = (size_t)ce[0] * ce[1] * ce[2];
-    return 3 * cv * sizeof(unsigned long long) + 6 * fv * sizeof(float);
+    return ((6 * fv * sizeof(float) + 15) & ~(size_t)15) + 3 * cv * sizeof(unsigned long long);
 }
 
-// Scale 2^e of the fixed-point current: every contribution is at most |fac| in magnitude
-// (|prefix of DS| <= 1, |F| <= 1), so any node's sum is below 2^62 when
-// 2^e * max|fac| * (number of particles) < 2^62; and a single contribution must stay
-// below 2^51 for the rounding constant.
-double gpd32_scale(const pp_run* r) {
-    double fmax = 0.0, ntot = 0.0;
+// Host part of the fixed-point exponent: e0 = 50 - ceil(log2(max |fac|)), every contribution
+// being at most |fac| = |q w d / dt| in magnitude (|prefix of DS| <= 1 and 0 <= F <= 1).
+int gpd32_scale_e0(const pp_run* r) {
+    double fmax = 0.0;
     for (int s = 0; s < PP_MAX_SPECIES; ++s) {
         const Species& S = r->sp[s];
         if (!S.active) continue;
-        ntot += (double)S.n;
         for (int d = 0; d < 3; ++d) {
             const double f = fabs(S.q * S.w * r->p.d[d] / r->p.dt);
             fmax = f > fmax ? f : fmax;
         }
     }
-    if (!(fmax > 0.0) || !(ntot > 0.0)) return 1.0;
-    int e1 = (int)floor(62.0 - log2(fmax * ntot));
-    int e2 = (int)floor(50.0 - log2(fmax));
-    int e = e1 < e2 ? e1 : e2;
-    return ldexp(1.0, e);
+    if (!(fmax > 0.0)) return 0;
+    // on a single-cell axis the O+2 window nodes of a particle all land on one LDS node, so a
+    // node can receive up to O+2 contributions of one particle per such axis
+    int collapsed = 0;
+    for (int d = 0; d < 3; ++d) collapsed += r->p.n[d] == 1 ? 1 : 0;
+    const int per_axis = (int)ceil(log2((double)(r->p.shape_order + 2)));
+    return 50 - (int)ceil(log2(fmax)) - collapsed * per_axis;
 }
 
 hipError_t launch_gpd32(pp_run* r, double* J) {
@@ -466,23 +488,28 @@ hipError_t launch_gpd32(pp_run* r, double* J) {
     A.ic = (float)(1.0 / r->p.c);
     A.pusher = r->p.pusher;
     A.nsp = 0;
+    int tile_max_idx[PP_MAX_SPECIES];
     for (int s = 0; s < PP_MAX_SPECIES; ++s) {
         const Species& S = r->sp[s];
         if (!S.active) continue;
+        tile_max_idx[A.nsp] = s;
         Sp32& D = A.sp[A.nsp++];
         D.start = S.offsets;
         D.cell = S.cur.cell;
         for (int d = 0; d < 3; ++d) {
             D.pos[d] = (float*)S.cur.pos[d];
             D.u[d] = (float*)S.cur.u[d];
-            D.fac[d] = (float)(-S.q * S.w * r->p.d[d] / r->p.dt);
+            D.fac[d] = -S.q * S.w * r->p.d[d] / r->p.dt;
         }
         D.h = (float)(S.q * r->p.dt / S.m);
     }
     A.E = r->mesh.E;
     A.B = r->mesh.B;
     A.Jq = (unsigned long long*)r->Jq;
-    A.qscale = gpd32_scale(r);
+    A.qscale = r->qscale;
+    (void)tile_max_idx;
+    hipLaunchKernelGGL(k_fixed_scale, dim3(1), dim3(64), 0, r->stream, (const int32_t*)r->tile_max, PP_MAX_SPECIES,
+                       gpd32_scale_e0(r), r->qscale);
     A.flags = r->flags;
     A.per_xcd = (int)((r->g.ntiles + 7) / 8);
     const int64_t n3 = 3 * r->g.ncell;
@@ -514,7 +541,7 @@ hipError_t launch_gpd32(pp_run* r, double* J) {
         int64_t g = (n3 + 255) / 256;
         if (g > 16384) g = 16384;
         hipLaunchKernelGGL(k_fixed_to_f64, dim3((unsigned)g), dim3(256), 0, r->stream, (const long long*)r->Jq, J, n3,
-                           1.0 / A.qscale);
+                           (const double*)r->qscale);
     }
     return hipGetLastError();
 }

@@ -17,6 +17,9 @@ constexpr int TILE_CELLS = 64;
 // LDS halo of the field tile (nodes below / above the tile) and of the current tile.
 constexpr int FLD_LO = 2, FLD_HI = 2;
 constexpr int CUR_LO = 3, CUR_HI = 3;
+// split form: the round-major order is rebuilt at the first sort and then every this many
+// sorts of a species (the bucketing sort in between keeps most of it)
+constexpr int REORDER_EVERY = 4;
 
 struct Geom {
     int n[3];       // cells
@@ -61,14 +64,14 @@ struct pp_run {
     double* rho = nullptr;     // charge density (diagnostics)
     double* rho_prev = nullptr;
     int64_t rho_prev_step = -1;
-    int32_t* sort_count = nullptr;   // nbins: particles per cell
-    int32_t* sort_cursor = nullptr;  // nbins: rank cursors per cell
-    int32_t* scan_tmp = nullptr;     // block sums of the scan
-    int32_t* round_T = nullptr;      // ntiles * (rcap + 1): start of round r inside the tile
-    uint64_t* round_M = nullptr;     // ntiles * rcap: cells of the tile taking part in round r
-    int32_t* tile_ovf = nullptr;     // ntiles: cursor of ranks beyond rcap
-    int rcap = 0;                    // rounds held in the tables
-    long long* Jq = nullptr;         // split form: current in 64-bit fixed point (3*ncell)
+    int32_t* sort_cursor = nullptr;   // nbins: scatter cursors (cell bins or tiles)
+    int32_t* scan_tmp = nullptr;      // block sums of the scan
+    int32_t* sort_scratch = nullptr;  // split form: rank and permutation of the round-major rebuild
+    int64_t sort_scratch_n = 0;       // particles per half of sort_scratch
+    int64_t sorts_done = 0;           // split form: counts sorts to schedule the rebuilds
+    long long* Jq = nullptr;          // split form: current in 64-bit fixed point (3*ncell)
+    int32_t* tile_max = nullptr;      // split form: largest particle count of a tile, per species
+    double* qscale = nullptr;         // split form: 2^e of the fixed-point current (device)
     int32_t* flags = nullptr;        // device error flags
     double* dacc = nullptr;          // device accumulators for diagnostics
     pp::LineStencil line[3];
@@ -106,7 +109,7 @@ hipError_t launch_gpd64(pp_run* r, int s, double* J);
 hipError_t launch_gpd32(pp_run* r, double* J);
 hipError_t launch_line_solve(pp_run* r, const double* J2, double* J);
 hipError_t launch_field_step(pp_run* r);
-hipError_t launch_sort(pp_run* r, int s);
+hipError_t launch_sort(pp_run* r, int s, bool reorder);
 hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 

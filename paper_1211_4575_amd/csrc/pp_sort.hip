@@ -4,18 +4,17 @@
 // FP64 form: counting sort by tile-major cell key (histogram -> exclusive scan -> scatter
 // with atomic cursors; order inside a cell unspecified).
 //
-// Split form: "round-major" order inside each tile of 64 cells.  Every particle gets a
-// rank r inside its cell; the tile's particles are laid out round by round (all rank-0
+// Split form: particles are bucketed by tile (64 cells): a count per tile, a scan over
+// tiles, and a scatter whose positions come from wavefront-aggregated atomics (one atomic per
+// destination tile per wavefront, so a wavefront's particles that stay in their tile are
+// written as one contiguous, coalesced block and keep their previous relative order).  The
+// particle kernel only needs each tile's particles to be contiguous.  It runs fastest when
+// 64 consecutive particles sit in 64 different cells, so at initialisation and then every
+// few sorts a per-tile pass rebuilds the "round-major" order: every particle gets a rank r
+// inside its cell, and the tile's particles are laid out round by round (all rank-0
 // particles of the tile's cells, then all rank-1 particles, ...), cells ascending inside a
-// round.  A wavefront reading 64 consecutive particles therefore reads coalesced memory and
-// its lanes sit in (almost always) 64 different cells, which keeps the LDS current
-// accumulation of the particle kernel free of same-address collisions; every wavefront
-// also gets a full 64 particles whatever the cell occupancy is.
-//   histogram per cell -> per tile (one wavefront): round starts T[r] and the bit mask of
-//   cells taking part M[r] (ballot over the 64 cells), tile totals -> scan over tiles ->
-//   scatter: r = atomic rank in the cell, position = tile start + T[r] + popcount(M[r]
-//   below the cell).  Ranks at or beyond the table capacity go to a per-tile overflow
-//   segment at the end of the tile.
+// round.  Between rebuilds the bucketing keeps most of that order because most particles
+// stay in their tile and their block keeps its order.
 #include "pp_device.hpp"
 #include "pp_internal.hpp"
 
@@ -79,45 +78,60 @@ __global__ void __launch_bounds__(256) k_hist_f64(KeyGeom G, const double* __res
     atomicAdd(count + key_f64(G, x[p], y[p], z[p]), 1);
 }
 
-__global__ void __launch_bounds__(256) k_hist_cell(KeyGeom G, const int32_t* __restrict__ cell, int64_t n,
-                                                   int32_t* count) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    atomicAdd(count + key_cell(G, cell[p]), 1);
+// Block-level aggregation for the bucketing sort: a block of 256 threads handles 1024
+// consecutive particles; each wavefront groups its lanes by destination tile (ballot loop),
+// the group leader reserves slots in a small LDS table keyed by tile, and after a barrier
+// one global atomic per distinct tile of the block reserves the block's run in that tile.
+// A block's particles come from one or two source tiles, so its destinations are a few
+// tiles of their neighbourhood.
+constexpr int AGG_SLOTS = 128;
+constexpr int AGG_PER_THREAD = 4;
+constexpr int AGG_BLOCK = 256 * AGG_PER_THREAD;
+
+// LDS slot of a key (open addressing); -1 when the table is full
+__device__ __forceinline__ int agg_slot(int32_t* keys, int32_t key) {
+    const unsigned h = ((unsigned)key * 2654435761u) >> 25;  // 7 bits
+    for (int probe = 0; probe < AGG_SLOTS; ++probe) {
+        const int sl = (int)((h + (unsigned)probe) & (AGG_SLOTS - 1));
+        const int32_t prev = atomicCAS(&keys[sl], -1, key);
+        if (prev == -1 || prev == key) return sl;
+    }
+    return -1;
 }
 
-// One wavefront per tile: lane c holds the count of cell c of the tile.
-__global__ void __launch_bounds__(64) k_tile_rounds(const int32_t* __restrict__ count, int64_t ntiles, int rcap,
-                                                    int32_t* __restrict__ T, uint64_t* __restrict__ M,
-                                                    int32_t* __restrict__ tile_total, int32_t* __restrict__ ovf) {
-    const int64_t tile = blockIdx.x;
-    if (tile >= ntiles) return;
-    const int lane = threadIdx.x;
-    const int cnt = count[tile * TILE_CELLS + lane];
-    int tot = cnt, mx = cnt;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        tot += __shfl_xor(tot, o, 64);
-        int other = __shfl_xor(mx, o, 64);
-        mx = other > mx ? other : mx;
+__global__ void __launch_bounds__(256) k_tile_count(KeyGeom G, const int32_t* __restrict__ cell, int64_t n,
+                                                    int32_t* __restrict__ count) {
+    __shared__ int32_t keys[AGG_SLOTS];
+    __shared__ int32_t cnt[AGG_SLOTS];
+    for (int i = threadIdx.x; i < AGG_SLOTS; i += 256) {
+        keys[i] = -1;
+        cnt[i] = 0;
     }
-    const int rmax = mx < rcap ? mx : rcap;
-    int32_t* Tt = T + tile * (int64_t)(rcap + 1);
-    uint64_t* Mt = M + tile * (int64_t)rcap;
-    int run = 0;
-    for (int r = 0; r < rmax; ++r) {
-        const uint64_t m = __ballot(cnt > r);
-        if (lane == 0) {
-            Tt[r] = run;
-            Mt[r] = m;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t base = (int64_t)blockIdx.x * AGG_BLOCK;
+    for (int k = 0; k < AGG_PER_THREAD; ++k) {
+        const int64_t p = base + k * 256 + threadIdx.x;
+        const bool active = p < n;
+        const int32_t tile = active ? key_cell(G, cell[p]) / TILE_CELLS : 0;
+        uint64_t todo = __ballot(active);
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const int32_t lk = __shfl(tile, leader, 64);
+            const uint64_t grp = __ballot(active && tile == lk) & todo;
+            if (lane == leader) {
+                const int sl = agg_slot(keys, lk);
+                if (sl >= 0)
+                    atomicAdd(&cnt[sl], (int32_t)__popcll(grp));
+                else
+                    atomicAdd(count + lk, (int32_t)__popcll(grp));
+            }
+            todo &= ~grp;
         }
-        run += __popcll(m);
     }
-    if (lane == 0) {
-        Tt[rcap] = run;  // start of the overflow segment
-        tile_total[tile] = tot;
-        ovf[tile] = 0;
-    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < AGG_SLOTS; i += 256)
+        if (keys[i] >= 0 && cnt[i] > 0) atomicAdd(count + keys[i], cnt[i]);
 }
 
 template <typename T>
@@ -132,46 +146,191 @@ struct ScatterArgs {
     T* pos_o[3];
     T* u_o[3];
     int64_t* id_o;
-    int32_t* cursor;        // FP64 form: bin starts (consumed); split form: per-cell rank cursors
-    const int32_t* tstart;  // split form: tile starts
-    const int32_t* rT;
-    const uint64_t* rM;
-    int32_t* ovf;
-    int rcap;
-    int split;  // 1: round-major order from the cell index; 0: cell order from the FP64 position
+    int32_t* cursor;  // FP64 form: cell-bin starts (consumed); split form: tile starts (consumed)
 };
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_scatter(ScatterArgs<T> A) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= A.n) return;
-    int32_t dst;
-    int32_t c = 0;
-    if (A.split) {
-        c = A.cell[p];
-        const int32_t key = key_cell(A.G, c);
-        const int32_t tile = key / TILE_CELLS;
-        const int lc = key - tile * TILE_CELLS;
-        const int32_t r = atomicAdd(A.cursor + key, 1);
-        const int32_t base = A.tstart[tile];
-        if (r < A.rcap) {
-            const uint64_t m = A.rM[(int64_t)tile * A.rcap + r];
-            const uint64_t below = lc == 0 ? 0ull : (m & ((1ull << lc) - 1ull));
-            dst = base + A.rT[(int64_t)tile * (A.rcap + 1) + r] + __popcll(below);
-        } else {
-            dst = base + A.rT[(int64_t)tile * (A.rcap + 1) + A.rcap] + atomicAdd(A.ovf + tile, 1);
-        }
-        A.cell_o[dst] = c;
-    } else {
-        const int32_t key = key_f64(A.G, (double)A.pos[0][p], (double)A.pos[1][p], (double)A.pos[2][p]);
-        dst = atomicAdd(A.cursor + key, 1);
-    }
+    const int32_t key = key_f64(A.G, (double)A.pos[0][p], (double)A.pos[1][p], (double)A.pos[2][p]);
+    const int32_t dst = atomicAdd(A.cursor + key, 1);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         A.pos_o[d][dst] = A.pos[d][p];
         A.u_o[d][dst] = A.u[d][p];
     }
     if (A.id) A.id_o[dst] = A.id[p];
+}
+
+// split form: bucket by tile with block-level aggregation (see k_tile_count); a wavefront's
+// particles bound for one tile get consecutive slots in their source order
+template <typename T>
+__global__ void __launch_bounds__(256) k_scatter_tiles(ScatterArgs<T> A) {
+    __shared__ int32_t keys[AGG_SLOTS];
+    __shared__ int32_t cnt[AGG_SLOTS];
+    __shared__ int32_t gbase[AGG_SLOTS];
+    for (int i = threadIdx.x; i < AGG_SLOTS; i += 256) {
+        keys[i] = -1;
+        cnt[i] = 0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t base = (int64_t)blockIdx.x * AGG_BLOCK;
+    int my_slot[AGG_PER_THREAD];
+    int32_t my_off[AGG_PER_THREAD];
+#pragma unroll
+    for (int k = 0; k < AGG_PER_THREAD; ++k) {
+        const int64_t p = base + k * 256 + threadIdx.x;
+        const bool active = p < A.n;
+        const int32_t tile = active ? key_cell(A.G, A.cell[p]) / TILE_CELLS : 0;
+        my_slot[k] = -2;
+        my_off[k] = 0;
+        uint64_t todo = __ballot(active);
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const int32_t lk = __shfl(tile, leader, 64);
+            const uint64_t grp = __ballot(active && tile == lk) & todo;
+            int sl = 0;
+            int32_t off = 0;
+            if (lane == leader) {
+                sl = agg_slot(keys, lk);
+                if (sl >= 0)
+                    off = atomicAdd(&cnt[sl], (int32_t)__popcll(grp));
+                else
+                    off = atomicAdd(A.cursor + lk, (int32_t)__popcll(grp));  // table full: direct
+            }
+            sl = __shfl(sl, leader, 64);
+            off = __shfl(off, leader, 64);
+            if ((grp >> lane) & 1ull) {
+                my_slot[k] = sl;
+                my_off[k] = off + (int32_t)__popcll(grp & ((1ull << lane) - 1ull));
+            }
+            todo &= ~grp;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < AGG_SLOTS; i += 256)
+        if (keys[i] >= 0) gbase[i] = atomicAdd(A.cursor + keys[i], cnt[i]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < AGG_PER_THREAD; ++k) {
+        const int64_t p = base + k * 256 + threadIdx.x;
+        if (p >= A.n || my_slot[k] == -2) continue;
+        const int32_t dst = my_slot[k] >= 0 ? gbase[my_slot[k]] + my_off[k] : my_off[k];
+        A.cell_o[dst] = A.cell[p];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            A.pos_o[d][dst] = A.pos[d][p];
+            A.u_o[d][dst] = A.u[d][p];
+        }
+        if (A.id) A.id_o[dst] = A.id[p];
+    }
+}
+
+// largest tile population (the fixed-point current's scale depends on it)
+__global__ void __launch_bounds__(256) k_tile_max(const int32_t* __restrict__ start, int64_t ntiles, int32_t* out) {
+    int m = 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x) {
+        const int c = start[t + 1] - start[t];
+        m = c > m ? c : m;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int other = __shfl_xor(m, o, 64);
+        m = other > m ? other : m;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+// Round-major rebuild of one tile (one workgroup per tile): ranks inside cells from LDS
+// atomics, the round table from ballots over the 64 cells, then a gather copy so the
+// writes are coalesced (the reads stay inside the tile's segment).
+constexpr int REORDER_RMAX = 1024;
+
+template <typename T>
+struct ReorderArgs {
+    KeyGeom G;
+    int64_t ntiles;
+    const int32_t* start;
+    const int32_t* cell;
+    const T* pos[3];
+    const T* u[3];
+    const int64_t* id;
+    int32_t* cell_o;
+    T* pos_o[3];
+    T* u_o[3];
+    int64_t* id_o;
+    int32_t* rank;  // scratch, one per particle
+    int32_t* perm;  // scratch, one per particle
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_tile_reorder(ReorderArgs<T> A) {
+    __shared__ int32_t cnt[TILE_CELLS];
+    __shared__ int32_t Tr[REORDER_RMAX + 1];
+    __shared__ uint64_t Mr[REORDER_RMAX];
+    __shared__ int32_t ovf;
+    const int64_t tile = blockIdx.x;
+    if (tile >= A.ntiles) return;
+    const int32_t s = A.start[tile], e = A.start[tile + 1];
+    if (threadIdx.x < TILE_CELLS) cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) ovf = 0;
+    __syncthreads();
+    for (int32_t i = s + threadIdx.x; i < e; i += 256) {
+        const int32_t lc = key_cell(A.G, A.cell[i]) % TILE_CELLS;
+        int32_t r = atomicAdd(&cnt[lc], 1);
+        r = r < REORDER_RMAX ? r : REORDER_RMAX;
+        A.rank[i] = (lc << 24) | r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const int c = cnt[lane];
+        int mx = c;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int other = __shfl_xor(mx, o, 64);
+            mx = other > mx ? other : mx;
+        }
+        const int rmax = mx < REORDER_RMAX ? mx : REORDER_RMAX;
+        int run = 0;
+        for (int r = 0; r < rmax; ++r) {
+            const uint64_t m = __ballot(c > r);
+            if (lane == 0) {
+                Tr[r] = run;
+                Mr[r] = m;
+            }
+            run += (int)__popcll(m);
+        }
+        if (lane == 0) Tr[REORDER_RMAX] = run;
+    }
+    __syncthreads();
+    for (int32_t i = s + threadIdx.x; i < e; i += 256) {
+        const int32_t rk = A.rank[i];
+        const int lc = rk >> 24;
+        const int r = rk & 0xFFFFFF;
+        int32_t pos;
+        if (r < REORDER_RMAX) {
+            const uint64_t m = Mr[r];
+            pos = Tr[r] + (int32_t)__popcll(lc == 0 ? 0ull : (m & ((1ull << lc) - 1ull)));
+        } else {
+            pos = Tr[REORDER_RMAX] + atomicAdd(&ovf, 1);
+        }
+        A.perm[s + pos] = i;
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int32_t j = s + threadIdx.x; j < e; j += 256) {
+        const int32_t i = A.perm[j];
+        A.cell_o[j] = A.cell[i];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            A.pos_o[d][j] = A.pos[d][i];
+            A.u_o[d][j] = A.u[d][i];
+        }
+        if (A.id) A.id_o[j] = A.id[i];
+    }
 }
 
 // ---- exclusive scan of int32, in place ------------------------------------------------
@@ -252,38 +411,51 @@ static unsigned grid_for(int64_t n, int bs, int64_t cap = 65535) {
     return (unsigned)(g < 1 ? 1 : g);
 }
 
+static void swap_buffers(pp_particles& c) {
+    int32_t* tc = c.cell;
+    c.cell = c.cell_alt;
+    c.cell_alt = tc;
+    int64_t* ti = c.id;
+    c.id = c.id_alt;
+    c.id_alt = ti;
+    for (int d = 0; d < 3; ++d) {
+        void* tp = c.pos[d];
+        c.pos[d] = c.pos_alt[d];
+        c.pos_alt[d] = tp;
+        void* tu = c.u[d];
+        c.u[d] = c.u_alt[d];
+        c.u_alt[d] = tu;
+    }
+}
+
 template <typename T>
-static hipError_t sort_species(pp_run* r, int s) {
+static hipError_t sort_species(pp_run* r, int s, bool reorder) {
     Species& S = r->sp[s];
     const KeyGeom G = key_geom(r);
     const int64_t nbins = r->g.nbins;
     const int64_t ntiles = r->g.ntiles;
     const bool split = r->p.precision == PP_PREC_FP32_SPLIT;
     const int bs = 256;
-    int32_t* count = split ? r->sort_count : S.offsets;
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nbins + 1, bs)), dim3(bs), 0, r->stream, count, split ? nbins : nbins + 1, 0);
+    const int64_t nkeys = split ? ntiles : nbins;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nkeys + 1, bs)), dim3(bs), 0, r->stream, S.offsets, nkeys + 1, 0);
     if (S.n > 0) {
         const unsigned pg = (unsigned)((S.n + bs - 1) / bs);
         if (split)
-            hipLaunchKernelGGL(k_hist_cell, dim3(pg), dim3(bs), 0, r->stream, G, (const int32_t*)S.cur.cell, S.n, count);
+            hipLaunchKernelGGL(k_tile_count, dim3((unsigned)((S.n + AGG_BLOCK - 1) / AGG_BLOCK)), dim3(256), 0,
+                               r->stream, G, (const int32_t*)S.cur.cell, S.n, S.offsets);
         else
             hipLaunchKernelGGL(k_hist_f64, dim3(pg), dim3(bs), 0, r->stream, G, (const double*)S.cur.pos[0],
-                               (const double*)S.cur.pos[1], (const double*)S.cur.pos[2], S.n, count);
+                               (const double*)S.cur.pos[1], (const double*)S.cur.pos[2], S.n, S.offsets);
     }
+    scan_inplace(S.offsets, nkeys + 1, r->scan_tmp, r->stream);
     if (split) {
-        // per-tile round tables and totals; then tile starts
-        hipLaunchKernelGGL(k_tile_rounds, dim3((unsigned)ntiles), dim3(64), 0, r->stream, (const int32_t*)count, ntiles,
-                           r->rcap, r->round_T, r->round_M, S.offsets, r->tile_ovf);
-        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, r->stream, S.offsets + ntiles, (int64_t)1, 0);
-        scan_inplace(S.offsets, ntiles + 1, r->scan_tmp, r->stream);
-        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nbins, bs)), dim3(bs), 0, r->stream, r->sort_cursor, nbins, 0);
-    } else {
-        scan_inplace(S.offsets, nbins + 1, r->scan_tmp, r->stream);
-        if (S.n > 0)
-            hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(nbins, bs)), dim3(bs), 0, r->stream, r->sort_cursor,
-                               (const int32_t*)S.offsets, nbins);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, r->stream, r->tile_max + s, (int64_t)1, 0);
+        hipLaunchKernelGGL(k_tile_max, dim3(grid_for(ntiles, bs, 1024)), dim3(bs), 0, r->stream,
+                           (const int32_t*)S.offsets, ntiles, r->tile_max + s);
     }
     if (S.n > 0) {
+        hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(nkeys, bs)), dim3(bs), 0, r->stream, r->sort_cursor,
+                           (const int32_t*)S.offsets, nkeys);
         ScatterArgs<T> A;
         A.G = G;
         A.n = S.n;
@@ -298,37 +470,40 @@ static hipError_t sort_species(pp_run* r, int s) {
             A.u_o[d] = (T*)S.cur.u_alt[d];
         }
         A.cursor = r->sort_cursor;
-        A.tstart = S.offsets;
-        A.rT = r->round_T;
-        A.rM = r->round_M;
-        A.ovf = r->tile_ovf;
-        A.rcap = r->rcap;
-        A.split = split ? 1 : 0;
-        hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((S.n + bs - 1) / bs)), dim3(bs), 0, r->stream, A);
-        // swap roles of the two buffers
-        pp_particles& c = S.cur;
-        int32_t* tc = c.cell;
-        c.cell = c.cell_alt;
-        c.cell_alt = tc;
-        int64_t* ti = c.id;
-        c.id = c.id_alt;
-        c.id_alt = ti;
-        for (int d = 0; d < 3; ++d) {
-            void* tp = c.pos[d];
-            c.pos[d] = c.pos_alt[d];
-            c.pos_alt[d] = tp;
-            void* tu = c.u[d];
-            c.u[d] = c.u_alt[d];
-            c.u_alt[d] = tu;
+        if (split)
+            hipLaunchKernelGGL(k_scatter_tiles<T>, dim3((unsigned)((S.n + AGG_BLOCK - 1) / AGG_BLOCK)), dim3(256), 0,
+                               r->stream, A);
+        else
+            hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((S.n + bs - 1) / bs)), dim3(bs), 0, r->stream, A);
+        swap_buffers(S.cur);
+        if (split && reorder) {
+            ReorderArgs<T> B;
+            B.G = G;
+            B.ntiles = ntiles;
+            B.start = S.offsets;
+            B.cell = S.cur.cell;
+            B.id = S.cur.id;
+            B.cell_o = S.cur.cell_alt;
+            B.id_o = S.cur.id ? S.cur.id_alt : nullptr;
+            for (int d = 0; d < 3; ++d) {
+                B.pos[d] = (const T*)S.cur.pos[d];
+                B.u[d] = (const T*)S.cur.u[d];
+                B.pos_o[d] = (T*)S.cur.pos_alt[d];
+                B.u_o[d] = (T*)S.cur.u_alt[d];
+            }
+            B.rank = r->sort_scratch;
+            B.perm = r->sort_scratch + r->sort_scratch_n;
+            hipLaunchKernelGGL(k_tile_reorder<T>, dim3((unsigned)ntiles), dim3(256), 0, r->stream, B);
+            swap_buffers(S.cur);
         }
     }
     S.sorted = true;
     return hipGetLastError();
 }
 
-hipError_t launch_sort(pp_run* r, int s) {
-    if (r->p.precision == PP_PREC_FP32_SPLIT) return sort_species<float>(r, s);
-    return sort_species<double>(r, s);
+hipError_t launch_sort(pp_run* r, int s, bool reorder) {
+    if (r->p.precision == PP_PREC_FP32_SPLIT) return sort_species<float>(r, s, reorder);
+    return sort_species<double>(r, s, false);
 }
 
 }  // namespace pp
