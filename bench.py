@@ -100,16 +100,54 @@ def cpu_baseline(n_sample=(16, 16, 16), ppc=32, steps=4):
 
 
 def flops_per_update(O=3):
-    """Algorithmic FP32 operations of one particle update in the tiled kernel's formulation
-    (FMA = 2): weights, factored gather, Vay push, move, Esirkepov current."""
-    n1 = O + 1
-    n2 = O + 2
-    weights = 3 * 2 * (4 * n1) + 3 * 2 * (4 * n1)  # gather sets (2/axis) + old/new current sets (2/axis)
+    """Algorithmic floating-point operations of one particle update (FMA = 2), counted from the
+    method as the tiled kernel formulates it: B-spline weight sets (centred and staggered at
+    the old position, centred at the new one; 3 axes; ~17 flops each for cubic), factored
+    gather of 6 components, Vay push, move, and per current component the weight changes,
+    prefix sum, the two factors of F, F itself and the (O+1)(O+2)^2 products."""
+    n1, n2 = O + 1, O + 2
+    weights = 9 * (17 if O == 3 else 9)
     gather = 6 * 2 * (n1 ** 3 + n1 ** 2 + n1)
-    push = 80
-    move = 3 * 4
-    esirkepov = 3 * (3 * n2 + n2 * n2 * 7 + n2 * n2 * n1 * 3)  # dS, F(b,e), prefix + scale
-    return weights + gather + push + move + esirkepov
+    push = 100
+    move = 12
+    per_comp = n2 + (n1 - 1) + 2 * n2 + 3 * n2 + 3 * n2 * n2 + 2 * n1 * n2 * n2
+    return weights + gather + push + move + 3 * per_comp
+
+
+def kernel_source_digest():
+    """Digest of the sources of the dominant kernel (so stored counter figures are only used
+    while the kernel they were taken on is unchanged)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("pp_gpd32.hip", "pp_device.hpp", "pp_internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1211_4575_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(particles):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, each divided by what the same counter reads per byte of a plain
+    copy of known size), or None when the summary is missing, for another workload, or was
+    taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "k_gpd32_pair_mj_256_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            vals[k.strip()] = v.strip()
+    try:
+        if vals.get("kernel_source_digest") != kernel_source_digest():
+            return None
+        if int(vals["particles"]) != particles:
+            return None
+        f = float(vals["fetch_kib_per_launch"]) * 1024.0 / (float(vals["copy_fetch_kib"]) * 1024.0 / float(vals["copy_bytes"]))
+        w = float(vals["write_kib_per_launch"]) * 1024.0 / (float(vals["copy_write_kib"]) * 1024.0 / float(vals["copy_bytes"]))
+        return f + w
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
 
 
 def main(argv=None):
@@ -122,6 +160,8 @@ def main(argv=None):
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
@@ -132,6 +172,17 @@ def main(argv=None):
 
     from paper_1211_4575_amd import inputs_device as ind
     from paper_1211_4575_amd import pp
+
+    if args.calib_copy_gib > 0:
+        nb = int(args.calib_copy_gib * (1 << 30))
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {nb} bytes")
+        del src, dst
+        torch.cuda.empty_cache()
 
     n = (args.grid, args.grid, args.grid)
     log(f"[bench] FP32 split: generating {n} x {args.ppc} ppc x 2 species on the device")
@@ -171,10 +222,13 @@ def main(argv=None):
     achieved_gbs = npart * bytes_per_update / (gpd_ms * 1e-3) / 1e9
     fl = flops_per_update(3)
     achieved_tf = npart * fl / (gpd_ms * 1e-3) / 1e12
+    traffic = measured_traffic(npart)
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved_tf / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-                "kernel": "k_gpd32<3>", "flop_per_update": fl, "hbm_gbs_algorithmic": round(achieved_gbs, 1),
-                "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "gpd_ms": round(gpd_ms, 3)}
+                "unit": "TFLOP/s", "frac": round(achieved_tf / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": traffic, "kernel": "k_gpd32<3>", "flop_per_update": fl,
+                "algorithmic_bytes_per_launch": npart * bytes_per_update,
+                "hbm_gbs_algorithmic": round(achieved_gbs, 1), "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                "gpd_ms": round(gpd_ms, 3)}
 
     cpu = None
     if not args.no_cpu:

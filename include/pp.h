@@ -74,7 +74,7 @@ enum {
 };
 
 /* Run parameters (Sec. II weight order, Sec. III.A pusher, Sec. III.B alpha and
- * difference order, Sec. IV current scheme).  Host validation rejects:
+ * difference order, Sec. III.C current scheme).  Host validation rejects:
  * shape_order not in {2,3} (TSC, PCS), field_order not in {2,4,6}, alpha outside
  * [1/2, 1), any n < 1, d <= 0, dt <= 0, c <= 0, eps0 <= 0, non-finite values, and
  * c*dt >= min(d) (PP_E_CFL: the fixed O+2 node current stencil needs every
@@ -132,7 +132,7 @@ typedef struct pp_diag {
     double relax_resid;/* estimated relative error bound of the last B relaxation    */
     int32_t relax_iters;
     int32_t flags;     /* PP_FLAG_* bits accumulated since the last pp_diagnostics    */
-    int64_t step;      /* number of completed pp_field_step calls                    */
+    int64_t step;      /* number of completed pp_gather_push_deposit calls          */
 } pp_diag;
 
 typedef struct pp_run pp_run;
@@ -152,7 +152,7 @@ pp_status pp_init_species(pp_run* run, int32_t s, double q, double m, double w, 
 /* Steps 1-3 of Sec. III for every registered species: gather E^n and B^n to each
  * particle with the B-spline weights of the run's order (eq. "pfields"), push
  * u^{n-1/2} -> u^{n+1/2} (Vay or Boris, Sec. III.A), move x^{n+1} = x^n +
- * dt u/gamma, and deposit the charge-conserving current (Sec. IV: Esirkepov's
+ * dt u/gamma, and deposit the charge-conserving current (Sec. III.C: Esirkepov's
  * split with per-particle prefix sums, then for field order 4/6 the line solve of
  * eqs. "jj6d"/"penta").  J is overwritten with J^{n+1}.  FP32_SPLIT requires the
  * particles to be sorted since their last push (PP_E_STATE otherwise). */

@@ -189,7 +189,7 @@ void orc_push(int pusher, double q, double m, double dt, double c, const double 
 }
 
 /* ------------------------------------------------------------------ */
-/* Charge-conserving current of one particle moving X0 -> X1, Sec. IV:  */
+/* Charge-conserving current of one particle moving X0 -> X1, Sec. III.C:*/
 /* Esirkepov's directional split of the charge change (the paper cites  */
 /* Esirkepov 2001 and prints no formula), then the per-particle prefix  */
 /* sum valid for the second-order operator.  With S0, S1 the 1D weights */
@@ -535,7 +535,7 @@ int orc_field_step(const orc_params* P, double* E, double* B, const double* J, d
 }
 
 /* ------------------------------------------------------------------ */
-/* High-order charge-conserving current, Sec. IV (eqs. "jj6d",          */
+/* High-order charge-conserving current, Sec. III.C (eqs. "jj6d",        */
 /* "penta"): per grid line along d, the second-order result J2 is       */
 /* turned into its differences dJ2(i) = J2(i+1/2) - J2(i-1/2); the      */
 /* banded system T dJ = dJ2 is solved on the line, with T the stencil   */

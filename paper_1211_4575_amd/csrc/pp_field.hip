@@ -1,5 +1,5 @@
 // Field kernels: the implicit B / explicit E step (Sec. III.B, eqs. "bnplus1",
-// "enplus1", "EllipticB") and the high-order current line solve (Sec. IV, eqs.
+// "enplus1", "EllipticB") and the high-order current line solve (Sec. III.C, eqs.
 // "jj6d", "penta").  Mesh arrays are FP64, x fastest, periodic.
 #include "pp_device.hpp"
 #include "pp_internal.hpp"

@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(256) k_gpd64(Gpd64Args A) {
         return;
     }
 
-    // Esirkepov current (Sec. IV) on the common window of O+2 centred nodes per axis
+    // Esirkepov current (Sec. III.C) on the common window of O+2 centred nodes per axis
     double S0[3][O + 2], DS[3][O + 2];
     int base[3];
 #pragma unroll

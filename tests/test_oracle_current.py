@@ -1,4 +1,4 @@
-"""Pins of the oracle's charge-conserving current (paper Sec. IV: eqs. "cc1", "jj3", "jj6d",
+"""Pins of the oracle's charge-conserving current (paper Sec. III.C: eqs. "cc1", "jj3", "jj6d",
 "penta").  Pins: the discrete continuity equation with the oracle's independent charge deposit
 (eq. "rho2"), the total current of a moving charge, the unique 1D charge-conserving current, the
 high-order line solve's defining property (high-order divergence of J_O equals the second-order

@@ -1,5 +1,5 @@
 """Whole-run pins of the oracle: invariants the paper states for the complete step (Gauss's law
-kept by the charge-conserving current, Sec. IV and its closing remarks on FP64 runs; div B kept by
+kept by the charge-conserving current, Sec. III.C and its closing remarks on FP64 runs; div B kept by
 the staggered curl, Sec. III.B), diagnostics against closed forms, the loaders' properties, and
 the linear growth rate of the symmetric relativistic two-stream instability."""
 import math
