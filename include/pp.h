@@ -185,6 +185,37 @@ pp_status pp_timing_read(pp_run* run, double* ms_total, int64_t* launches);
 /* Release internal scratch.  Caller memory is untouched. */
 pp_status pp_destroy(pp_run* run);
 
+/* ---- continuous batching of many runs ------------------------------------------------
+ * A batch steps a changing set of runs together: every phase of a time step (the particle
+ * kernel, the line solve, the sort of each species slot, the field step) is one launch over
+ * all member runs.  Runs are created, loaded and destroyed with the calls above and join or
+ * leave the batch between steps; their memory stays theirs.  Members must use
+ * PP_PREC_FP32_SPLIT, grids with at least 4 cells per axis (4x4x4 tiles), the batch's
+ * stream and one common shape order.  A member's results equal those of stepping it alone
+ * (the current is an exact integer sum; every other reduction has a fixed order).
+ * Calls that overlap on one batch race; one host thread per batch. */
+typedef struct pp_batch pp_batch;
+
+/* Create an empty batch for at most max_runs members on a HIP stream. */
+pp_status pp_batch_create(int32_t max_runs, void* hip_stream, pp_batch** out);
+
+/* Add a run (PP_E_ARG if it cannot be batched, PP_E_CAPACITY if full, PP_E_STATE if it is
+ * already a member or has unsorted species). */
+pp_status pp_batch_add(pp_batch* batch, pp_run* run);
+
+/* Remove a run (PP_E_STATE if it is not a member).  The run itself stays valid. */
+pp_status pp_batch_remove(pp_batch* batch, pp_run* run);
+
+/* Number of member runs. */
+pp_status pp_batch_size(const pp_batch* batch, int32_t* n);
+
+/* One whole time step of every member (Sec. III order: particles, sort, fields), enqueued
+ * on the batch's stream.  Each member's step counter advances by one. */
+pp_status pp_batch_step(pp_batch* batch);
+
+/* Release the batch's own buffers (members are untouched). */
+pp_status pp_batch_destroy(pp_batch* batch);
+
 /* Static description of a status code. */
 const char* pp_status_str(pp_status st);
 

@@ -38,6 +38,15 @@ int ppi_pair_maxwell_juttner(uint64_t seed, const int32_t n[3], int64_t start, i
                              int32_t split, int32_t* const cell[2], void* const off[2][3], void* const u[2][3],
                              void* hip_stream);
 
+/* Two counter-streaming electron beams on a quiet lattice (both at the same points):
+ * n[3] cells, k[3] lattice points per cell per axis, beam 0 drifting at +v_beam along x and
+ * beam 1 at -v_beam (three-velocities), thermal spread uth per component of the proper
+ * velocity; workload id wl selects the random streams (as in inputs.two_stream).  Particle
+ * p = ix + Lx*(iy + Ly*iz) over the fine lattice.  Output layout as above. */
+int ppi_two_stream_lattice(uint64_t seed, int32_t wl, const int32_t n[3], const int32_t k[3], double v_beam,
+                           double uth, int32_t split, int32_t* const cell[2], void* const off[2][3],
+                           void* const u[2][3], void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,22 +51,16 @@ static pp_status validate(const pp_params* p) {
     return PP_OK;
 }
 
-// Tile shape: powers of two with product 64 where the box allows, growing the axis with
-// the most cells per tile first.
+// Tile shape: powers of two with product TILE_CELLS where the box allows, as close to a cube
+// as the box allows (the LDS halo per cell is smallest for a cube): double the shortest tile
+// side that is still below the box side.  Boxes at least 4 cells on every side get 4x4x4
+// tiles, flat boxes 8x8x1.
 static void choose_tiles(const int n[3], int t[3]) {
     t[0] = t[1] = t[2] = 1;
-    for (;;) {
-        if (t[0] * t[1] * t[2] >= TILE_CELLS) break;
+    while (t[0] * t[1] * t[2] < TILE_CELLS) {
         int best = -1;
-        double br = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            if (t[d] >= n[d]) continue;
-            double ratio = (double)n[d] / t[d];
-            if (ratio > br + 1e-12) {
-                br = ratio;
-                best = d;
-            }
-        }
+        for (int d = 0; d < 3; ++d)
+            if (t[d] < n[d] && (best < 0 || t[d] < t[best])) best = d;
         if (best < 0) break;
         t[best] *= 2;
     }

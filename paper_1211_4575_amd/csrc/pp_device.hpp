@@ -131,6 +131,21 @@ __device__ __forceinline__ void push_boris(T h, T ic, const V3<T>& E, const V3<T
 }
 
 __device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+// Segment of a batched launch: the largest r in [0, n) with prefix[r] <= b < prefix[r + 1]
+// (prefix has n + 1 non-decreasing entries), or -1 when b is beyond the last segment.
+__device__ __forceinline__ int find_segment(const int64_t* __restrict__ prefix, int n, int64_t b) {
+    if (n <= 0 || b < prefix[0] || b >= prefix[n]) return -1;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
 __device__ __forceinline__ void atomic_or_flag(int32_t* p, int32_t v) { atomicOr(p, v); }
 
 }  // namespace pp

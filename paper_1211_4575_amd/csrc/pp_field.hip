@@ -63,58 +63,105 @@ __device__ __forceinline__ double lap(const FieldGeom& G, const double* __restri
     return s;
 }
 
-// rhs = B + alpha beta s lap B - dt curl+ E + alpha c^2 mu0 dt^2 curl+ J     (s = c^2 dt^2)
-__global__ void __launch_bounds__(256) k_field_rhs(FieldGeom G, const double* __restrict__ E, const double* __restrict__ B,
-                                                   const double* __restrict__ J, double* __restrict__ R, double cab,
-                                                   double dt, double cj) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= G.nc) return;
-    const int i = (int)(q % G.n[0]);
-    const int j = (int)((q / G.n[0]) % G.n[1]);
-    const int k = (int)(q / ((int64_t)G.n[0] * G.n[1]));
+// Everything one field step of one run needs (the single-run launches pass it by value,
+// the batched launches read a table of them).
+struct FieldDesc {
+    FieldGeom G;
+    double* E;
+    double* B;
+    const double* J;
+    double* Bn;  // copy of B^n
+    double* Bw;  // relaxation partner
+    double* R;   // right-hand side
+    double cab, dt, cj;         // alpha beta s, dt, alpha c^2 mu0 dt^2   (s = c^2 dt^2)
+    double al2s, inv_diag;      // alpha^2 s, 1 / diagonal
+    double al, be, c2dt, mu0;   // alpha, beta, c^2 dt, mu0
+    int sweeps;
+};
+
+__device__ __forceinline__ void cell_ijk(const FieldGeom& G, int64_t q, int& i, int& j, int& k) {
+    i = (int)(q % G.n[0]);
+    j = (int)((q / G.n[0]) % G.n[1]);
+    k = (int)(q / ((int64_t)G.n[0] * G.n[1]));
+}
+
+__device__ __forceinline__ void copy_body(const FieldDesc& D, int64_t q) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) D.Bn[c * D.G.nc + q] = D.B[c * D.G.nc + q];
+}
+
+// rhs = B + alpha beta s lap B - dt curl+ E + alpha c^2 mu0 dt^2 curl+ J   (B = B^n from Bn)
+__device__ __forceinline__ void rhs_body(const FieldDesc& D, int64_t q) {
+    const FieldGeom& G = D.G;
+    int i, j, k;
+    cell_ijk(G, q, i, j, k);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int d1 = (c + 1) % 3, d2 = (c + 2) % 3;
-        const double* Bc = B + c * G.nc;
-        double curlE = dup(G, E + d2 * G.nc, d1, i, j, k) - dup(G, E + d1 * G.nc, d2, i, j, k);
-        double curlJ = dup(G, J + d2 * G.nc, d1, i, j, k) - dup(G, J + d1 * G.nc, d2, i, j, k);
-        R[c * G.nc + q] = Bc[q] + cab * lap(G, Bc, i, j, k) - dt * curlE + cj * curlJ;
+        const double* Bc = D.Bn + c * G.nc;
+        double curlE = dup(G, D.E + d2 * G.nc, d1, i, j, k) - dup(G, D.E + d1 * G.nc, d2, i, j, k);
+        double curlJ = dup(G, D.J + d2 * G.nc, d1, i, j, k) - dup(G, D.J + d1 * G.nc, d2, i, j, k);
+        D.R[c * G.nc + q] = Bc[q] + D.cab * lap(G, Bc, i, j, k) - D.dt * curlE + D.cj * curlJ;
     }
 }
 
-// one Jacobi sweep of (1 - al2s lap) x = rhs:  out = in + (rhs - in + al2s lap in) / diag
-__global__ void __launch_bounds__(256) k_jacobi(FieldGeom G, const double* __restrict__ in, const double* __restrict__ R,
-                                                double* __restrict__ out, double al2s, double inv_diag) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= G.nc) return;
-    const int i = (int)(q % G.n[0]);
-    const int j = (int)((q / G.n[0]) % G.n[1]);
-    const int k = (int)(q / ((int64_t)G.n[0] * G.n[1]));
+// sweep k (1-based) of Jacobi on (1 - al2s lap) x = rhs:  out = in + (rhs - in + al2s lap in) / diag.
+// The sweeps alternate between B and Bw so that the last one writes B.
+__device__ __forceinline__ void jacobi_body(const FieldDesc& D, int64_t q, int k) {
+    const FieldGeom& G = D.G;
+    const int m = D.sweeps;
+    const double* in = k == 1 ? D.Bn : (((m - k + 1) % 2 == 0) ? D.B : D.Bw);
+    double* out = ((m - k) % 2 == 0) ? D.B : D.Bw;
+    int i, j, kk;
+    cell_ijk(G, q, i, j, kk);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double* x = in + c * G.nc;
         double xq = x[q];
-        double Ax = xq - al2s * lap(G, x, i, j, k);
-        out[c * G.nc + q] = xq + (R[c * G.nc + q] - Ax) * inv_diag;
+        double Ax = xq - D.al2s * lap(G, x, i, j, kk);
+        out[c * G.nc + q] = xq + (D.R[c * G.nc + q] - Ax) * D.inv_diag;
     }
 }
 
 // E += c^2 dt (curl- (alpha B' + beta B) - mu0 J)
-__global__ void __launch_bounds__(256) k_update_E(FieldGeom G, double* __restrict__ E, const double* __restrict__ Bnew,
-                                                  const double* __restrict__ Bold, const double* __restrict__ J, double al,
-                                                  double be, double c2dt, double mu0) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= G.nc) return;
-    const int i = (int)(q % G.n[0]);
-    const int j = (int)((q / G.n[0]) % G.n[1]);
-    const int k = (int)(q / ((int64_t)G.n[0] * G.n[1]));
+__device__ __forceinline__ void update_E_body(const FieldDesc& D, int64_t q) {
+    const FieldGeom& G = D.G;
+    int i, j, k;
+    cell_ijk(G, q, i, j, k);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int d1 = (c + 1) % 3, d2 = (c + 2) % 3;
-        double cn = ddn(G, Bnew + d2 * G.nc, d1, i, j, k) - ddn(G, Bnew + d1 * G.nc, d2, i, j, k);
-        double co = ddn(G, Bold + d2 * G.nc, d1, i, j, k) - ddn(G, Bold + d1 * G.nc, d2, i, j, k);
-        E[c * G.nc + q] += c2dt * (al * cn + be * co - mu0 * J[c * G.nc + q]);
+        double cn = ddn(G, D.B + d2 * G.nc, d1, i, j, k) - ddn(G, D.B + d1 * G.nc, d2, i, j, k);
+        double co = ddn(G, D.Bn + d2 * G.nc, d1, i, j, k) - ddn(G, D.Bn + d1 * G.nc, d2, i, j, k);
+        D.E[c * G.nc + q] += D.c2dt * (D.al * cn + D.be * co - D.mu0 * D.J[c * G.nc + q]);
     }
+}
+
+enum FieldPhase { PH_COPY = 0, PH_RHS = 1, PH_JACOBI = 2, PH_UPDATE_E = 3 };
+
+__device__ __forceinline__ void field_phase(const FieldDesc& D, int64_t q, int phase, int k) {
+    if (q >= D.G.nc) return;
+    if (phase == PH_COPY)
+        copy_body(D, q);
+    else if (phase == PH_RHS)
+        rhs_body(D, q);
+    else if (phase == PH_JACOBI) {
+        if (k <= D.sweeps) jacobi_body(D, q, k);
+    } else
+        update_E_body(D, q);
+}
+
+__global__ void __launch_bounds__(256) k_field(FieldDesc D, int phase, int k) {
+    field_phase(D, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, phase, k);
+}
+
+// batched: block b belongs to run r with prefix[r] <= b < prefix[r+1] (prefix in blocks)
+__global__ void __launch_bounds__(256) k_field_batch(const FieldDesc* __restrict__ T, const int64_t* __restrict__ prefix,
+                                                     int nruns, int phase, int k) {
+    const int64_t b = blockIdx.x;
+    const int r = find_segment(prefix, nruns, b);
+    if (r < 0) return;
+    field_phase(T[r], (b - prefix[r]) * blockDim.x + threadIdx.x, phase, k);
 }
 
 static void fd_coeffs(int order, double a[3]) {
@@ -201,28 +248,54 @@ void field_setup(pp_run* r) {
     r->jac_bound = rho > 0.0 ? pow(rho, sweeps) : 0.0;
 }
 
-hipError_t launch_field_step(pp_run* r) {
-    const FieldGeom G = make_geom(r);
-    const int64_t nc = G.nc;
-    const int bs = 256;
-    const dim3 grid((unsigned)((nc + bs - 1) / bs));
+void field_desc(const pp_run* r, FieldDesc* D) {
+    D->G = make_geom(r);
     const double c2 = r->p.c * r->p.c, dt = r->p.dt, s = c2 * dt * dt;
     const double al = r->p.alpha, be = 1.0 - al;
     const double mu0 = 1.0 / (r->p.eps0 * c2);
-    hipError_t e = hipMemcpyAsync(r->Bn, r->mesh.B, 3 * nc * sizeof(double), hipMemcpyDeviceToDevice, r->stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_field_rhs, grid, dim3(bs), 0, r->stream, G, (const double*)r->mesh.E, (const double*)r->Bn,
-                       (const double*)r->mesh.J, r->R, al * be * s, dt, al * c2 * mu0 * dt * dt);
-    const int m = r->jac_sweeps;
-    const double* in = r->Bn;
-    for (int k = 1; k <= m; ++k) {
-        double* out = ((m - k) % 2 == 0) ? r->mesh.B : r->Bw;
-        hipLaunchKernelGGL(k_jacobi, grid, dim3(bs), 0, r->stream, G, in, (const double*)r->R, out, al * al * s,
-                           1.0 / r->diagA);
-        in = out;
-    }
-    hipLaunchKernelGGL(k_update_E, grid, dim3(bs), 0, r->stream, G, r->mesh.E, (const double*)r->mesh.B,
-                       (const double*)r->Bn, (const double*)r->mesh.J, al, be, c2 * dt, mu0);
+    D->E = r->mesh.E;
+    D->B = r->mesh.B;
+    D->J = r->mesh.J;
+    D->Bn = r->Bn;
+    D->Bw = r->Bw;
+    D->R = r->R;
+    D->cab = al * be * s;
+    D->dt = dt;
+    D->cj = al * c2 * mu0 * dt * dt;
+    D->al2s = al * al * s;
+    D->inv_diag = 1.0 / r->diagA;
+    D->al = al;
+    D->be = be;
+    D->c2dt = c2 * dt;
+    D->mu0 = mu0;
+    D->sweeps = r->jac_sweeps;
+}
+
+size_t field_desc_size() { return sizeof(FieldDesc); }
+
+hipError_t launch_field_step(pp_run* r) {
+    FieldDesc D;
+    field_desc(r, &D);
+    const int bs = 256;
+    const dim3 grid((unsigned)((D.G.nc + bs - 1) / bs));
+    hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_COPY, 0);
+    hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_RHS, 0);
+    for (int k = 1; k <= D.sweeps; ++k) hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_JACOBI, k);
+    hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_UPDATE_E, 0);
+    return hipGetLastError();
+}
+
+// Batched field step over n runs: table (device) of FieldDesc, prefix (device) of blocks.
+hipError_t launch_field_step_batch(const void* table, const int64_t* prefix, int n, int64_t total_blocks,
+                                   int max_sweeps, hipStream_t st) {
+    if (n == 0 || total_blocks == 0) return hipSuccess;
+    const FieldDesc* T = (const FieldDesc*)table;
+    const dim3 grid((unsigned)total_blocks);
+    hipLaunchKernelGGL(k_field_batch, grid, dim3(256), 0, st, T, prefix, n, (int)PH_COPY, 0);
+    hipLaunchKernelGGL(k_field_batch, grid, dim3(256), 0, st, T, prefix, n, (int)PH_RHS, 0);
+    for (int k = 1; k <= max_sweeps; ++k)
+        hipLaunchKernelGGL(k_field_batch, grid, dim3(256), 0, st, T, prefix, n, (int)PH_JACOBI, k);
+    hipLaunchKernelGGL(k_field_batch, grid, dim3(256), 0, st, T, prefix, n, (int)PH_UPDATE_E, 0);
     return hipGetLastError();
 }
 
@@ -238,16 +311,17 @@ struct LineArgs {
     int64_t nc;
     const double* coef[3];
     int len[3], off[3];
+    const double* J2;
+    double* J;
 };
 
-__global__ void __launch_bounds__(256) k_line_solve(LineArgs A, const double* __restrict__ J2, double* __restrict__ J) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void line_body(const LineArgs& A, int64_t q) {
     if (q >= A.nc) return;
     const int ijk[3] = {(int)(q % A.n[0]), (int)((q / A.n[0]) % A.n[1]), (int)(q / ((int64_t)A.n[0] * A.n[1]))};
     const int64_t stride[3] = {1, A.n[0], (int64_t)A.n[0] * A.n[1]};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double* src = J2 + c * A.nc;
+        const double* src = A.J2 + c * A.nc;
         const int N = A.n[c];
         const int64_t rowbase = q - (int64_t)ijk[c] * stride[c];
         double s = 0.0;
@@ -256,8 +330,20 @@ __global__ void __launch_bounds__(256) k_line_solve(LineArgs A, const double* __
             s += A.coef[c][jj] * src[rowbase + (int64_t)idx * stride[c]];
             if (++idx == N) idx = 0;
         }
-        J[c * A.nc + q] = s;
+        A.J[c * A.nc + q] = s;
     }
+}
+
+__global__ void __launch_bounds__(256) k_line_solve(LineArgs A) {
+    line_body(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_line_solve_batch(const LineArgs* __restrict__ T, const int64_t* __restrict__ prefix,
+                                                          int nruns) {
+    const int64_t b = blockIdx.x;
+    const int r = find_segment(prefix, nruns, b);
+    if (r < 0) return;
+    line_body(T[r], (b - prefix[r]) * blockDim.x + threadIdx.x);
 }
 
 // Host: coefficients of T^{-1} on a periodic line of N cells, by the discrete Fourier
@@ -296,17 +382,31 @@ int line_setup_axis(int order, int N, double* coef_host, int* off) {
     return 2 * Rr + 1;
 }
 
+void line_desc(const pp_run* r, const double* J2, double* J, LineArgs* A) {
+    for (int d = 0; d < 3; ++d) {
+        A->n[d] = r->p.n[d];
+        A->coef[d] = r->line[d].coef;
+        A->len[d] = r->line[d].len;
+        A->off[d] = r->line[d].off;
+    }
+    A->nc = r->g.ncell;
+    A->J2 = J2;
+    A->J = J;
+}
+
+size_t line_desc_size() { return sizeof(LineArgs); }
+
 hipError_t launch_line_solve(pp_run* r, const double* J2, double* J) {
     LineArgs A;
-    for (int d = 0; d < 3; ++d) {
-        A.n[d] = r->p.n[d];
-        A.coef[d] = r->line[d].coef;
-        A.len[d] = r->line[d].len;
-        A.off[d] = r->line[d].off;
-    }
-    A.nc = r->g.ncell;
+    line_desc(r, J2, J, &A);
     const int bs = 256;
-    hipLaunchKernelGGL(k_line_solve, dim3((unsigned)((A.nc + bs - 1) / bs)), dim3(bs), 0, r->stream, A, J2, J);
+    hipLaunchKernelGGL(k_line_solve, dim3((unsigned)((A.nc + bs - 1) / bs)), dim3(bs), 0, r->stream, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_solve_batch(const void* table, const int64_t* prefix, int n, int64_t total_blocks, hipStream_t st) {
+    if (n == 0 || total_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_line_solve_batch, dim3((unsigned)total_blocks), dim3(256), 0, st, (const LineArgs*)table, prefix, n);
     return hipGetLastError();
 }
 

@@ -167,15 +167,11 @@ __device__ __forceinline__ float gather_comp(const float* __restrict__ F, const 
     return acc;
 }
 
+// One tile of one run: the whole particle step of the tile's particles (the body shared by
+// the single-run kernel and the batched kernel, so both do identical arithmetic).
 template <int O, class TL>
-__global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
+__device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, unsigned char* lds_raw) {
     const TL L(A);
-    // XCD-aware tile order: consecutive workgroups go round-robin over the 8 XCDs, so give
-    // each XCD a contiguous run of tiles (neighbouring tiles share halos in that XCD's L2).
-    const int64_t b = blockIdx.x;
-    const int64_t tile = (b & 7) * (int64_t)A.per_xcd + (b >> 3);
-    if (tile >= A.ntiles) return;
     const int ti = (int)(tile % A.nt[0]);
     const int tj = (int)((tile / A.nt[0]) % A.nt[1]);
     const int tk = (int)(tile / ((int64_t)A.nt[0] * A.nt[1]));
@@ -396,28 +392,80 @@ __global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
     }
 }
 
-// J (FP64) = fixed-point accumulator * 2^-e
-__global__ void __launch_bounds__(256) k_fixed_to_f64(const long long* __restrict__ Jq, double* __restrict__ J,
-                                                      int64_t n, const double* __restrict__ scale) {
-    const double inv = 1.0 / *scale;  // exact: a power of two
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
-        J[q] = (double)Jq[q] * inv;
+template <int O, class TL>
+__global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    // XCD-aware tile order: consecutive workgroups go round-robin over the 8 XCDs, so give
+    // each XCD a contiguous run of tiles (neighbouring tiles share halos in that XCD's L2).
+    const int64_t b = blockIdx.x;
+    const int64_t tile = (b & 7) * (int64_t)A.per_xcd + (b >> 3);
+    if (tile >= A.ntiles) return;
+    gpd32_tile<O, TL>(A, tile, lds_raw);
 }
+
+// Batched: block b of the launch is tile b - prefix[r] of run r (prefix = running tile counts).
+template <int O, class TL>
+__global__ void __launch_bounds__(GPD32_BS) k_gpd32_batch(const Gpd32Args* __restrict__ table,
+                                                          const int64_t* __restrict__ prefix, int nruns) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int64_t b = blockIdx.x;
+    const int r = find_segment(prefix, nruns, b);
+    if (r < 0) return;
+    gpd32_tile<O, TL>(table[r], b - prefix[r], lds_raw);
+}
+
+// Fixed-point current bookkeeping of one run: scale, accumulator, FP64 target.
+struct FixedDesc {
+    const int32_t* tile_max;  // largest tile population per species slot
+    int e0;                   // host part of the exponent
+    double* scale;            // 2^e (device)
+    unsigned long long* Jq;   // accumulator, 3 * nc
+    double* J;                // FP64 current written from the accumulator
+    int64_t n3;
+};
 
 // 2^e with e = e0 - ceil(log2(N)), N the sum over species of the largest particle count of
 // any tile: then |one contribution| <= 2^(50 - ceil log2 N) and |a node's LDS sum| <= 2^50.
-__global__ void k_fixed_scale(const int32_t* __restrict__ tile_max, int nsp, int e0, double* scale) {
-    if (threadIdx.x != 0) return;
+__device__ __forceinline__ void fixed_scale_body(const FixedDesc& D) {
     long long nb = 0;
-    for (int s = 0; s < nsp; ++s) nb += tile_max[s];
+    for (int s = 0; s < PP_MAX_SPECIES; ++s) nb += D.tile_max[s];
     int lg = 0;
     while ((1ll << lg) < nb) ++lg;
-    *scale = ldexp(1.0, e0 - lg);
+    *D.scale = ldexp(1.0, D.e0 - lg);
 }
 
-__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
-        p[q] = 0ull;
+enum FixedPhase { FX_ZERO = 0, FX_TO_F64 = 1 };
+
+__device__ __forceinline__ void fixed_body(const FixedDesc& D, int64_t q, int phase) {
+    if (q >= D.n3) return;
+    if (phase == FX_ZERO) {
+        D.Jq[q] = 0ull;
+    } else {
+        const double inv = 1.0 / *D.scale;  // exact: a power of two
+        D.J[q] = (double)(long long)D.Jq[q] * inv;
+    }
+}
+
+__global__ void k_fixed_scale(FixedDesc D) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) fixed_scale_body(D);
+}
+
+__global__ void __launch_bounds__(256) k_fixed(FixedDesc D, int phase) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < D.n3; q += (int64_t)gridDim.x * blockDim.x)
+        fixed_body(D, q, phase);
+}
+
+__global__ void k_fixed_scale_batch(const FixedDesc* __restrict__ T, int n) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) fixed_scale_body(T[r]);
+}
+
+__global__ void __launch_bounds__(256) k_fixed_batch(const FixedDesc* __restrict__ T, const int64_t* __restrict__ prefix,
+                                                     int n, int phase) {
+    const int64_t b = blockIdx.x;
+    const int r = find_segment(prefix, n, b);
+    if (r < 0) return;
+    fixed_body(T[r], (b - prefix[r]) * blockDim.x + threadIdx.x, phase);
 }
 
 enum TileKind { TILE_444 = 0, TILE_881_FLAT = 1, TILE_RT = 2 };
@@ -468,8 +516,9 @@ int gpd32_scale_e0(const pp_run* r) {
     return 50 - (int)ceil(log2(fmax)) - collapsed * per_axis;
 }
 
-hipError_t launch_gpd32(pp_run* r, double* J) {
-    Gpd32Args A;
+// Kernel arguments of one run (also the batched table entries).
+void gpd32_fill_args(const pp_run* r, Gpd32Args* Ap) {
+    Gpd32Args& A = *Ap;
     int fe[3], ce[3], flo[3], clo[3];
     lds_extents(r, fe, ce, flo, clo);
     for (int d = 0; d < 3; ++d) {
@@ -488,11 +537,9 @@ hipError_t launch_gpd32(pp_run* r, double* J) {
     A.ic = (float)(1.0 / r->p.c);
     A.pusher = r->p.pusher;
     A.nsp = 0;
-    int tile_max_idx[PP_MAX_SPECIES];
     for (int s = 0; s < PP_MAX_SPECIES; ++s) {
         const Species& S = r->sp[s];
         if (!S.active) continue;
-        tile_max_idx[A.nsp] = s;
         Sp32& D = A.sp[A.nsp++];
         D.start = S.offsets;
         D.cell = S.cur.cell;
@@ -507,15 +554,36 @@ hipError_t launch_gpd32(pp_run* r, double* J) {
     A.B = r->mesh.B;
     A.Jq = (unsigned long long*)r->Jq;
     A.qscale = r->qscale;
-    (void)tile_max_idx;
-    hipLaunchKernelGGL(k_fixed_scale, dim3(1), dim3(64), 0, r->stream, (const int32_t*)r->tile_max, PP_MAX_SPECIES,
-                       gpd32_scale_e0(r), r->qscale);
     A.flags = r->flags;
     A.per_xcd = (int)((r->g.ntiles + 7) / 8);
-    const int64_t n3 = 3 * r->g.ncell;
-    int64_t zg = (n3 + 255) / 256;
-    if (zg > 16384) zg = 16384;
-    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)zg), dim3(256), 0, r->stream, (unsigned long long*)r->Jq, n3);
+}
+
+void gpd32_fixed_desc(const pp_run* r, double* J, FixedDesc* D) {
+    D->tile_max = r->tile_max;
+    D->e0 = gpd32_scale_e0(r);
+    D->scale = r->qscale;
+    D->Jq = (unsigned long long*)r->Jq;
+    D->J = J;
+    D->n3 = 3 * r->g.ncell;
+}
+
+size_t gpd32_args_size() { return sizeof(Gpd32Args); }
+size_t gpd32_fixed_desc_size() { return sizeof(FixedDesc); }
+bool gpd32_batchable(const pp_run* r) { return tile_kind(r) == TILE_444; }
+
+static unsigned fixed_grid(int64_t n3) {
+    int64_t g = (n3 + 255) / 256;
+    if (g > 16384) g = 16384;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_gpd32(pp_run* r, double* J) {
+    Gpd32Args A;
+    gpd32_fill_args(r, &A);
+    FixedDesc F;
+    gpd32_fixed_desc(r, J, &F);
+    hipLaunchKernelGGL(k_fixed_scale, dim3(1), dim3(64), 0, r->stream, F);
+    hipLaunchKernelGGL(k_fixed, dim3(fixed_grid(F.n3)), dim3(256), 0, r->stream, F, (int)FX_ZERO);
     const size_t lds = gpd32_lds_bytes(r);
     const unsigned grid = (unsigned)(8 * (int64_t)A.per_xcd);
     const int kind = tile_kind(r);
@@ -536,13 +604,29 @@ hipError_t launch_gpd32(pp_run* r, double* J) {
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // the FP64 current the rest of the step uses
-    if (J) {
-        int64_t g = (n3 + 255) / 256;
-        if (g > 16384) g = 16384;
-        hipLaunchKernelGGL(k_fixed_to_f64, dim3((unsigned)g), dim3(256), 0, r->stream, (const long long*)r->Jq, J, n3,
-                           (const double*)r->qscale);
-    }
+    if (J) hipLaunchKernelGGL(k_fixed, dim3(fixed_grid(F.n3)), dim3(256), 0, r->stream, F, (int)FX_TO_F64);
+    return hipGetLastError();
+}
+
+// Batched particle step of n runs that all use 4x4x4 tiles and the same weight order:
+// fixed-point scales, accumulator clear, the tiled kernel, conversion to FP64.
+hipError_t launch_gpd32_batch(const void* args_table, const int64_t* tile_prefix, int64_t total_tiles,
+                              const void* fixed_table, const int64_t* fixed_prefix, int64_t total_fixed_blocks, int n,
+                              int shape_order, size_t lds, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const FixedDesc* F = (const FixedDesc*)fixed_table;
+    hipLaunchKernelGGL(k_fixed_scale_batch, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, F, n);
+    hipLaunchKernelGGL(k_fixed_batch, dim3((unsigned)total_fixed_blocks), dim3(256), 0, st, F, fixed_prefix, n,
+                       (int)FX_ZERO);
+    const Gpd32Args* T = (const Gpd32Args*)args_table;
+    if (shape_order == 2)
+        hipLaunchKernelGGL((k_gpd32_batch<2, TileCT<4, 4, 4, false>>), dim3((unsigned)total_tiles), dim3(GPD32_BS), lds,
+                           st, T, tile_prefix, n);
+    else
+        hipLaunchKernelGGL((k_gpd32_batch<3, TileCT<4, 4, 4, false>>), dim3((unsigned)total_tiles), dim3(GPD32_BS), lds,
+                           st, T, tile_prefix, n);
+    hipLaunchKernelGGL(k_fixed_batch, dim3((unsigned)total_fixed_blocks), dim3(256), 0, st, F, fixed_prefix, n,
+                       (int)FX_TO_F64);
     return hipGetLastError();
 }
 

@@ -112,5 +112,34 @@ hipError_t launch_field_step(pp_run* r);
 hipError_t launch_sort(pp_run* r, int s, bool reorder);
 hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+void swap_buffers(pp_particles& c);
+
+// batched launches (pp_batch.hip builds the descriptor tables)
+size_t gpd32_args_size();
+size_t gpd32_fixed_desc_size();
+bool gpd32_batchable(const pp_run* r);
+size_t gpd32_lds_bytes(const pp_run* r);
+struct Gpd32Args;
+struct FixedDesc;
+struct FieldDesc;
+struct LineArgs;
+struct SortDesc;
+void gpd32_fill_args(const pp_run* r, Gpd32Args* A);
+void gpd32_fixed_desc(const pp_run* r, double* J, FixedDesc* D);
+hipError_t launch_gpd32_batch(const void* args_table, const int64_t* tile_prefix, int64_t total_tiles,
+                              const void* fixed_table, const int64_t* fixed_prefix, int64_t total_fixed_blocks, int n,
+                              int shape_order, size_t lds, hipStream_t st);
+size_t field_desc_size();
+void field_desc(const pp_run* r, FieldDesc* D);
+hipError_t launch_field_step_batch(const void* table, const int64_t* prefix, int n, int64_t total_blocks,
+                                   int max_sweeps, hipStream_t st);
+size_t line_desc_size();
+void line_desc(const pp_run* r, const double* J2, double* J, LineArgs* A);
+hipError_t launch_line_solve_batch(const void* table, const int64_t* prefix, int n, int64_t total_blocks, hipStream_t st);
+size_t sort_desc_size();
+void sort_desc(const pp_run* r, int s, SortDesc* D);
+void sort_desc_blocks(const pp_run* r, int s, bool reorder, int64_t blocks[7]);
+hipError_t launch_sort_batch(const void* table, const int64_t* const prefixes[7], const int64_t totals[7], int nseg,
+                             hipStream_t st);
 
 }  // namespace pp

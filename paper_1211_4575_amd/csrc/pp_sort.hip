@@ -99,8 +99,8 @@ __device__ __forceinline__ int agg_slot(int32_t* keys, int32_t key) {
     return -1;
 }
 
-__global__ void __launch_bounds__(256) k_tile_count(KeyGeom G, const int32_t* __restrict__ cell, int64_t n,
-                                                    int32_t* __restrict__ count) {
+__device__ __forceinline__ void tile_count_block(const KeyGeom& G, const int32_t* __restrict__ cell, int64_t n,
+                                                 int32_t* __restrict__ count, int64_t blk) {
     __shared__ int32_t keys[AGG_SLOTS];
     __shared__ int32_t cnt[AGG_SLOTS];
     for (int i = threadIdx.x; i < AGG_SLOTS; i += 256) {
@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(256) k_tile_count(KeyGeom G, const int32_t* __
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int64_t base = (int64_t)blockIdx.x * AGG_BLOCK;
+    const int64_t base = blk * AGG_BLOCK;
     for (int k = 0; k < AGG_PER_THREAD; ++k) {
         const int64_t p = base + k * 256 + threadIdx.x;
         const bool active = p < n;
@@ -132,6 +132,11 @@ __global__ void __launch_bounds__(256) k_tile_count(KeyGeom G, const int32_t* __
     __syncthreads();
     for (int i = threadIdx.x; i < AGG_SLOTS; i += 256)
         if (keys[i] >= 0 && cnt[i] > 0) atomicAdd(count + keys[i], cnt[i]);
+}
+
+__global__ void __launch_bounds__(256) k_tile_count(KeyGeom G, const int32_t* __restrict__ cell, int64_t n,
+                                                    int32_t* __restrict__ count) {
+    tile_count_block(G, cell, n, count, blockIdx.x);
 }
 
 template <typename T>
@@ -166,7 +171,7 @@ __global__ void __launch_bounds__(256) k_scatter(ScatterArgs<T> A) {
 // split form: bucket by tile with block-level aggregation (see k_tile_count); a wavefront's
 // particles bound for one tile get consecutive slots in their source order
 template <typename T>
-__global__ void __launch_bounds__(256) k_scatter_tiles(ScatterArgs<T> A) {
+__device__ __forceinline__ void scatter_tiles_block(const ScatterArgs<T>& A, int64_t blk) {
     __shared__ int32_t keys[AGG_SLOTS];
     __shared__ int32_t cnt[AGG_SLOTS];
     __shared__ int32_t gbase[AGG_SLOTS];
@@ -176,7 +181,7 @@ __global__ void __launch_bounds__(256) k_scatter_tiles(ScatterArgs<T> A) {
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int64_t base = (int64_t)blockIdx.x * AGG_BLOCK;
+    const int64_t base = blk * AGG_BLOCK;
     int my_slot[AGG_PER_THREAD];
     int32_t my_off[AGG_PER_THREAD];
 #pragma unroll
@@ -228,6 +233,11 @@ __global__ void __launch_bounds__(256) k_scatter_tiles(ScatterArgs<T> A) {
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_scatter_tiles(ScatterArgs<T> A) {
+    scatter_tiles_block(A, blockIdx.x);
+}
+
 // largest tile population (the fixed-point current's scale depends on it)
 __global__ void __launch_bounds__(256) k_tile_max(const int32_t* __restrict__ start, int64_t ntiles, int32_t* out) {
     int m = 0;
@@ -266,12 +276,11 @@ struct ReorderArgs {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_tile_reorder(ReorderArgs<T> A) {
+__device__ __forceinline__ void tile_reorder_tile(const ReorderArgs<T>& A, int64_t tile) {
     __shared__ int32_t cnt[TILE_CELLS];
     __shared__ int32_t Tr[REORDER_RMAX + 1];
     __shared__ uint64_t Mr[REORDER_RMAX];
     __shared__ int32_t ovf;
-    const int64_t tile = blockIdx.x;
     if (tile >= A.ntiles) return;
     const int32_t s = A.start[tile], e = A.start[tile + 1];
     if (threadIdx.x < TILE_CELLS) cnt[threadIdx.x] = 0;
@@ -331,6 +340,11 @@ __global__ void __launch_bounds__(256) k_tile_reorder(ReorderArgs<T> A) {
         }
         if (A.id) A.id_o[j] = A.id[i];
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_tile_reorder(ReorderArgs<T> A) {
+    tile_reorder_tile(A, blockIdx.x);
 }
 
 // ---- exclusive scan of int32, in place ------------------------------------------------
@@ -395,6 +409,13 @@ static void scan_inplace(int32_t* data, int64_t n, int32_t* tmp, hipStream_t st)
     }
 }
 
+
+static unsigned grid_for(int64_t n, int bs, int64_t cap = 65535) {
+    int64_t g = (n + bs - 1) / bs;
+    if (g > cap) g = cap;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
 static KeyGeom key_geom(const pp_run* r) {
     KeyGeom G;
     for (int d = 0; d < 3; ++d) {
@@ -405,13 +426,165 @@ static KeyGeom key_geom(const pp_run* r) {
     return G;
 }
 
-static unsigned grid_for(int64_t n, int bs, int64_t cap = 65535) {
-    int64_t g = (n + bs - 1) / bs;
-    if (g > cap) g = cap;
-    return (unsigned)(g < 1 ? 1 : g);
+// ---- batched split-form sort of one species slot over several runs ------------------------
+struct SortDesc {
+    KeyGeom G;
+    int64_t n, ntiles;
+    int32_t* offsets;   // ntiles + 1
+    int32_t* cursor;    // ntiles
+    int32_t* tile_max;  // the run's slot for this species
+    ScatterArgs<float> A;
+    ReorderArgs<float> B;
+};
+
+enum SortPhase { SP_FILL = 0, SP_COUNT = 1, SP_SCAN = 2, SP_MAX = 3, SP_CURSOR = 4, SP_SCATTER = 5, SP_REORDER = 6 };
+
+// whole-segment exclusive scan by one workgroup (segments are short: one entry per tile)
+__device__ __forceinline__ void scan_segment(int32_t* data, int64_t n) {
+    __shared__ int32_t sh[256];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < n; base += 256) {
+        const int64_t q = base + threadIdx.x;
+        const int32_t v = q < n ? data[q] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const int32_t x = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += x;
+            __syncthreads();
+        }
+        const int32_t incl = sh[threadIdx.x];
+        if (q < n) data[q] = carry + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 255) carry += incl;
+        __syncthreads();
+    }
 }
 
-static void swap_buffers(pp_particles& c) {
+__device__ __forceinline__ void tile_max_segment(const int32_t* start, int64_t ntiles, int32_t* out) {
+    __shared__ int32_t sh[256];
+    int m = 0;
+    for (int64_t t = threadIdx.x; t < ntiles; t += 256) {
+        const int c = start[t + 1] - start[t];
+        m = c > m ? c : m;
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] = sh[threadIdx.x] > sh[threadIdx.x + off] ? sh[threadIdx.x] : sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_sort_batch(const SortDesc* __restrict__ T, const int64_t* __restrict__ prefix,
+                                                    int nseg, int phase) {
+    const int64_t b = blockIdx.x;
+    const int r = find_segment(prefix, nseg, b);
+    if (r < 0) return;
+    const SortDesc& D = T[r];
+    const int64_t blk = b - prefix[r];
+    switch (phase) {
+    case SP_FILL: {
+        const int64_t q = blk * 256 + threadIdx.x;
+        if (q <= D.ntiles) D.offsets[q] = 0;
+        break;
+    }
+    case SP_COUNT:
+        tile_count_block(D.G, D.A.cell, D.n, D.offsets, blk);
+        break;
+    case SP_SCAN:
+        scan_segment(D.offsets, D.ntiles + 1);
+        break;
+    case SP_MAX:
+        tile_max_segment(D.offsets, D.ntiles, D.tile_max);
+        break;
+    case SP_CURSOR: {
+        const int64_t q = blk * 256 + threadIdx.x;
+        if (q < D.ntiles) D.cursor[q] = D.offsets[q];
+        break;
+    }
+    case SP_SCATTER:
+        scatter_tiles_block(D.A, blk);
+        break;
+    default:
+        tile_reorder_tile(D.B, blk);
+        break;
+    }
+}
+
+// Fill the descriptor of species s of run r (buffers: cur -> alt for the bucketing; the
+// rebuild reads alt and writes back into cur).
+void sort_desc(const pp_run* r, int s, SortDesc* D) {
+    const Species& S = r->sp[s];
+    D->G = key_geom(r);
+    D->n = S.n;
+    D->ntiles = r->g.ntiles;
+    D->offsets = S.offsets;
+    D->cursor = r->sort_cursor;
+    D->tile_max = r->tile_max + s;
+    ScatterArgs<float>& A = D->A;
+    A.G = D->G;
+    A.n = S.n;
+    A.cell = S.cur.cell;
+    A.id = S.cur.id;
+    A.cell_o = S.cur.cell_alt;
+    A.id_o = S.cur.id ? S.cur.id_alt : nullptr;
+    for (int d = 0; d < 3; ++d) {
+        A.pos[d] = (const float*)S.cur.pos[d];
+        A.u[d] = (const float*)S.cur.u[d];
+        A.pos_o[d] = (float*)S.cur.pos_alt[d];
+        A.u_o[d] = (float*)S.cur.u_alt[d];
+    }
+    A.cursor = r->sort_cursor;
+    ReorderArgs<float>& B = D->B;
+    B.G = D->G;
+    B.ntiles = r->g.ntiles;
+    B.start = S.offsets;
+    B.cell = S.cur.cell_alt;
+    B.id = S.cur.id ? S.cur.id_alt : nullptr;
+    B.cell_o = S.cur.cell;
+    B.id_o = S.cur.id;
+    for (int d = 0; d < 3; ++d) {
+        B.pos[d] = (const float*)S.cur.pos_alt[d];
+        B.u[d] = (const float*)S.cur.u_alt[d];
+        B.pos_o[d] = (float*)S.cur.pos[d];
+        B.u_o[d] = (float*)S.cur.u[d];
+    }
+    B.rank = r->sort_scratch;
+    B.perm = r->sort_scratch + r->sort_scratch_n;
+}
+
+size_t sort_desc_size() { return sizeof(SortDesc); }
+
+// Blocks each phase needs for one descriptor.
+void sort_desc_blocks(const pp_run* r, int s, bool reorder, int64_t blocks[7]) {
+    const int64_t n = r->sp[s].n, nt = r->g.ntiles;
+    blocks[SP_FILL] = (nt + 1 + 255) / 256;
+    blocks[SP_COUNT] = (n + AGG_BLOCK - 1) / AGG_BLOCK;
+    blocks[SP_SCAN] = 1;
+    blocks[SP_MAX] = 1;
+    blocks[SP_CURSOR] = (nt + 255) / 256;
+    blocks[SP_SCATTER] = (n + AGG_BLOCK - 1) / AGG_BLOCK;
+    blocks[SP_REORDER] = reorder && n > 0 ? nt : 0;
+}
+
+// prefixes: 7 arrays of nseg + 1 block prefixes (device), totals: blocks per phase
+hipError_t launch_sort_batch(const void* table, const int64_t* const prefixes[7], const int64_t totals[7], int nseg,
+                             hipStream_t st) {
+    if (nseg == 0) return hipSuccess;
+    const SortDesc* T = (const SortDesc*)table;
+    for (int ph = SP_FILL; ph <= SP_REORDER; ++ph) {
+        if (totals[ph] == 0) continue;
+        hipLaunchKernelGGL(k_sort_batch, dim3((unsigned)totals[ph]), dim3(256), 0, st, T, prefixes[ph], nseg, ph);
+    }
+    return hipGetLastError();
+}
+
+void swap_buffers(pp_particles& c) {
     int32_t* tc = c.cell;
     c.cell = c.cell_alt;
     c.cell_alt = tc;

@@ -135,9 +135,105 @@ __global__ void __launch_bounds__(256) k_pair_mj(MJArgs A) {
     }
 }
 
+struct TSArgs {
+    uint64_t seed;
+    int wl;
+    int n[3], k[3];
+    int64_t npart;
+    double drift[2];
+    double uth;
+    int split;
+    int32_t* cell[2];
+    void* off[2][3];
+    void* u[2][3];
+};
+
+// Two beams on a quiet lattice: particle p sits at lattice point (ix, iy, iz), x fastest, of
+// k[d] points per cell per axis at offsets (a + 1/2)/k; both beams share the points.  Proper
+// velocity = drift along x + uth * standard normals (Box-Muller of draw blocks 0 and 1).
+__global__ void __launch_bounds__(256) k_two_stream(TSArgs A) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.npart) return;
+    const int64_t Lx = (int64_t)A.n[0] * A.k[0], Ly = (int64_t)A.n[1] * A.k[1];
+    const int64_t ix = p % Lx, iy = (p / Lx) % Ly, iz = p / (Lx * Ly);
+    const double X[3] = {((double)ix + 0.5) / A.k[0], ((double)iy + 0.5) / A.k[1], ((double)iz + 0.5) / A.k[2]};
+    int32_t cellv = 0;
+    float offf[3];
+    if (A.split) {
+        int64_t ijk[3];
+        for (int d = 0; d < 3; ++d) {
+            double c = floor(X[d] + 0.5);
+            float o = (float)(X[d] - c);
+            if (o >= 0.5f) {
+                c += 1.0;
+                o = (float)(X[d] - c);
+            }
+            offf[d] = o;
+            int64_t ci = (int64_t)c % A.n[d];
+            ijk[d] = ci < 0 ? ci + A.n[d] : ci;
+        }
+        cellv = (int32_t)(ijk[0] + (int64_t)A.n[0] * (ijk[1] + (int64_t)A.n[1] * ijk[2]));
+    }
+    for (int s = 0; s < 2; ++s) {
+        double U[4];
+        uniform_pair(A.seed, (uint64_t)p, 0, stream_id(A.wl, s, 1), U[0], U[1]);
+        uniform_pair(A.seed, (uint64_t)p, 1, stream_id(A.wl, s, 1), U[2], U[3]);
+        const double r0 = sqrt(-2.0 * log(U[0])), t0 = 2.0 * M_PI * U[1];
+        const double r1 = sqrt(-2.0 * log(U[2])), t1 = 2.0 * M_PI * U[3];
+        const double g[3] = {r0 * cos(t0), r0 * sin(t0), r1 * cos(t1)};
+        const double uv[3] = {A.drift[s] + A.uth * g[0], A.uth * g[1], A.uth * g[2]};
+        if (A.split) {
+            A.cell[s][p] = cellv;
+            for (int d = 0; d < 3; ++d) {
+                ((float*)A.off[s][d])[p] = offf[d];
+                ((float*)A.u[s][d])[p] = (float)uv[d];
+            }
+        } else {
+            for (int d = 0; d < 3; ++d) {
+                ((double*)A.off[s][d])[p] = X[d];
+                ((double*)A.u[s][d])[p] = uv[d];
+            }
+        }
+    }
+}
+
 }  // namespace
 
 extern "C" {
+
+int ppi_two_stream_lattice(uint64_t seed, int32_t wl, const int32_t n[3], const int32_t k[3], double v_beam,
+                           double uth, int32_t split, int32_t* const cell[2], void* const off[2][3],
+                           void* const u[2][3], void* hip_stream) {
+    if (!n || !k || !(v_beam >= 0.0 && v_beam < 1.0) || !(uth >= 0.0)) return -1;
+    TSArgs A;
+    A.seed = seed;
+    A.wl = wl;
+    A.npart = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] < 1 || k[d] < 1) return -1;
+        A.n[d] = n[d];
+        A.k[d] = k[d];
+        A.npart *= (int64_t)n[d] * k[d];
+    }
+    const double g0 = 1.0 / sqrt(1.0 - v_beam * v_beam);
+    A.drift[0] = v_beam * g0;
+    A.drift[1] = -v_beam * g0;
+    A.uth = uth;
+    A.split = split ? 1 : 0;
+    for (int s = 0; s < 2; ++s) {
+        A.cell[s] = cell ? cell[s] : nullptr;
+        if (split && !A.cell[s]) return -1;
+        for (int d = 0; d < 3; ++d) {
+            A.off[s][d] = off[s][d];
+            A.u[s][d] = u[s][d];
+            if (!A.off[s][d] || !A.u[s][d]) return -1;
+        }
+    }
+    const int bs = 256;
+    hipLaunchKernelGGL(k_two_stream, dim3((unsigned)((A.npart + bs - 1) / bs)), dim3(bs), 0, (hipStream_t)hip_stream, A);
+    return hipGetLastError() == hipSuccess ? 0 : -6;
+}
+
 
 int ppi_philox_blocks(uint64_t seed, uint32_t block, uint32_t stream, int64_t ctr0, int64_t count, uint32_t* out,
                       void* hip_stream) {

@@ -24,6 +24,11 @@ def lib():
                                                ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
                                                ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         L.ppi_pair_maxwell_juttner.restype = ctypes.c_int
+        L.ppi_two_stream_lattice.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                             ctypes.POINTER(vp), vp]
+        L.ppi_two_stream_lattice.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -47,3 +52,17 @@ def pair_maxwell_juttner(seed, n, start, count, theta, split, cells, offs, us, h
                                         hip_stream)
     if rc:
         raise RuntimeError(f"ppi_pair_maxwell_juttner failed ({rc})")
+
+
+def two_stream_lattice(seed, wl, n, per_dim, v_beam, uth, split, cells, offs, us, hip_stream):
+    """Quiet-lattice two-beam load written into device tensors (see inputs.two_stream)."""
+    vp = ctypes.c_void_p
+    n_arr = (ctypes.c_int32 * 3)(*[int(v) for v in n])
+    k_arr = (ctypes.c_int32 * 3)(*[int(v) for v in per_dim])
+    cell_arr = (vp * 2)(*([c.data_ptr() for c in cells] if cells is not None else [None, None]))
+    off_arr = (vp * 6)(*[offs[s][d].data_ptr() for s in range(2) for d in range(3)])
+    u_arr = (vp * 6)(*[us[s][d].data_ptr() for s in range(2) for d in range(3)])
+    rc = lib().ppi_two_stream_lattice(seed, wl, n_arr, k_arr, v_beam, uth, int(split), cell_arr, off_arr, u_arr,
+                                      hip_stream)
+    if rc:
+        raise RuntimeError(f"ppi_two_stream_lattice failed ({rc})")

@@ -23,7 +23,8 @@ PP_DIAG_MOMENTS, PP_DIAG_FIELDS, PP_DIAG_RHO, PP_DIAG_DIVB, PP_DIAG_ALL = 1, 2, 
 
 EXPORTED = ("pp_create", "pp_init_species", "pp_gather_push_deposit", "pp_field_step", "pp_sort_particles",
             "pp_diagnostics", "pp_get_particles", "pp_timing_enable", "pp_timing_read", "pp_destroy",
-            "pp_status_str", "pp_last_hip_error")
+            "pp_status_str", "pp_last_hip_error", "pp_batch_create", "pp_batch_add", "pp_batch_remove",
+            "pp_batch_size", "pp_batch_step", "pp_batch_destroy")
 
 
 class pp_params(ctypes.Structure):
@@ -111,6 +112,12 @@ def lib():
         L.pp_timing_enable.argtypes = [vp, ctypes.c_int32]
         L.pp_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.pp_destroy.argtypes = [vp]
+        L.pp_batch_create.argtypes = [ctypes.c_int32, vp, ctypes.POINTER(vp)]
+        L.pp_batch_add.argtypes = [vp, vp]
+        L.pp_batch_remove.argtypes = [vp, vp]
+        L.pp_batch_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+        L.pp_batch_step.argtypes = [vp]
+        L.pp_batch_destroy.argtypes = [vp]
         L.pp_status_str.argtypes = [ctypes.c_int32]
         L.pp_status_str.restype = ctypes.c_char_p
         L.pp_last_hip_error.argtypes = []
@@ -176,6 +183,34 @@ def pp_timing_read(run):
 
 def pp_destroy(run):
     _check("pp_destroy", lib().pp_destroy(run))
+
+
+def pp_batch_create(max_runs: int, stream: int):
+    h = ctypes.c_void_p()
+    _check("pp_batch_create", lib().pp_batch_create(int(max_runs), ctypes.c_void_p(stream), ctypes.byref(h)))
+    return h
+
+
+def pp_batch_add(batch, run):
+    _check("pp_batch_add", lib().pp_batch_add(batch, run))
+
+
+def pp_batch_remove(batch, run):
+    _check("pp_batch_remove", lib().pp_batch_remove(batch, run))
+
+
+def pp_batch_size(batch) -> int:
+    n = ctypes.c_int32()
+    _check("pp_batch_size", lib().pp_batch_size(batch, ctypes.byref(n)))
+    return n.value
+
+
+def pp_batch_step(batch):
+    _check("pp_batch_step", lib().pp_batch_step(batch))
+
+
+def pp_batch_destroy(batch):
+    _check("pp_batch_destroy", lib().pp_batch_destroy(batch))
 
 
 # ---- convenience owner of the torch tensors ---------------------------------------------

@@ -1,0 +1,160 @@
+"""GPU: continuous batching (pp_batch_*) gives every run exactly the results it gets alone.
+
+Runs of different boxes, field orders and pushers join a batch at different steps and leave
+after their own number of steps; the same inputs stepped alone through pp_gather_push_deposit
+/ pp_sort_particles / pp_field_step must give bitwise-identical E, B, J and particle states
+(compared by particle id, since the order inside a tile is not unique).  Both paths run the
+same per-tile and per-cell bodies and the current sum is exact fixed point, so the results
+may not depend on which other runs share a launch."""
+import sys
+
+import numpy as np
+import pytest
+
+from _state import random_state
+from paper_1211_4575_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ppm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1211_4575_amd import pp
+    pp.lib()
+    return pp
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# n, ppc, field order, pusher, cell size, dt, join step, own steps
+RUNS = [
+    ((16, 16, 16), 4, 6, 0, (1.0, 1.0, 1.0), 0.4, 0, 7),
+    ((12, 8, 8), 3, 4, 1, (0.8, 1.0, 1.2), 0.3, 1, 5),
+    ((20, 12, 8), 2, 2, 0, (1.0, 1.0, 1.0), 0.35, 2, 6),
+    ((9, 7, 5), 3, 6, 0, (1.0, 1.0, 1.0), 0.4, 2, 4),
+]
+
+
+def _split_species(species, n):
+    out = []
+    for s in species:
+        cell, off = I.to_split(s["pos"], n)
+        out.append(dict(q=s["q"], m=s["m"], w=s["w"], cell=cell, off=off, u=s["u"].astype(np.float32)))
+    return out
+
+
+def _make(ppm, orc, k):
+    n, ppc, fo, pusher, d, dt, _, _ = RUNS[k]
+    species, E, B = random_state(orc, n, ppc, seed=700 + k, d=d)
+    P = ppm.make_params(n=n, d=d, dt=dt, shape_order=3, field_order=fo, pusher=pusher,
+                        precision=ppm.PP_PREC_FP32_SPLIT, relax_tol=1e-14, relax_max_iter=200)
+    return ppm.Run(P, _split_species(species, n), E=E, B=B)
+
+
+def _state(run):
+    E, B, J = run.fields()
+    parts = []
+    for s in range(len(run.species)):
+        p = run.particles(s)
+        o = np.argsort(p["id"])
+        parts.append({k: (v[..., o] if k != "id" else v[o]) for k, v in p.items()})
+    return (E.copy(), B.copy(), J.copy()), parts
+
+
+def _assert_same(a, b, what):
+    (fa, pa), (fb, pb) = a, b
+    for name, x, y in zip("EBJ", fa, fb):
+        assert np.array_equal(x, y), f"{what}: {name} differs (max {np.max(np.abs(x - y))})"
+    for s, (x, y) in enumerate(zip(pa, pb)):
+        for key in x:
+            assert np.array_equal(x[key], y[key]), f"{what}: species {s} {key} differs"
+
+
+def test_batch_equals_alone(ppm, orc):
+    import torch
+    stream = torch.cuda.current_stream().cuda_stream
+    alone = []
+    for k, case in enumerate(RUNS):
+        _say("alone", k, case)
+        r = _make(ppm, orc, k)
+        for _ in range(case[7]):
+            r.step()
+        d = r.diagnostics(ppm.PP_DIAG_MOMENTS)
+        assert d.flags == 0
+        alone.append(_state(r))
+        r.close()
+
+    runs = [_make(ppm, orc, k) for k in range(len(RUNS))]
+    left = [case[7] for case in RUNS]
+    batch = ppm.pp_batch_create(8, stream)
+    try:
+        g = 0
+        done = [False] * len(RUNS)
+        while not all(done):
+            for k, case in enumerate(RUNS):
+                if case[6] == g:
+                    ppm.pp_batch_add(batch, runs[k].handle)
+            _say("batch step", g, "members", ppm.pp_batch_size(batch))
+            ppm.pp_batch_step(batch)
+            for k, case in enumerate(RUNS):
+                if case[6] <= g and not done[k]:
+                    left[k] -= 1
+                    if left[k] == 0:
+                        ppm.pp_batch_remove(batch, runs[k].handle)
+                        done[k] = True
+            g += 1
+        assert ppm.pp_batch_size(batch) == 0
+    finally:
+        ppm.pp_batch_destroy(batch)
+    for k in range(len(RUNS)):
+        d = runs[k].diagnostics(ppm.PP_DIAG_MOMENTS)
+        assert d.flags == 0
+        assert d.step == RUNS[k][7]
+        _assert_same(_state(runs[k]), alone[k], f"run {k}")
+        runs[k].close()
+
+
+def test_batch_rejects_what_it_cannot_batch(ppm, orc):
+    import torch
+    stream = torch.cuda.current_stream().cuda_stream
+    batch = ppm.pp_batch_create(2, stream)
+    try:
+        # FP64 form
+        species, E, B = random_state(orc, (8, 8, 8), 2, seed=3)
+        P64 = ppm.make_params(n=(8, 8, 8), shape_order=3, field_order=2)
+        r64 = ppm.Run(P64, species, E=E, B=B)
+        with pytest.raises(ppm.PPError):
+            ppm.pp_batch_add(batch, r64.handle)
+        # a flat box (8x8x1 tiles)
+        species, E, B = random_state(orc, (16, 16, 1), 2, seed=4)
+        Pf = ppm.make_params(n=(16, 16, 1), shape_order=3, field_order=2, precision=ppm.PP_PREC_FP32_SPLIT)
+        rf = ppm.Run(Pf, _split_species(species, (16, 16, 1)), E=E, B=B)
+        with pytest.raises(ppm.PPError):
+            ppm.pp_batch_add(batch, rf.handle)
+        # capacity, duplicates, other weight order
+        ra, rb = _make(ppm, orc, 0), _make(ppm, orc, 1)
+        ppm.pp_batch_add(batch, ra.handle)
+        with pytest.raises(ppm.PPError):
+            ppm.pp_batch_add(batch, ra.handle)
+        species, E, B = random_state(orc, (8, 8, 8), 2, seed=5)
+        P2 = ppm.make_params(n=(8, 8, 8), shape_order=2, field_order=2, precision=ppm.PP_PREC_FP32_SPLIT)
+        r2 = ppm.Run(P2, _split_species(species, (8, 8, 8)), E=E, B=B)
+        with pytest.raises(ppm.PPError):
+            ppm.pp_batch_add(batch, r2.handle)
+        ppm.pp_batch_add(batch, rb.handle)
+        with pytest.raises(ppm.PPError):
+            ppm.pp_batch_add(batch, _make(ppm, orc, 2).handle)
+        # a run that was pushed but not sorted cannot join
+        ppm.pp_batch_remove(batch, rb.handle)
+        rb.gather_push_deposit()
+        with pytest.raises(ppm.PPError):
+            ppm.pp_batch_add(batch, rb.handle)
+        with pytest.raises(ppm.PPError):
+            ppm.pp_batch_remove(batch, rb.handle)
+        assert ppm.pp_batch_size(batch) == 1
+    finally:
+        ppm.pp_batch_destroy(batch)

@@ -48,3 +48,31 @@ def test_device_pair_mj_matches_host(split):
             assert np.array_equal(offs[s].cpu().numpy(), wl.species[s].pos)
             close = np.all(np.abs(u - uref) <= 1e-12 * (1 + np.abs(uref)), axis=0)
         assert close.mean() > 0.999
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_device_two_stream_matches_host(split):
+    import torch
+    from paper_1211_4575_amd import inputs_device as ind
+    n, per_dim = (12, 6, 4), (4, 2, 2)
+    wl = I.two_stream(n=n, per_dim=per_dim, v_beam=0.3, uth=0.02)
+    cnt = wl.species[0].pos.shape[1]
+    rt = torch.float32 if split else torch.float64
+    cells = [torch.empty(cnt, dtype=torch.int32, device="cuda") for _ in range(2)] if split else None
+    offs = [torch.empty((3, cnt), dtype=rt, device="cuda") for _ in range(2)]
+    us = [torch.empty((3, cnt), dtype=rt, device="cuda") for _ in range(2)]
+    ind.two_stream_lattice(I.SEED_BASE, 2, n, per_dim, 0.3, 0.02, split, cells, [[o[d] for d in range(3)] for o in offs],
+                           [[u[d] for d in range(3)] for u in us], torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    for s in range(2):
+        u = us[s].cpu().numpy().astype(np.float64)
+        uref = wl.species[s].u
+        if split:
+            cell, off = I.to_split(wl.species[s].pos, n)
+            assert np.array_equal(cells[s].cpu().numpy(), cell)
+            assert np.array_equal(offs[s].cpu().numpy(), off)
+            assert np.array_equal(us[s].cpu().numpy(), uref.astype(np.float32)) or \
+                np.max(np.abs(u - uref)) <= 1e-7 * np.max(np.abs(uref))
+        else:
+            assert np.array_equal(offs[s].cpu().numpy(), wl.species[s].pos)
+            assert np.max(np.abs(u - uref)) <= 1e-14 * np.max(np.abs(uref))

@@ -92,6 +92,7 @@ FP32_CASES = [
     ((20, 6, 1), 4, 3, 6),
     ((9, 7, 5), 3, 3, 4),
     ((64, 1, 1), 16, 3, 6),
+    ((6, 2, 12), 3, 2, 4),
 ]
 
 
