@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -150,6 +151,65 @@ def measured_traffic(particles):
         return None
 
 
+def serving_bench(args, torch, pp):
+    """The serving ensemble: a Poisson stream of two-stream requests (grids 32^3, 64x32x32,
+    128x16x16; 8-64 particles per cell per beam; beam speed 0.1-0.5 c; 200-2000 steps), served
+    by continuous batching of FP32 split-precision runs; p50/p99 completion latency and
+    aggregate updates/s, beside the same requests served one at a time (FP64 plain form and
+    FP32 split form, from measured per-step times)."""
+    from paper_1211_4575_amd import inputs as I
+    from paper_1211_4575_amd import serve as S
+
+    reqs = I.serving_requests(count=args.requests, rate=args.rate, seed=SEED)
+    be = S.DeviceBackend(max_slots=args.slots)
+    log(f"[serve] {len(reqs)} requests, rate {args.rate}/s, {sum(r.updates for r in reqs):.3e} updates, "
+        f"budget {args.mem_gib} GiB, {args.slots} slots")
+    sched = S.Scheduler(be, mem_budget=int(args.mem_gib * (1 << 30)), max_slots=args.slots)
+    t0 = time.perf_counter()
+    res = sched.run(reqs)
+    wall = time.perf_counter() - t0
+    summ = S.summarize(res, t_first=0.0)
+    log(f"[serve] batched: {summ}, wall {wall:.1f} s, peak members {sched.peak_members}, "
+        f"peak {sched.peak_bytes / 2**30:.1f} GiB, {sched.batch_steps} batch steps")
+    refs = {}
+    for name, split in (("fp64_plain_one_at_a_time", False), ("fp32_split_one_at_a_time", True)):
+        if split is False and args.no_fp64:
+            continue
+        r1, per_class = S.one_at_a_time_reference(be, reqs, split=split, steps=args.ref_steps)
+        s1 = S.summarize(r1, t_first=0.0)
+        s1["ms_per_step_by_class"] = per_class
+        s1["kind"] = "measured per-step time of each grid/lattice class x steps + set-up, FIFO over the same arrivals"
+        refs[name] = s1
+        log(f"[serve] {name}: {s1}")
+    be.close()
+    fails = [r.rid for r in res if r.status != "ok"]
+    out = {
+        "metric": "particle updates/s (gather+push+deposit) FP32 vs FP64; ensemble p50/p99",
+        "value": summ.get("updates_per_s"),
+        "unit": "particle updates/s",
+        "n_gpus": 1,
+        "steps": sched.batch_steps,
+        "warmup": 0,
+        "ms_per_step": 1e3 * summ.get("makespan_s", math.nan) / max(sched.batch_steps, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"serving ensemble: {len(reqs)} two-stream requests, Poisson arrivals at {args.rate}/s, "
+                               f"grids 32^3/64x32x32/128x16x16, 8-64 ppc per beam, 200-2000 steps, cubic weights, "
+                               f"6th-order fields, FP32 split, continuous batching",
+                   "p50_s": summ.get("p50_s"), "p99_s": summ.get("p99_s"), "makespan_s": summ.get("makespan_s"),
+                   "completed": summ.get("completed"), "failed": fails, "peak_members": sched.peak_members,
+                   "peak_gib": round(sched.peak_bytes / 2**30, 2), "mem_budget_gib": args.mem_gib,
+                   "slots": args.slots, "references": refs,
+                   "speedup_vs_fp64_one_at_a_time": (summ["updates_per_s"] / refs["fp64_plain_one_at_a_time"]["updates_per_s"])
+                   if "fp64_plain_one_at_a_time" in refs and summ.get("updates_per_s") else None},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +222,12 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--workload", choices=("pair_mj", "serving"), default="pair_mj")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=1.0, help="serving: mean arrivals per second")
+    ap.add_argument("--slots", type=int, default=64, help="serving: most runs in the batch")
+    ap.add_argument("--mem-gib", type=float, default=160.0, help="serving: device memory budget for runs")
+    ap.add_argument("--ref-steps", type=int, default=3, help="serving: timed steps per class for the references")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
@@ -172,6 +238,9 @@ def main(argv=None):
 
     from paper_1211_4575_amd import inputs_device as ind
     from paper_1211_4575_amd import pp
+
+    if args.workload == "serving":
+        return serving_bench(args, torch, pp)
 
     if args.calib_copy_gib > 0:
         nb = int(args.calib_copy_gib * (1 << 30))

@@ -137,6 +137,14 @@ typedef struct pp_diag {
 
 typedef struct pp_run pp_run;
 
+/* Device memory a run with these parameters allocates inside the library (its
+ * scratch: relaxation buffers, the fixed-point current, sort buckets and
+ * scratch, per-species offsets), for nspecies species of at most
+ * max_particles particles each; the caller-owned mesh and particle arrays are
+ * not included.  For admission by memory footprint (several runs sharing one
+ * GPU).  Validates params like pp_create; no device call. */
+pp_status pp_workspace_size(const pp_params* params, int64_t max_particles, int32_t nspecies, size_t* bytes);
+
 /* Create a run: validates params, records the mesh views and the stream
  * (a hipStream_t; NULL = default stream) and allocates internal scratch of
  * O(ncell) doubles.  *out receives the handle. */

@@ -130,6 +130,49 @@ const char* pp_status_str(pp_status st) {
 
 const char* pp_last_hip_error(void) { return g_err; }
 
+// Device bytes pp_create and pp_init_species allocate for a run (the caller-owned mesh and
+// particle arrays not included); mirrors the allocations below.
+static size_t internal_bytes(const pp_params* p, const Geom& g, int64_t nmax, int nsp) {
+    const size_t nc = (size_t)g.ncell, n3 = 3 * nc, nb = (size_t)g.nbins;
+    size_t b = 0;
+    if (p->field_order > 2) b += n3 * sizeof(double);                     // J2
+    b += 3 * n3 * sizeof(double);                                          // Bn, Bw, R
+    b += 2 * nc * sizeof(double);                                          // rho, rho_prev
+    b += nb * sizeof(int32_t) + (size_t)scan_tmp_size(g.nbins + 1) * sizeof(int32_t);
+    b += sizeof(int32_t) + ((size_t)diag_acc_count() + 8) * sizeof(double);
+    if (p->precision == PP_PREC_FP32_SPLIT) {
+        b += n3 * sizeof(long long) + PP_MAX_SPECIES * sizeof(int32_t) + sizeof(double);
+        b += 2 * (size_t)nmax * sizeof(int32_t);                           // sort scratch
+    }
+    if (p->field_order > 2)  // line-solve coefficients: at most min(N, 127) per axis
+        for (int d = 0; d < 3; ++d) b += (size_t)(p->n[d] < 127 ? p->n[d] : 127) * sizeof(double);
+    b += (size_t)nsp * (nb + 1) * sizeof(int32_t);                        // per-species offsets
+    return b;
+}
+
+static void make_geom_host(const pp_params* p, Geom& g) {
+    for (int d = 0; d < 3; ++d) g.n[d] = p->n[d];
+    choose_tiles(g.n, g.t);
+    for (int d = 0; d < 3; ++d) g.nt[d] = (g.n[d] + g.t[d] - 1) / g.t[d];
+    g.ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    g.ntiles = (int64_t)g.nt[0] * g.nt[1] * g.nt[2];
+    g.nbins = g.ntiles * TILE_CELLS;
+}
+
+pp_status pp_workspace_size(const pp_params* params, int64_t max_particles, int32_t nspecies, size_t* bytes) {
+    if (!bytes) return PP_E_ARG;
+    *bytes = 0;
+    pp_status st = validate(params);
+    if (st != PP_OK) return st;
+    if (max_particles < 0 || nspecies < 0 || nspecies > PP_MAX_SPECIES) return PP_E_ARG;
+    if (max_particles >= INT32_MAX) return PP_E_CAPACITY;
+    Geom g;
+    make_geom_host(params, g);
+    if (g.nbins + 1 > INT32_MAX) return PP_E_CAPACITY;
+    *bytes = internal_bytes(params, g, max_particles, nspecies);
+    return PP_OK;
+}
+
 pp_status pp_create(const pp_params* params, const pp_mesh* mesh, void* hip_stream, pp_run** out) {
     if (!out) return PP_E_ARG;
     *out = nullptr;
@@ -142,12 +185,7 @@ pp_status pp_create(const pp_params* params, const pp_mesh* mesh, void* hip_stre
     r->mesh = *mesh;
     r->stream = (hipStream_t)hip_stream;
     Geom& g = r->g;
-    for (int d = 0; d < 3; ++d) g.n[d] = params->n[d];
-    choose_tiles(g.n, g.t);
-    for (int d = 0; d < 3; ++d) g.nt[d] = (g.n[d] + g.t[d] - 1) / g.t[d];
-    g.ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    g.ntiles = (int64_t)g.nt[0] * g.nt[1] * g.nt[2];
-    g.nbins = g.ntiles * TILE_CELLS;
+    make_geom_host(params, g);
     if (g.nbins + 1 > INT32_MAX) {
         delete r;
         return PP_E_CAPACITY;

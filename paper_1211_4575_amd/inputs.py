@@ -278,6 +278,58 @@ def kelvin_helmholtz(seed=SEED_BASE, n=(1024, 512, 1), ppc=64, mass_ratio=25.0, 
 
 
 # ---------------------------------------------------------------------------------------------
+# Serving ensemble: a stream of small two-stream runs (a parameter scan)
+# ---------------------------------------------------------------------------------------------
+SERVING_GRIDS = ((32, 32, 32), (64, 32, 32), (128, 16, 16))
+SERVING_LATTICES = ((2, 2, 2), (4, 2, 2), (4, 4, 2), (4, 4, 4))  # 8, 16, 32, 64 per cell per beam
+
+
+@dataclass
+class TwoStreamRequest:
+    """One request: a two-stream run (the loader :func:`two_stream` with these settings) of
+    ``steps`` steps, arriving ``arrival`` seconds after the stream starts."""
+    rid: int
+    arrival: float
+    n: tuple
+    per_dim: tuple
+    v_beam: float
+    uth: float
+    steps: int
+    seed: int
+    dx: float = 0.1
+    cfl: float = 0.4
+    wl_id: int = 5
+
+    @property
+    def ppc(self) -> int:
+        return self.per_dim[0] * self.per_dim[1] * self.per_dim[2]
+
+    @property
+    def n_per_beam(self) -> int:
+        return self.n[0] * self.n[1] * self.n[2] * self.ppc
+
+    @property
+    def updates(self) -> int:
+        return 2 * self.n_per_beam * self.steps
+
+
+def serving_requests(count=256, rate=1.0, seed=SEED_BASE, steps=(200, 2000), v_beam=(0.1, 0.5), uth=0.01,
+                     grids=SERVING_GRIDS, lattices=SERVING_LATTICES):
+    """Poisson stream of ``count`` two-stream requests at ``rate`` per second: grid and
+    lattice uniform over the given sets, beam speed uniform in ``v_beam``, step count uniform
+    over the integers in ``steps``; request i draws its particles with seed ``seed + 1 + i``."""
+    rng = np.random.Generator(np.random.Philox(key=seed))
+    gaps = rng.exponential(1.0 / rate, count)
+    t = np.cumsum(gaps)
+    g = rng.integers(0, len(grids), count)
+    lat = rng.integers(0, len(lattices), count)
+    v = rng.uniform(v_beam[0], v_beam[1], count)
+    k = rng.integers(steps[0], steps[1] + 1, count)
+    return [TwoStreamRequest(i, float(t[i]), tuple(grids[g[i]]), tuple(lattices[lat[i]]), float(v[i]), float(uth),
+                             int(k[i]), seed + 1 + i) for i in range(count)]
+
+
+# ---------------------------------------------------------------------------------------------
 # Split-precision form: integer cell (nearest cell centre) + in-cell offset in [-1/2, 1/2)
 # ---------------------------------------------------------------------------------------------
 def to_split(pos: np.ndarray, n, dtype=np.float32):

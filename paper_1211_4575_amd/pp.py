@@ -21,7 +21,7 @@ PP_MAX_SPECIES = 8
 PP_FLAG_CFL, PP_FLAG_NONFINITE, PP_FLAG_OUT_OF_TILE = 1, 2, 4
 PP_DIAG_MOMENTS, PP_DIAG_FIELDS, PP_DIAG_RHO, PP_DIAG_DIVB, PP_DIAG_ALL = 1, 2, 4, 8, 15
 
-EXPORTED = ("pp_create", "pp_init_species", "pp_gather_push_deposit", "pp_field_step", "pp_sort_particles",
+EXPORTED = ("pp_workspace_size", "pp_create", "pp_init_species", "pp_gather_push_deposit", "pp_field_step", "pp_sort_particles",
             "pp_diagnostics", "pp_get_particles", "pp_timing_enable", "pp_timing_read", "pp_destroy",
             "pp_status_str", "pp_last_hip_error", "pp_batch_create", "pp_batch_add", "pp_batch_remove",
             "pp_batch_size", "pp_batch_step", "pp_batch_destroy")
@@ -101,6 +101,8 @@ def lib():
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_1211_4575_amd.build.build()")
         L = ctypes.CDLL(LIB_PATH)
         vp = ctypes.c_void_p
+        L.pp_workspace_size.argtypes = [ctypes.POINTER(pp_params), ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_size_t)]
         L.pp_create.argtypes = [ctypes.POINTER(pp_params), ctypes.POINTER(pp_mesh), vp, ctypes.POINTER(vp)]
         L.pp_init_species.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.POINTER(pp_particles)]
@@ -135,6 +137,13 @@ def _check(where, st):
 
 
 # ---- the C calls, same names ------------------------------------------------------------
+def pp_workspace_size(params: pp_params, max_particles: int, nspecies: int) -> int:
+    b = ctypes.c_size_t()
+    _check("pp_workspace_size", lib().pp_workspace_size(ctypes.byref(params), int(max_particles), int(nspecies),
+                                                        ctypes.byref(b)))
+    return b.value
+
+
 def pp_create(params: pp_params, mesh: pp_mesh, stream: int) -> ctypes.c_void_p:
     h = ctypes.c_void_p()
     _check("pp_create", lib().pp_create(ctypes.byref(params), ctypes.byref(mesh), ctypes.c_void_p(stream),

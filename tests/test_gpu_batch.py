@@ -158,3 +158,33 @@ def test_batch_rejects_what_it_cannot_batch(ppm, orc):
         assert ppm.pp_batch_size(batch) == 1
     finally:
         ppm.pp_batch_destroy(batch)
+
+
+def test_serving_scheduler_results_equal_alone(ppm):
+    """Requests served through the scheduler (arrivals overlapping, continuous batching) end in
+    the same state as each request stepped alone: energies from the FP64 diagnostics (whose
+    reductions may sum in another order: 1e-12 relative)."""
+    import torch
+    from paper_1211_4575_amd import serve as S
+    reqs = I.serving_requests(count=6, rate=400.0, seed=99, steps=(3, 12), grids=((16, 16, 16), (32, 16, 16)),
+                              lattices=((1, 1, 1), (2, 1, 1)))
+    be = S.DeviceBackend(max_slots=4)
+    try:
+        sch = S.Scheduler(be, mem_budget=1 << 34, max_slots=4)
+        res = sch.run(reqs)
+        _say("serve", S.summarize(res), "peak members", sch.peak_members)
+        assert sch.peak_members >= 2
+        for r, q in zip(res, reqs):
+            assert r.status == "ok" and r.info["step"] == q.steps
+            run = be.make_run(q, split=True)
+            for _ in range(q.steps):
+                run.step()
+            d = run.diagnostics(ppm.PP_DIAG_MOMENTS | ppm.PP_DIAG_FIELDS)
+            run.close()
+            assert d.flags == 0
+            for key, v in (("kinetic", d.kinetic[0] + d.kinetic[1]), ("field_E", d.field_E), ("field_B", d.field_B),
+                           ("field_Ex", d.field_Ex)):
+                assert abs(r.info[key] - v) <= 1e-12 * abs(v) + 1e-300, (q.rid, key, r.info[key], v)
+    finally:
+        be.close()
+    torch.cuda.synchronize()
