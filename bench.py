@@ -46,7 +46,7 @@ def make_pair_mj_run(pp, ind, torch, n, ppc, theta, split, with_id=False):
     chunk = 1 << 26
     for start in range(0, npart, chunk):
         cnt = min(chunk, npart - start)
-        ind.pair_maxwell_juttner(SEED, n, start, cnt, theta, split,
+        ind.pair_maxwell_juttner(SEED, n, start, cnt, theta, ind.split_mode(split, 3),
                                  [c[start:] for c in cells] if split else None,
                                  [[o[d, start:] for d in range(3)] for o in offs],
                                  [[u[d, start:] for d in range(3)] for u in us], st)
@@ -164,7 +164,15 @@ def serving_bench(args, torch, pp):
     be = S.DeviceBackend(max_slots=args.slots)
     log(f"[serve] {len(reqs)} requests, rate {args.rate}/s, {sum(r.updates for r in reqs):.3e} updates, "
         f"budget {args.mem_gib} GiB, {args.slots} slots")
-    sched = S.Scheduler(be, mem_budget=int(args.mem_gib * (1 << 30)), max_slots=args.slots)
+    done = []
+
+    def progress(r, members):
+        done.append(r)
+        if len(done) % 8 == 0 or len(done) == len(reqs):
+            log(f"[serve] {len(done)}/{len(reqs)} done at t={r.done:.1f} s (request {r.rid}: latency "
+                f"{r.latency:.2f} s, {r.status}), {members} runs in the batch")
+
+    sched = S.Scheduler(be, mem_budget=int(args.mem_gib * (1 << 30)), max_slots=args.slots, on_complete=progress)
     t0 = time.perf_counter()
     res = sched.run(reqs)
     wall = time.perf_counter() - t0

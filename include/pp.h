@@ -102,9 +102,14 @@ typedef struct pp_mesh {
 
 /* Caller-owned particle storage of one species, structure of arrays (device).
  *  PP_PREC_FP64:       pos[d] -> double X_d in cell units, [0, n_d);  cell unused.
- *  PP_PREC_FP32_SPLIT: cell   -> int32 linear index i + n0*(j + n1*k) of the cell
- *                                 whose centre is nearest (i = floor(X + 1/2) mod n0);
- *                      pos[d] -> float offset X_d - i in [-1/2, 1/2).
+ *  PP_PREC_FP32_SPLIT: cell   -> int32 linear index i + n0*(j + n1*k) of the particle's
+ *                                 cell, pos[d] -> float offset X_d - i in [lo, lo + 2):
+ *                      lo = -1/2 for shape_order 2, 0 for shape_order 3.  A loader
+ *                      gives i = floor(X - lo) mod n0 (offset in [lo, lo + 1): the
+ *                      nearest node for quadratic, the node below for cubic weights).
+ *                      The push keeps a particle whose last displacement, repeated, would
+ *                      cross the lower face of its cell in the cell below (offset in
+ *                      [lo + 1, lo + 2)), so that the stencils of the next step line up.
  *  u[d]: proper velocity (double for FP64, float for FP32_SPLIT).
  *  id:   optional int64 tag per particle carried along by the sort (NULL = none).
  *  *_alt: a second buffer of the same types and length (the sort writes there and

@@ -30,9 +30,11 @@ int ppi_philox_blocks(uint64_t seed, uint32_t block, uint32_t stream, int64_t ct
 /* Pair-loaded relativistic pair plasma (electron = species 0, positron = species 1 at the
  * same positions), Maxwell-Juettner momenta at kT/mc^2 = theta, for particle indices
  * [start, start + count) of a box of n[0] x n[1] x n[2] cells with ppc particles per cell per
- * species.  split = 1: cell (int32, x-fastest index of the nearest cell centre), off[3]
- * (float offsets in [-1/2,1/2)), u[3] (float).  split = 0: off[3] are double positions in
- * cell units and u[3] double; cell is unused.  Arrays of species s are cell[s], off[s][d],
+ * species.  split = 1: cell (int32, x-fastest index of the nearest node), off[3] (float
+ * offsets in [-1/2,1/2)), u[3] (float); split = 2: the same with the node below and offsets
+ * in [0,1) (the split form of libpp for quadratic and for cubic weights respectively);
+ * split = 0: off[3] are double positions in cell units and u[3] double; cell is unused.
+ * Returns 0, or -1 for invalid arguments.  Arrays of species s are cell[s], off[s][d],
  * u[s][d] (device pointers to element 0 of the slice). */
 int ppi_pair_maxwell_juttner(uint64_t seed, const int32_t n[3], int64_t start, int64_t count, double theta,
                              int32_t split, int32_t* const cell[2], void* const off[2][3], void* const u[2][3],

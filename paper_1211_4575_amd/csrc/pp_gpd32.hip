@@ -1,14 +1,21 @@
 // Split-precision form of steps 1-3 (Sec. III), tiled.  Particles: int32 cell index +
-// FP32 offset from the cell centre in [-1/2, 1/2) + FP32 proper velocity (the paper's
-// integer cell + fraction storage, Sec. V.B), stored per tile in round-major order (see
-// pp_sort.hip): 64 consecutive particles sit in 64 different cells of the tile.
+// FP32 offset inside the cell + FP32 proper velocity (the paper's integer cell + fraction
+// storage, Sec. V.B).  The offset is measured from the nearest node (lo = -1/2) for quadratic
+// weights and from the node below (lo = 0) for cubic weights and lies in [lo, lo + 1), so
+// that the centred support starts one node below the cell; a particle whose last
+// displacement, repeated, would take it across the lower face of its cell is kept in the
+// cell below with its offset in [lo + 1, lo + 2).  Then the current window of the next step
+// (old and new support) starts 2 nodes below the cell for almost every particle.
+// Particles are stored per tile in round-major order (see pp_sort.hip): 64 consecutive
+// particles sit in 64 different cells of the tile, so the 64 lanes of a wavefront touch 64
+// aligned stencils, which the padded LDS layout spreads over all banks.
 //
 // One workgroup (4 wavefronts) per tile of 64 cells:
 //   1. stage E and B of the tile plus a 2-node halo from the FP64 mesh into LDS as FP32;
 //   2. each wavefront takes 64 consecutive particles at a time (coalesced loads and
 //      stores): gather (LDS) -> push (registers) -> move and renormalise the split
 //      position -> Esirkepov current (registers) -> LDS accumulation of the tile's current
-//      block (3-node halo);
+//      block (halo of 2 nodes below and O + 1 above);
 //   3. flush the current block to the global accumulator with 64-bit integer atomics.
 // Current accumulation is exact 64-bit fixed point.  Each contribution P_a * F * fac is
 // formed in FP64 by one fused multiply-add with the rounding constant 1.5*2^52, whose bit
@@ -67,18 +74,38 @@ __device__ __forceinline__ long long fixed_sum(unsigned long long v) {
     return (long long)((v & LOW51) ^ (unsigned long long)BIT50) - BIT50;
 }
 
+// Padded row and plane strides (64-bit elements) of the current block.  The 64 lanes of a
+// round hold one particle per cell, so an accumulation instruction touches 64 addresses laid
+// out like the tile's cells.  A 64-bit LDS access covers a pair of the 32 banks and is served
+// 16 lanes at a time; lanes 16g..16g+15 are the 4x4 cells of one z layer (or two x rows of
+// a flat 8x8 tile), and a row stride of 12 (24) puts those 16 addresses on 16 different bank
+// pairs.  A plane stride that is a multiple of 16 keeps a window moved by one z layer on its
+// bank pairs.
+constexpr int cur_row_444 = 12;
+constexpr int cur_plane_444(int O) { return O == 2 ? 112 : 128; }
+constexpr int cur_row_881 = 24;
+
 // LDS layout of a tile: compile-time for the common shapes, runtime otherwise.  A
 // single-cell axis is collapsed (extent 1, stride 0): every node offset maps to plane 0.
-template <int TX, int TY, int TZ, bool CZ>
+// The current block is indexed x + crow*y + cplane*z (padding entries stay zero).
+template <int O, int TX, int TY, int TZ, bool CZ>
 struct TileCT {
     static constexpr int tx = TX, ty = TY, tz = TZ;
     static constexpr int flox = FLD_LO, floy = FLD_LO, floz = CZ ? 0 : FLD_LO;
-    static constexpr int clox = CUR_LO, cloy = CUR_LO, cloz = CZ ? 0 : CUR_LO;
-    static constexpr int fex = TX + 4, fey = TY + 4, fez = CZ ? 1 : TZ + 4;
-    static constexpr int cex = TX + 6, cey = TY + 6, cez = CZ ? 1 : TZ + 6;
+    static constexpr int clox = cur_lo(O), cloy = cur_lo(O), cloz = CZ ? 0 : cur_lo(O);
+    static constexpr int fex = TX + FLD_LO + fld_hi(O), fey = TY + FLD_LO + fld_hi(O);
+    static constexpr int fez = CZ ? 1 : TZ + FLD_LO + fld_hi(O);
+    static constexpr int cex = TX + cur_lo(O) + cur_hi(O), cey = TY + cur_lo(O) + cur_hi(O);
+    static constexpr int cez = CZ ? 1 : TZ + cur_lo(O) + cur_hi(O);
     static constexpr int fsx = 1, fsy = fex, fsz = CZ ? 0 : fex * fey;
-    static constexpr int csx = 1, csy = cex, csz = CZ ? 0 : cex * cey;
-    static constexpr int fvol = fex * fey * fez, cvol = cex * cey * cez;
+    static constexpr bool t444 = TX == 4 && TY == 4 && TZ == 4 && !CZ;
+    static constexpr bool t881 = TX == 8 && TY == 8 && CZ;
+    static constexpr int crow = t444 ? cur_row_444 : (t881 ? cur_row_881 : cex);
+    static constexpr int cplane = t444 ? cur_plane_444(O) : crow * cey;
+    static_assert(crow >= cex, "current row padding");
+    static_assert(cplane >= crow * cey, "current plane padding");
+    static constexpr int csx = 1, csy = crow, csz = CZ ? 0 : cplane;
+    static constexpr int fvol = fex * fey * fez, cvol = cplane * cez;
     __device__ TileCT(const Gpd32Args&) {}
 };
 
@@ -87,6 +114,7 @@ struct TileRT {
     int flox, floy, floz, clox, cloy, cloz;
     int fex, fey, fez, cex, cey, cez;
     int fsx, fsy, fsz, csx, csy, csz;
+    int crow, cplane;
     int fvol, cvol;
     __device__ TileRT(const Gpd32Args& A) {
         tx = A.t[0];
@@ -107,29 +135,46 @@ struct TileRT {
         fsx = A.n[0] > 1 ? 1 : 0;
         fsy = A.n[1] > 1 ? fex : 0;
         fsz = A.n[2] > 1 ? fex * fey : 0;
+        crow = cex;
+        cplane = cex * cey;
         csx = A.n[0] > 1 ? 1 : 0;
-        csy = A.n[1] > 1 ? cex : 0;
-        csz = A.n[2] > 1 ? cex * cey : 0;
+        csy = A.n[1] > 1 ? crow : 0;
+        csz = A.n[2] > 1 ? cplane : 0;
         fvol = fex * fey * fez;
-        cvol = cex * cey * cez;
+        cvol = cplane * cez;
     }
 };
 
-// weights of the centred and staggered node sets for offset f in [-1/2, 1/2) of a
-// particle in cell c; returned base offsets are relative to c.
+// Lower end of the offset range of the split form (see the header).
+template <int O>
+__device__ __forceinline__ constexpr float off_lo() {
+    return O == 2 ? -0.5f : 0.0f;
+}
+
+template <int O>
+__device__ __forceinline__ bool offset_ok(float f) {
+    return f >= off_lo<O>() && f < off_lo<O>() + 2.0f;
+}
+
+// weights of the centred and staggered node sets for offset f of a particle in cell c;
+// returned base offsets are relative to c.
 template <int O>
 __device__ __forceinline__ void split_weights(float f, float* wc, int& bc, float* ws, int& bs) {
-    const float fl = f < 0.0f ? -1.0f : 0.0f;
     if (O == 2) {
-        weights_frac<2, float>(f, wc);  // nodes c-1..c+1
-        bc = -1;
-        weights_frac<2, float>(f - 0.5f - fl, ws);  // staggered nodes start at c-1+fl
-        bs = -1 + (int)fl;
+        const float cn = floorf(f + 0.5f);  // nearest node: 0 or 1
+        weights_frac<2, float>(f - cn, wc);  // nodes c-1+cn .. c+1+cn
+        bc = -1 + (int)cn;
+        const float cs = floorf(f);  // nearest staggered node c+cs+1/2, cs in -1..1
+        weights_frac<2, float>(f - 0.5f - cs, ws);
+        bs = -1 + (int)cs;
     } else {
+        const float fl = floorf(f);  // 0 or 1
         weights_frac<3, float>(f - fl, wc);  // nodes c-1+fl .. c+2+fl
         bc = -1 + (int)fl;
-        weights_frac<3, float>(f + 0.5f, ws);  // staggered nodes c-2 .. c+1
-        bs = -2;
+        const float y = f - 0.5f;  // position on the staggered lattice
+        const float fy = floorf(y);  // -1, 0 or 1
+        weights_frac<3, float>(y - fy, ws);
+        bs = -1 + (int)fy;
     }
 }
 
@@ -232,8 +277,7 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
             const bool inside = rel >= 0 && li < L.tx && org[0] + li < n0 && org[1] + lj < n1 && org[2] + lk < n2 &&
                                 (int64_t)(org[0] + li) + (int64_t)n0 * ((org[1] + lj) + (int64_t)n1 * (org[2] + lk)) ==
                                     (int64_t)cell;
-            if (!inside || !(f[0] >= -0.5f && f[0] < 0.5f) || !(f[1] >= -0.5f && f[1] < 0.5f) ||
-                !(f[2] >= -0.5f && f[2] < 0.5f)) {
+            if (!inside || !offset_ok<O>(f[0]) || !offset_ok<O>(f[1]) || !offset_ok<O>(f[2])) {
                 bad_all |= PP_FLAG_OUT_OF_TILE;
                 continue;
             }
@@ -266,14 +310,15 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
 
             const float ig = rsqrtf(1.0f + dot(u, u) * A.ic * A.ic);
             const float uu[3] = {u.x, u.y, u.z};
-            float x1[3];
+            float x1[3], dxs[3];
             int bad = 0;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const float dd = A.dt * uu[d] * ig * A.inv_d[d];
                 if (!(fabsf(dd) < 1.0f)) bad |= isfinite(dd) ? PP_FLAG_CFL : PP_FLAG_NONFINITE;
                 if (!isfinite(uu[d])) bad |= PP_FLAG_NONFINITE;
-                x1[d] = f[d] + dd;  // new position relative to the old cell centre
+                x1[d] = f[d] + dd;  // new position relative to the old cell's node
+                dxs[d] = dd;
             }
             if (bad) {
                 bad_all |= bad;
@@ -342,27 +387,31 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
                 }
             }
 
-            // renormalise: new cell = old cell + round(x1), offset back into [-1/2, 1/2)
+            // renormalise: new cell and offset in [lo, lo + 1), or in [lo + 1, lo + 2) in the
+            // cell below when the same displacement again would cross the lower face
             int nc3[3];
             float fn[3];
             const int gc[3] = {org[0] + li, org[1] + lj, org[2] + lk};
+            const float lo = off_lo<O>();
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                float sh = floorf(x1[d] + 0.5f);
+                float sh = floorf(x1[d] - lo);
                 float o = x1[d] - sh;
-                // x1 + 1/2 can round up onto an integer: keep the offset in [-1/2, 1/2)
-                if (o < -0.5f) {
+                // rounding can land the offset just outside the range: move it back in
+                if (o < lo) {
                     o += 1.0f;
                     sh -= 1.0f;
-                } else if (o >= 0.5f) {
+                } else if (o >= lo + 1.0f) {
                     o -= 1.0f;
                     sh += 1.0f;
                 }
+                const float up = o + 1.0f;
+                if (o + dxs[d] < lo && up < lo + 2.0f) {
+                    o = up;
+                    sh -= 1.0f;
+                }
                 fn[d] = o;
-                int v = gc[d] + (int)sh;
-                if (v < 0) v += A.n[d];
-                if (v >= A.n[d]) v -= A.n[d];
-                nc3[d] = v;
+                nc3[d] = wrap(gc[d] + (int)sh, A.n[d]);
             }
             S.cell[p] = nc3[0] + n0 * (nc3[1] + n1 * nc3[2]);
             S.pos[0][p] = fn[0];
@@ -382,9 +431,11 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
         if (v == 0) continue;
         const int comp = q / L.cvol;
         const int r = q - comp * L.cvol;
-        const int a = r % L.cex;
-        const int bb = (r / L.cex) % L.cey;
-        const int c = r / (L.cex * L.cey);
+        const int c = r / L.cplane;
+        const int rr = r - c * L.cplane;
+        const int bb = rr / L.crow;
+        const int a = rr - bb * L.crow;
+        if (bb >= L.cey) continue;  // padding
         const int gi = wrap(org[0] - L.clox + a, n0);
         const int gj = wrap(org[1] - L.cloy + bb, n1);
         const int gk = wrap(org[2] - L.cloz + c, n2);
@@ -481,17 +532,21 @@ static int tile_kind(const pp_run* r) {
 static void lds_extents(const pp_run* r, int fe[3], int ce[3], int flo[3], int clo[3]) {
     for (int d = 0; d < 3; ++d) {
         const bool single = r->p.n[d] == 1;
-        fe[d] = single ? 1 : r->g.t[d] + FLD_LO + FLD_HI;
-        ce[d] = single ? 1 : r->g.t[d] + CUR_LO + CUR_HI;
+        fe[d] = single ? 1 : r->g.t[d] + FLD_LO + fld_hi(r->p.shape_order);
+        ce[d] = single ? 1 : r->g.t[d] + cur_lo(r->p.shape_order) + cur_hi(r->p.shape_order);
         flo[d] = single ? 0 : FLD_LO;
-        clo[d] = single ? 0 : CUR_LO;
+        clo[d] = single ? 0 : cur_lo(r->p.shape_order);
     }
 }
 
 size_t gpd32_lds_bytes(const pp_run* r) {
     int fe[3], ce[3], flo[3], clo[3];
     lds_extents(r, fe, ce, flo, clo);
-    const size_t fv = (size_t)fe[0] * fe[1] * fe[2], cv = (size_t)ce[0] * ce[1] * ce[2];
+    const size_t fv = (size_t)fe[0] * fe[1] * fe[2];
+    const int kind = tile_kind(r);
+    const size_t cv = kind == TILE_444       ? (size_t)cur_plane_444(r->p.shape_order) * ce[2]
+                      : kind == TILE_881_FLAT ? (size_t)cur_row_881 * ce[1]
+                                              : (size_t)ce[0] * ce[1] * ce[2];
     return ((6 * fv * sizeof(float) + 15) & ~(size_t)15) + 3 * cv * sizeof(unsigned long long);
 }
 
@@ -589,16 +644,16 @@ hipError_t launch_gpd32(pp_run* r, double* J) {
     const int kind = tile_kind(r);
     if (r->p.shape_order == 2) {
         if (kind == TILE_444)
-            hipLaunchKernelGGL((k_gpd32<2, TileCT<4, 4, 4, false>>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
+            hipLaunchKernelGGL((k_gpd32<2, TileCT<2, 4, 4, 4, false>>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
         else if (kind == TILE_881_FLAT)
-            hipLaunchKernelGGL((k_gpd32<2, TileCT<8, 8, 1, true>>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
+            hipLaunchKernelGGL((k_gpd32<2, TileCT<2, 8, 8, 1, true>>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
         else
             hipLaunchKernelGGL((k_gpd32<2, TileRT>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
     } else {
         if (kind == TILE_444)
-            hipLaunchKernelGGL((k_gpd32<3, TileCT<4, 4, 4, false>>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
+            hipLaunchKernelGGL((k_gpd32<3, TileCT<3, 4, 4, 4, false>>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
         else if (kind == TILE_881_FLAT)
-            hipLaunchKernelGGL((k_gpd32<3, TileCT<8, 8, 1, true>>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
+            hipLaunchKernelGGL((k_gpd32<3, TileCT<3, 8, 8, 1, true>>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
         else
             hipLaunchKernelGGL((k_gpd32<3, TileRT>), dim3(grid), dim3(GPD32_BS), lds, r->stream, A);
     }
@@ -620,10 +675,10 @@ hipError_t launch_gpd32_batch(const void* args_table, const int64_t* tile_prefix
                        (int)FX_ZERO);
     const Gpd32Args* T = (const Gpd32Args*)args_table;
     if (shape_order == 2)
-        hipLaunchKernelGGL((k_gpd32_batch<2, TileCT<4, 4, 4, false>>), dim3((unsigned)total_tiles), dim3(GPD32_BS), lds,
+        hipLaunchKernelGGL((k_gpd32_batch<2, TileCT<2, 4, 4, 4, false>>), dim3((unsigned)total_tiles), dim3(GPD32_BS), lds,
                            st, T, tile_prefix, n);
     else
-        hipLaunchKernelGGL((k_gpd32_batch<3, TileCT<4, 4, 4, false>>), dim3((unsigned)total_tiles), dim3(GPD32_BS), lds,
+        hipLaunchKernelGGL((k_gpd32_batch<3, TileCT<3, 4, 4, 4, false>>), dim3((unsigned)total_tiles), dim3(GPD32_BS), lds,
                            st, T, tile_prefix, n);
     hipLaunchKernelGGL(k_fixed_batch, dim3((unsigned)total_fixed_blocks), dim3(256), 0, st, F, fixed_prefix, n,
                        (int)FX_TO_F64);

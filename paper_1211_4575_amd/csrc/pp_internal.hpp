@@ -14,12 +14,18 @@ namespace pp {
 // one cell per lane of a wavefront); key = tile * 64 + local cell.  Tiles at the upper
 // edge may be partial (cells outside the box never receive particles).
 constexpr int TILE_CELLS = 64;
-// LDS halo of the field tile (nodes below / above the tile) and of the current tile.
-constexpr int FLD_LO = 2, FLD_HI = 2;
-constexpr int CUR_LO = 3, CUR_HI = 3;
-// split form: the round-major order is rebuilt at the first sort and then every this many
-// sorts of a species (the bucketing sort in between keeps most of it)
-constexpr int REORDER_EVERY = 4;
+// LDS halo of the field tile (nodes below / above the tile) and of the current tile.  A split
+// particle's offset lies in [lo, lo + 2) (lo = -1/2 for O = 2, 0 for O = 3), so its supports
+// start between 2 nodes below and 1 node above its cell; the current window (O + 2 nodes
+// per axis, covering the old and the new support) ends at most O + 1 nodes above its start.
+constexpr int FLD_LO = 2;
+constexpr int fld_hi(int O) { return O == 2 ? 2 : 3; }
+constexpr int cur_lo(int) { return 2; }
+constexpr int cur_hi(int O) { return O + 1; }
+// split form: the round-major order is rebuilt every this many sorts of a species.  Every
+// sort: one step of motion moves about half of the particles to another cell, and a round
+// whose particles no longer sit one per cell makes the LDS accumulation conflict.
+constexpr int REORDER_EVERY = 1;
 
 struct Geom {
     int n[3];       // cells

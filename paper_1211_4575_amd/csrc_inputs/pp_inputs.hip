@@ -48,6 +48,26 @@ __device__ __forceinline__ uint32_t stream_id(int wl, int sp, int purpose) {
     return (uint32_t)((wl << 8) | (sp << 4) | purpose);
 }
 
+// Split form of positions X[3] in [0, n): mode 1 = nearest node (offset in [-1/2, 1/2)),
+// mode 2 = node below (offset in [0, 1)); the offset is rounded to float and a particle whose
+// rounded offset lands on the upper end of the range moves to the next cell.
+__device__ __forceinline__ int32_t to_split(const double* X, const int* n, int mode, float* off) {
+    const double lo = mode == 1 ? -0.5 : 0.0;
+    int64_t ijk[3];
+    for (int d = 0; d < 3; ++d) {
+        double c = floor(X[d] - lo);
+        float o = (float)(X[d] - c);
+        if (o >= (float)(lo + 1.0)) {  // the moved particle starts the next cell's range
+            c += 1.0;
+            o = fmaxf((float)(X[d] - c), (float)lo);
+        }
+        off[d] = o;
+        int64_t ci = (int64_t)c % n[d];
+        ijk[d] = ci < 0 ? ci + n[d] : ci;
+    }
+    return (int32_t)(ijk[0] + (int64_t)n[0] * (ijk[1] + (int64_t)n[1] * ijk[2]));
+}
+
 __global__ void k_philox_blocks(uint64_t seed, uint32_t block, uint32_t stream, int64_t ctr0, int64_t count,
                                 uint32_t* out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -85,21 +105,7 @@ __global__ void __launch_bounds__(256) k_pair_mj(MJArgs A) {
     }
     int32_t cellv = 0;
     float offf[3];
-    if (A.split) {
-        int64_t ijk[3];
-        for (int d = 0; d < 3; ++d) {
-            double c = floor(pos[d] + 0.5);
-            float o = (float)(pos[d] - c);
-            if (o >= 0.5f) {
-                c += 1.0;
-                o = (float)(pos[d] - c);
-            }
-            offf[d] = o;
-            int64_t ci = (int64_t)c % A.n[d];
-            ijk[d] = ci < 0 ? ci + A.n[d] : ci;
-        }
-        cellv = (int32_t)(ijk[0] + (int64_t)A.n[0] * (ijk[1] + (int64_t)A.n[1] * ijk[2]));
-    }
+    if (A.split) cellv = to_split(pos, A.n, A.split, offf);
     for (int s = 0; s < 2; ++s) {
         // Sobol rejection: attempt t uses draw blocks 2t, 2t+1
         double mag = 0.0;
@@ -159,21 +165,7 @@ __global__ void __launch_bounds__(256) k_two_stream(TSArgs A) {
     const double X[3] = {((double)ix + 0.5) / A.k[0], ((double)iy + 0.5) / A.k[1], ((double)iz + 0.5) / A.k[2]};
     int32_t cellv = 0;
     float offf[3];
-    if (A.split) {
-        int64_t ijk[3];
-        for (int d = 0; d < 3; ++d) {
-            double c = floor(X[d] + 0.5);
-            float o = (float)(X[d] - c);
-            if (o >= 0.5f) {
-                c += 1.0;
-                o = (float)(X[d] - c);
-            }
-            offf[d] = o;
-            int64_t ci = (int64_t)c % A.n[d];
-            ijk[d] = ci < 0 ? ci + A.n[d] : ci;
-        }
-        cellv = (int32_t)(ijk[0] + (int64_t)A.n[0] * (ijk[1] + (int64_t)A.n[1] * ijk[2]));
-    }
+    if (A.split) cellv = to_split(X, A.n, A.split, offf);
     for (int s = 0; s < 2; ++s) {
         double U[4];
         uniform_pair(A.seed, (uint64_t)p, 0, stream_id(A.wl, s, 1), U[0], U[1]);
@@ -219,7 +211,8 @@ int ppi_two_stream_lattice(uint64_t seed, int32_t wl, const int32_t n[3], const 
     A.drift[0] = v_beam * g0;
     A.drift[1] = -v_beam * g0;
     A.uth = uth;
-    A.split = split ? 1 : 0;
+    if (split < 0 || split > 2) return -1;
+    A.split = split;
     for (int s = 0; s < 2; ++s) {
         A.cell[s] = cell ? cell[s] : nullptr;
         if (split && !A.cell[s]) return -1;
@@ -258,7 +251,8 @@ int ppi_pair_maxwell_juttner(uint64_t seed, const int32_t n[3], int64_t start, i
     A.start = start;
     A.count = count;
     A.theta = theta;
-    A.split = split ? 1 : 0;
+    if (split < 0 || split > 2) return -1;
+    A.split = split;
     for (int s = 0; s < 2; ++s) {
         A.cell[s] = cell ? cell[s] : nullptr;
         if (split && !A.cell[s]) return -1;

@@ -332,16 +332,26 @@ def serving_requests(count=256, rate=1.0, seed=SEED_BASE, steps=(200, 2000), v_b
 # ---------------------------------------------------------------------------------------------
 # Split-precision form: integer cell (nearest cell centre) + in-cell offset in [-1/2, 1/2)
 # ---------------------------------------------------------------------------------------------
-def to_split(pos: np.ndarray, n, dtype=np.float32):
-    """(cell linear index int32 x-fastest, offsets [3, n] in ``dtype``) of positions in [0, N).
-    The offset is rounded to ``dtype``; :func:`from_split` gives the exactly represented
-    position of that rounded state."""
-    ijk = np.floor(pos + 0.5)
+def split_origin(shape_order: int) -> str:
+    """Offset convention of the split form for a weight order: the nearest node (offset in
+    [-1/2, 1/2)) for quadratic weights, the node below (offset in [0, 1)) for cubic weights,
+    so that the centred support of every particle starts one node below its cell."""
+    return "nearest" if shape_order == 2 else "floor"
+
+
+def to_split(pos: np.ndarray, n, dtype=np.float32, origin="nearest"):
+    """(cell linear index int32 x-fastest, offsets [3, n] in ``dtype``) of positions in [0, N),
+    the cell being the nearest node (``origin="nearest"``, offset in [-1/2, 1/2)) or the node
+    below (``origin="floor"``, offset in [0, 1)).  The offset is rounded to ``dtype``;
+    :func:`from_split` gives the exactly represented position of that rounded state."""
+    lo = {"nearest": -0.5, "floor": 0.0}[origin]
+    ijk = np.floor(pos - lo)
     off = (pos - ijk).astype(dtype)
-    # rounding can push an offset onto +1/2; move such particles to the next cell
-    bump = off >= dtype(0.5)
+    # rounding can push an offset onto the upper end of the range; move such particles on
+    bump = off >= dtype(lo + 1.0)
     ijk = ijk + bump
-    off = np.where(bump, (pos - ijk).astype(dtype), off)
+    # the moved particle sits a rounding error below the new cell's range: put it at its start
+    off = np.where(bump, np.maximum((pos - ijk).astype(dtype), dtype(lo)), off)
     ijk = ijk.astype(np.int64)
     for d in range(3):
         ijk[d] %= n[d]

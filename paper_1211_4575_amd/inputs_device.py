@@ -9,6 +9,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpp_inputs.so")
 _lib = None
 
+FP64, SPLIT_NEAREST, SPLIT_FLOOR = 0, 1, 2
+
+
+def split_mode(split: bool, shape_order: int) -> int:
+    """Generator output mode for a run: FP64 positions, or the split form whose offset
+    convention goes with the weight order (nearest node for quadratic, node below for cubic)."""
+    if not split:
+        return FP64
+    return SPLIT_NEAREST if shape_order == 2 else SPLIT_FLOOR
+
 
 def lib():
     global _lib

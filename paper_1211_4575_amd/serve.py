@@ -69,8 +69,9 @@ class Scheduler:
     ``max_inflight`` bounds how many batch steps the host enqueues ahead of the device, so
     that a new arrival joins within about that many steps."""
 
-    def __init__(self, backend, mem_budget: int, max_slots: int, max_inflight: int = 2):
+    def __init__(self, backend, mem_budget: int, max_slots: int, max_inflight: int = 2, on_complete=None):
         self.be = backend
+        self.on_complete = on_complete  # called with each Result as it completes
         self.mem_budget = int(mem_budget)
         self.max_slots = int(max_slots)
         self.max_inflight = max(1, int(max_inflight))
@@ -93,6 +94,8 @@ class Scheduler:
                 used -= need
                 results.append(Result(req.rid, req.arrival, t_adm, t_done, req.steps, req.updates,
                                       "ok" if flags == 0 else "failed", flags, info))
+                if self.on_complete is not None:
+                    self.on_complete(results[-1], len(active))
 
         be.start()
         while pending or active or inflight:
@@ -199,7 +202,8 @@ class DeviceBackend:
         cells = [torch.empty(npart, dtype=torch.int32, device=self.dev) for _ in range(2)] if split else None
         offs = [torch.empty((3, npart), dtype=rt, device=self.dev) for _ in range(2)]
         us = [torch.empty((3, npart), dtype=rt, device=self.dev) for _ in range(2)]
-        self.ind.two_stream_lattice(req.seed, req.wl_id, req.n, req.per_dim, req.v_beam, req.uth, int(split), cells,
+        self.ind.two_stream_lattice(req.seed, req.wl_id, req.n, req.per_dim, req.v_beam, req.uth,
+                                    self.ind.split_mode(split, 3), cells,
                                     [[o[d] for d in range(3)] for o in offs], [[u[d] for d in range(3)] for u in us],
                                     self.stream.cuda_stream)
         species = []

@@ -39,10 +39,10 @@ RUNS = [
 ]
 
 
-def _split_species(species, n):
+def _split_species(species, n, O):
     out = []
     for s in species:
-        cell, off = I.to_split(s["pos"], n)
+        cell, off = I.to_split(s["pos"], n, origin=I.split_origin(O))
         out.append(dict(q=s["q"], m=s["m"], w=s["w"], cell=cell, off=off, u=s["u"].astype(np.float32)))
     return out
 
@@ -52,7 +52,7 @@ def _make(ppm, orc, k):
     species, E, B = random_state(orc, n, ppc, seed=700 + k, d=d)
     P = ppm.make_params(n=n, d=d, dt=dt, shape_order=3, field_order=fo, pusher=pusher,
                         precision=ppm.PP_PREC_FP32_SPLIT, relax_tol=1e-14, relax_max_iter=200)
-    return ppm.Run(P, _split_species(species, n), E=E, B=B)
+    return ppm.Run(P, _split_species(species, n, 3), E=E, B=B)
 
 
 def _state(run):
@@ -132,7 +132,7 @@ def test_batch_rejects_what_it_cannot_batch(ppm, orc):
         # a flat box (8x8x1 tiles)
         species, E, B = random_state(orc, (16, 16, 1), 2, seed=4)
         Pf = ppm.make_params(n=(16, 16, 1), shape_order=3, field_order=2, precision=ppm.PP_PREC_FP32_SPLIT)
-        rf = ppm.Run(Pf, _split_species(species, (16, 16, 1)), E=E, B=B)
+        rf = ppm.Run(Pf, _split_species(species, (16, 16, 1), 3), E=E, B=B)
         with pytest.raises(ppm.PPError):
             ppm.pp_batch_add(batch, rf.handle)
         # capacity, duplicates, other weight order
@@ -142,7 +142,7 @@ def test_batch_rejects_what_it_cannot_batch(ppm, orc):
             ppm.pp_batch_add(batch, ra.handle)
         species, E, B = random_state(orc, (8, 8, 8), 2, seed=5)
         P2 = ppm.make_params(n=(8, 8, 8), shape_order=2, field_order=2, precision=ppm.PP_PREC_FP32_SPLIT)
-        r2 = ppm.Run(P2, _split_species(species, (8, 8, 8)), E=E, B=B)
+        r2 = ppm.Run(P2, _split_species(species, (8, 8, 8), 2), E=E, B=B)
         with pytest.raises(ppm.PPError):
             ppm.pp_batch_add(batch, r2.handle)
         ppm.pp_batch_add(batch, rb.handle)

@@ -22,7 +22,7 @@ def test_device_philox_matches_host():
     assert np.array_equal(got, np.stack(ref, axis=1))
 
 
-@pytest.mark.parametrize("split", [0, 1])
+@pytest.mark.parametrize("split", [0, 1, 2])
 def test_device_pair_mj_matches_host(split):
     import torch
     from paper_1211_4575_amd import inputs_device as ind
@@ -40,7 +40,7 @@ def test_device_pair_mj_matches_host(split):
         u = us[s].cpu().numpy().astype(np.float64)
         uref = wl.species[s].u
         if split:
-            cell, off = I.to_split(wl.species[s].pos, n)
+            cell, off = I.to_split(wl.species[s].pos, n, origin="nearest" if split == 1 else "floor")
             assert np.array_equal(cells[s].cpu().numpy(), cell)
             assert np.array_equal(offs[s].cpu().numpy(), off)
             close = np.all(np.abs(u - uref) <= 1e-6 * (1 + np.abs(uref)), axis=0)
@@ -50,7 +50,7 @@ def test_device_pair_mj_matches_host(split):
         assert close.mean() > 0.999
 
 
-@pytest.mark.parametrize("split", [0, 1])
+@pytest.mark.parametrize("split", [0, 1, 2])
 def test_device_two_stream_matches_host(split):
     import torch
     from paper_1211_4575_amd import inputs_device as ind
@@ -68,7 +68,7 @@ def test_device_two_stream_matches_host(split):
         u = us[s].cpu().numpy().astype(np.float64)
         uref = wl.species[s].u
         if split:
-            cell, off = I.to_split(wl.species[s].pos, n)
+            cell, off = I.to_split(wl.species[s].pos, n, origin="nearest" if split == 1 else "floor")
             assert np.array_equal(cells[s].cpu().numpy(), cell)
             assert np.array_equal(offs[s].cpu().numpy(), off)
             assert np.array_equal(us[s].cpu().numpy(), uref.astype(np.float32)) or \

@@ -76,10 +76,10 @@ def test_fp64_one_step_matches_oracle(ppm, orc, ci):
     run.close()
 
 
-def _split_species(species, n):
+def _split_species(species, n, O):
     out = []
     for s in species:
-        cell, off = I.to_split(s["pos"], n)
+        cell, off = I.to_split(s["pos"], n, origin=I.split_origin(O))
         u32 = s["u"].astype(np.float32)
         out.append(dict(q=s["q"], m=s["m"], w=s["w"], cell=cell, off=off, u=u32,
                         pos=I.from_split(cell, off, n), u64=u32.astype(np.float64)))
@@ -102,7 +102,7 @@ def test_fp32_split_one_step_matches_oracle(ppm, orc, ci):
     n, ppc, O, fo = case
     _say("fp32 one step", case)
     species, E, B = random_state(orc, n, ppc, seed=200 + ci, uth=0.2)
-    sp32 = _split_species(species, n)
+    sp32 = _split_species(species, n, O)
     kw = dict(n=n, dt=0.4, shape_order=O, field_order=fo, relax_tol=1e-14, relax_max_iter=200)
     P = orc.make_params(**kw)
     ref = _orc_run(orc, P, [dict(s, u=s["u64"]) for s in sp32], E, B)
@@ -118,9 +118,41 @@ def test_fp32_split_one_step_matches_oracle(ppm, orc, ci):
         X = I.from_split(g["cell"], g["pos"], n)
         assert np.max(np.abs(periodic_diff(X, sp["pos"], n))) < 1e-6
         assert rel_inf(g["u"].astype(np.float64), sp["u"]) < 1e-5
-        assert np.all(g["pos"] >= -0.5) and np.all(g["pos"] < 0.5)
+        lo = -0.5 if O == 2 else 0.0
+        assert np.all(g["pos"] >= lo) and np.all(g["pos"] < lo + 2.0)
     dg = run.diagnostics()
     assert dg.flags == 0
+    run.close()
+
+
+@pytest.mark.parametrize("O", [2, 3])
+def test_fp32_split_several_steps_match_oracle(ppm, orc, O):
+    # from the second step on, particles that keep moving down sit in the cell below with an
+    # offset in [lo + 1, lo + 2): positions, current and fields must still follow the oracle
+    n = (12, 8, 8)
+    _say("fp32 several steps", O)
+    species, E, B = random_state(orc, n, 3, seed=11, uth=0.4)
+    sp32 = _split_species(species, n, O)
+    kw = dict(n=n, dt=0.4, shape_order=O, field_order=6, relax_tol=1e-14, relax_max_iter=200)
+    ref = _orc_run(orc, orc.make_params(**kw), [dict(s, u=s["u64"]) for s in sp32], E, B)
+    run = ppm.Run(ppm.make_params(precision=ppm.PP_PREC_FP32_SPLIT, **kw), sp32, E=E, B=B)
+    lo = -0.5 if O == 2 else 0.0
+    moved_down = 0
+    for step in range(4):
+        ref.step()
+        run.step()
+        Eg, Bg, Jg = run.fields()
+        assert rel_l2(Jg, ref.J) < 1e-5, step
+        assert rel_l2(Eg - E, ref.E - E) < 1e-5, step
+        assert rel_l2(Bg - B, ref.B - B) < 1e-5, step
+        for s, sp in enumerate(ref.species):
+            g = _by_id(run.particles(s))
+            X = I.from_split(g["cell"], g["pos"], n)
+            assert np.max(np.abs(periodic_diff(X, sp["pos"], n))) < 1e-6, step
+            assert np.all(g["pos"] >= lo) and np.all(g["pos"] < lo + 2.0)
+            moved_down += int(np.sum(g["pos"] >= lo + 1.0))
+    assert moved_down > 0
+    assert run.diagnostics().flags == 0
     run.close()
 
 
@@ -132,7 +164,7 @@ def test_fp32_gauss_residual_one_step(ppm, orc):
     species, E, B = random_state(orc, n, 8, seed=3, uth=0.2)
     P = orc.make_params(n=n, field_order=6)
     E = orc.curl_down(P, E)  # divergence free: the 6th-order down divergence of a down curl vanishes
-    sp32 = _split_species(species, n)
+    sp32 = _split_species(species, n, 3)
     for s in sp32[1:]:  # keep the pair exactly co-located after rounding
         s["cell"], s["off"] = sp32[0]["cell"], sp32[0]["off"]
     run = ppm.Run(ppm.make_params(n=n, shape_order=3, field_order=6, precision=ppm.PP_PREC_FP32_SPLIT), sp32, E=E,
@@ -190,7 +222,7 @@ def test_sort_is_a_permutation_by_cell(ppm, orc):
         change = np.flatnonzero(np.diff(cells) != 0)
         assert len(change) + 1 == len(np.unique(cells))
     run.close()
-    sp32 = _split_species(species, n)
+    sp32 = _split_species(species, n, 3)
     run = ppm.Run(ppm.make_params(n=n, shape_order=3, field_order=2, precision=ppm.PP_PREC_FP32_SPLIT), sp32, E=E,
                   B=B)
     run.step()
@@ -219,7 +251,7 @@ def test_host_validation_rejects_bad_params(ppm):
 def test_fp32_push_requires_sort(ppm, orc):
     n = (8, 8, 4)
     species, E, B = random_state(orc, n, 2, seed=5)
-    run = ppm.Run(ppm.make_params(n=n, precision=ppm.PP_PREC_FP32_SPLIT), _split_species(species, n))
+    run = ppm.Run(ppm.make_params(n=n, precision=ppm.PP_PREC_FP32_SPLIT), _split_species(species, n, 2))
     run.gather_push_deposit()
     with pytest.raises(ppm.PPError) as ei:
         run.gather_push_deposit()

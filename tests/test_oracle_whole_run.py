@@ -101,13 +101,20 @@ def test_philox_known_answers():
         assert tuple(int(x) for x in I.philox4x32(*ctr, *key)) == exp
 
 
-def test_split_roundtrip():
+@pytest.mark.parametrize("origin", ["nearest", "floor"])
+def test_split_roundtrip(origin):
     rng = np.random.default_rng(0)
     n = (16, 8, 4)
     pos = rng.uniform(0, 1, (3, 1000)) * np.array(n)[:, None]
     pos[:, 0] = [15.9999999999, 7.5, 3.5]
-    cell, off = I.to_split(pos, n)
-    assert off.dtype == np.float32 and np.all(off >= -0.5) and np.all(off < 0.5)
+    pos[:, 1] = [2.9999999999, 0.4999999999, 0.0]
+    cell, off = I.to_split(pos, n, origin=origin)
+    lo = -0.5 if origin == "nearest" else 0.0
+    assert off.dtype == np.float32 and np.all(off >= lo) and np.all(off < lo + 1.0)
+    ijk = np.stack([cell % n[0], (cell // n[0]) % n[1], cell // (n[0] * n[1])])
+    base = np.floor(pos + 0.5) if origin == "nearest" else np.floor(pos)
+    moved = (ijk - base.astype(np.int64)) % np.array(n)[:, None]
+    assert np.all((moved == 0) | (moved == 1))  # the cell, or the next one after rounding up
     back = I.from_split(cell, off, n)
     dist = np.abs(back - pos)
     dist = np.minimum(dist, np.array(n)[:, None] - dist)
