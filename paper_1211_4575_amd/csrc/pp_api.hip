@@ -18,7 +18,7 @@ void set_hip_error(hipError_t e, const char* where) {
 }
 
 // defined in the kernel translation units
-void field_setup(pp_run* r);
+hipError_t field_setup(pp_run* r);
 int line_setup_axis(int order, int N, double* coef_host, int* off);
 int64_t scan_tmp_size(int64_t n);
 int diag_acc_count();
@@ -91,6 +91,7 @@ static void release(pp_run* r) {
     f(r->Jq);
     f(r->tile_max);
     f(r->qscale);
+    f(r->omega);
     for (int d = 0; d < 3; ++d) f(r->line[d].coef);
     for (int s = 0; s < PP_MAX_SPECIES; ++s) f(r->sp[s].offsets);
     if (r->ev0) (void)hipEventDestroy(r->ev0);
@@ -140,6 +141,7 @@ static size_t internal_bytes(const pp_params* p, const Geom& g, int64_t nmax, in
     b += 2 * nc * sizeof(double);                                          // rho, rho_prev
     b += nb * sizeof(int32_t) + (size_t)scan_tmp_size(g.nbins + 1) * sizeof(int32_t);
     b += sizeof(int32_t) + ((size_t)diag_acc_count() + 8) * sizeof(double);
+    b += ((size_t)p->relax_max_iter + 2) * sizeof(double);  // relaxation weights
     if (p->precision == PP_PREC_FP32_SPLIT) {
         b += n3 * sizeof(long long) + PP_MAX_SPECIES * sizeof(int32_t) + sizeof(double);
         b += 2 * (size_t)nmax * sizeof(int32_t);                           // sort scratch
@@ -197,6 +199,7 @@ pp_status pp_create(const pp_params* params, const pp_mesh* mesh, void* hip_stre
     okk = okk && dmalloc(&r->rho, (size_t)g.ncell) && dmalloc(&r->rho_prev, (size_t)g.ncell);
     okk = okk && dmalloc(&r->sort_cursor, (size_t)g.nbins) && dmalloc(&r->scan_tmp, (size_t)scan_tmp_size(g.nbins + 1));
     okk = okk && dmalloc(&r->flags, 1) && dmalloc(&r->dacc, (size_t)diag_acc_count() + 8);
+    okk = okk && dmalloc(&r->omega, (size_t)params->relax_max_iter + 2);
     if (params->precision == PP_PREC_FP32_SPLIT) {
         okk = okk && dmalloc(&r->Jq, n3) && dmalloc(&r->tile_max, PP_MAX_SPECIES) && dmalloc(&r->qscale, 1) &&
               ok(hipMemset(r->tile_max, 0, PP_MAX_SPECIES * sizeof(int32_t)), "hipMemset");
@@ -242,7 +245,11 @@ pp_status pp_create(const pp_params* params, const pp_mesh* mesh, void* hip_stre
         delete r;
         return PP_E_HIP;
     }
-    field_setup(r);
+    if (!ok(field_setup(r), "field_setup")) {
+        release(r);
+        delete r;
+        return PP_E_HIP;
+    }
     *out = r;
     return PP_OK;
 }

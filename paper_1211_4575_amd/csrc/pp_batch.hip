@@ -169,7 +169,7 @@ pp_status pp_batch_step(pp_batch* b) {
         field_desc(r, (FieldDesc*)(H + o_field + i * field_desc_size()));
         tpre[i + 1] = tpre[i] + r->g.ntiles;
         fpre[i + 1] = fpre[i] + (3 * r->g.ncell + 255) / 256;
-        cpre[i + 1] = cpre[i] + (r->g.ncell + 255) / 256;
+        cpre[i + 1] = cpre[i] + field_blocks(r);
         max_sweeps = r->jac_sweeps > max_sweeps ? r->jac_sweeps : max_sweeps;
     }
     int64_t* lpre = (int64_t*)(H + o_lpre);
@@ -177,7 +177,7 @@ pp_status pp_batch_step(pp_batch* b) {
     for (int j = 0; j < nl; ++j) {
         pp_run* r = b->runs[line_runs[j]];
         line_desc(r, r->J2, r->mesh.J, (LineArgs*)(H + o_line + j * line_desc_size()));
-        lpre[j + 1] = lpre[j] + (r->g.ncell + 255) / 256;
+        lpre[j + 1] = lpre[j] + field_blocks(r);
     }
     int64_t stot[PP_MAX_SPECIES][7];
     std::vector<char> reorder(n, 0);

@@ -6,6 +6,10 @@
 
 namespace pp {
 
+// Threads of a field launch: a block of 256 threads covers rows of x-consecutive cells
+// (a row of nx cells, padded to a power of two, several rows per block) or, for nx > 256, a
+// 256-cell chunk of one row; the remaining indices j, k come from the row number.  All
+// indices are 32-bit (a box has at most 2^30 cells).
 struct FieldGeom {
     int n[3];
     int64_t nc;
@@ -13,28 +17,56 @@ struct FieldGeom {
     double a[3][3];  // a[axis][m-1] / d[axis]: first-derivative coefficients
     int R;           // Laplacian half-width 2M - 1
     double L[3][11]; // Laplacian stencil per axis, offsets -R..R
+    int xchunks;     // 256-cell chunks per row (nx > 256), else 1
+    int xbits;       // log2 of the padded row length inside a block (<= 8)
+    int rows;        // ny * nz
+    int rpb;         // rows per block
+    double inv_ny;   // 1 / ny (row -> j, k)
+    int small;       // an axis shorter than the stencil reach: general wrap
 };
 
-__device__ __forceinline__ int nb(int i, int o, int n) {
+constexpr int FIELD_BS = 256;
+
+// index o cells away from i on a periodic axis of n cells
+__device__ __forceinline__ int nbw(int i, int o, int n, int small) {
     int j = i + o;
-    while (j < 0) j += n;
-    while (j >= n) j -= n;
-    return j;
+    if (small) {
+        j %= n;
+        return j < 0 ? j + n : j;
+    }
+    return j < 0 ? j + n : (j >= n ? j - n : j);
 }
 
-__device__ __forceinline__ int64_t lin(const FieldGeom& G, int i, int j, int k) {
-    return (int64_t)i + (int64_t)G.n[0] * ((int64_t)j + (int64_t)G.n[1] * k);
+// cell of thread t in block b of a run's launch; false for padding threads
+__device__ __forceinline__ bool field_cell(const FieldGeom& G, int64_t b, int t, int& i, int& j, int& k) {
+    const int xc = (int)(b % G.xchunks);
+    const int64_t rb = b / G.xchunks;
+    i = xc * FIELD_BS + (t & ((1 << G.xbits) - 1));
+    const int64_t row = rb * G.rpb + (t >> G.xbits);
+    if (i >= G.n[0] || row >= G.rows) return false;
+    k = (int)floor(((double)row + 0.5) * G.inv_ny);
+    j = (int)(row - (int64_t)k * G.n[1]);
+    if (j < 0) {
+        j += G.n[1];
+        --k;
+    } else if (j >= G.n[1]) {
+        j -= G.n[1];
+        ++k;
+    }
+    return true;
 }
+
+__device__ __forceinline__ int lin(const FieldGeom& G, int i, int j, int k) { return i + G.n[0] * (j + G.n[1] * k); }
 
 // up-shifted derivative along axis ax of f (values on integer nodes along ax) at cell (i,j,k):
 // sum_m a_m (f[i+m] - f[i-m+1]) / d
 __device__ __forceinline__ double dup(const FieldGeom& G, const double* __restrict__ f, int ax, int i, int j, int k) {
-    int c[3] = {i, j, k};
+    const int c[3] = {i, j, k};
     double s = 0.0;
     for (int m = 1; m <= G.M; ++m) {
         int hi[3] = {i, j, k}, lo[3] = {i, j, k};
-        hi[ax] = nb(c[ax], m, G.n[ax]);
-        lo[ax] = nb(c[ax], -m + 1, G.n[ax]);
+        hi[ax] = nbw(c[ax], m, G.n[ax], G.small);
+        lo[ax] = nbw(c[ax], -m + 1, G.n[ax], G.small);
         s += G.a[ax][m - 1] * (f[lin(G, hi[0], hi[1], hi[2])] - f[lin(G, lo[0], lo[1], lo[2])]);
     }
     return s;
@@ -42,23 +74,28 @@ __device__ __forceinline__ double dup(const FieldGeom& G, const double* __restri
 
 // down-shifted derivative: sum_m a_m (g[i+m-1] - g[i-m]) / d
 __device__ __forceinline__ double ddn(const FieldGeom& G, const double* __restrict__ f, int ax, int i, int j, int k) {
-    int c[3] = {i, j, k};
+    const int c[3] = {i, j, k};
     double s = 0.0;
     for (int m = 1; m <= G.M; ++m) {
         int hi[3] = {i, j, k}, lo[3] = {i, j, k};
-        hi[ax] = nb(c[ax], m - 1, G.n[ax]);
-        lo[ax] = nb(c[ax], -m, G.n[ax]);
+        hi[ax] = nbw(c[ax], m - 1, G.n[ax], G.small);
+        lo[ax] = nbw(c[ax], -m, G.n[ax], G.small);
         s += G.a[ax][m - 1] * (f[lin(G, hi[0], hi[1], hi[2])] - f[lin(G, lo[0], lo[1], lo[2])]);
     }
     return s;
 }
 
+// composed Laplacian (d- after d+) of f at (i,j,k)
 __device__ __forceinline__ double lap(const FieldGeom& G, const double* __restrict__ f, int i, int j, int k) {
+    const int nx = G.n[0], nxy = G.n[0] * G.n[1];
+    const int rowx = nx * (j + G.n[1] * k);
+    const int colyz = i + nxy * k;
+    const int colzx = i + nx * j;
     double s = 0.0;
     for (int o = -G.R; o <= G.R; ++o) {
-        s += G.L[0][o + G.R] * f[lin(G, nb(i, o, G.n[0]), j, k)];
-        s += G.L[1][o + G.R] * f[lin(G, i, nb(j, o, G.n[1]), k)];
-        s += G.L[2][o + G.R] * f[lin(G, i, j, nb(k, o, G.n[2]))];
+        s += G.L[0][o + G.R] * f[rowx + nbw(i, o, nx, G.small)];
+        s += G.L[1][o + G.R] * f[colyz + nx * nbw(j, o, G.n[1], G.small)];
+        s += G.L[2][o + G.R] * f[colzx + nxy * nbw(k, o, G.n[2], G.small)];
     }
     return s;
 }
@@ -73,28 +110,22 @@ struct FieldDesc {
     double* Bn;  // copy of B^n
     double* Bw;  // relaxation partner
     double* R;   // right-hand side
+    const double* omega;        // Chebyshev weights omega_k, k = 1..sweeps (device)
     double cab, dt, cj;         // alpha beta s, dt, alpha c^2 mu0 dt^2   (s = c^2 dt^2)
-    double al2s, inv_diag;      // alpha^2 s, 1 / diagonal
+    double al2s, gdiag;         // alpha^2 s, gamma / diagonal
     double al, be, c2dt, mu0;   // alpha, beta, c^2 dt, mu0
     int sweeps;
 };
 
-__device__ __forceinline__ void cell_ijk(const FieldGeom& G, int64_t q, int& i, int& j, int& k) {
-    i = (int)(q % G.n[0]);
-    j = (int)((q / G.n[0]) % G.n[1]);
-    k = (int)(q / ((int64_t)G.n[0] * G.n[1]));
-}
-
-__device__ __forceinline__ void copy_body(const FieldDesc& D, int64_t q) {
+__device__ __forceinline__ void copy_body(const FieldDesc& D, int q) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) D.Bn[c * D.G.nc + q] = D.B[c * D.G.nc + q];
 }
 
 // rhs = B + alpha beta s lap B - dt curl+ E + alpha c^2 mu0 dt^2 curl+ J   (B = B^n from Bn)
-__device__ __forceinline__ void rhs_body(const FieldDesc& D, int64_t q) {
+__device__ __forceinline__ void rhs_body(const FieldDesc& D, int i, int j, int k) {
     const FieldGeom& G = D.G;
-    int i, j, k;
-    cell_ijk(G, q, i, j, k);
+    const int q = lin(G, i, j, k);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int d1 = (c + 1) % 3, d2 = (c + 2) % 3;
@@ -105,29 +136,34 @@ __device__ __forceinline__ void rhs_body(const FieldDesc& D, int64_t q) {
     }
 }
 
-// sweep k (1-based) of Jacobi on (1 - al2s lap) x = rhs:  out = in + (rhs - in + al2s lap in) / diag.
-// The sweeps alternate between B and Bw so that the last one writes B.
-__device__ __forceinline__ void jacobi_body(const FieldDesc& D, int64_t q, int k) {
+// Sweep k (1-based) of the Chebyshev-accelerated Jacobi iteration for (1 - al2s lap) x = rhs:
+//   y = x_{k-1} + gamma (rhs - A x_{k-1}) / diag,   x_k = x_{k-2} + omega_k (y - x_{k-2}),
+// x_0 = x_{-1} = B^n (Bn), omega_1 = 1.  Iterate k lives in B when sweeps - k is even and in
+// Bw otherwise, so the last one is B and x_{k-2} shares x_k's array (each cell reads its own
+// old value before writing it).
+__device__ __forceinline__ void relax_body(const FieldDesc& D, int i, int j, int kk, int k) {
     const FieldGeom& G = D.G;
     const int m = D.sweeps;
-    const double* in = k == 1 ? D.Bn : (((m - k + 1) % 2 == 0) ? D.B : D.Bw);
     double* out = ((m - k) % 2 == 0) ? D.B : D.Bw;
-    int i, j, kk;
-    cell_ijk(G, q, i, j, kk);
+    const double* in = k == 1 ? D.Bn : (((m - k + 1) % 2 == 0) ? D.B : D.Bw);
+    const double* prev = k <= 2 ? D.Bn : out;
+    const double w = D.omega[k];
+    const int q = lin(G, i, j, kk);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double* x = in + c * G.nc;
-        double xq = x[q];
-        double Ax = xq - D.al2s * lap(G, x, i, j, kk);
-        out[c * G.nc + q] = xq + (D.R[c * G.nc + q] - Ax) * D.inv_diag;
+        const double xq = x[q];
+        const double Ax = xq - D.al2s * lap(G, x, i, j, kk);
+        const double y = xq + (D.R[c * G.nc + q] - Ax) * D.gdiag;
+        const double p = prev[c * G.nc + q];
+        out[c * G.nc + q] = p + w * (y - p);
     }
 }
 
 // E += c^2 dt (curl- (alpha B' + beta B) - mu0 J)
-__device__ __forceinline__ void update_E_body(const FieldDesc& D, int64_t q) {
+__device__ __forceinline__ void update_E_body(const FieldDesc& D, int i, int j, int k) {
     const FieldGeom& G = D.G;
-    int i, j, k;
-    cell_ijk(G, q, i, j, k);
+    const int q = lin(G, i, j, k);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int d1 = (c + 1) % 3, d2 = (c + 2) % 3;
@@ -139,29 +175,31 @@ __device__ __forceinline__ void update_E_body(const FieldDesc& D, int64_t q) {
 
 enum FieldPhase { PH_COPY = 0, PH_RHS = 1, PH_JACOBI = 2, PH_UPDATE_E = 3 };
 
-__device__ __forceinline__ void field_phase(const FieldDesc& D, int64_t q, int phase, int k) {
-    if (q >= D.G.nc) return;
+__device__ __forceinline__ void field_phase(const FieldDesc& D, int64_t b, int phase, int k) {
+    int i, j, kk;
+    if (!field_cell(D.G, b, threadIdx.x, i, j, kk)) return;
     if (phase == PH_COPY)
-        copy_body(D, q);
+        copy_body(D, lin(D.G, i, j, kk));
     else if (phase == PH_RHS)
-        rhs_body(D, q);
+        rhs_body(D, i, j, kk);
     else if (phase == PH_JACOBI) {
-        if (k <= D.sweeps) jacobi_body(D, q, k);
+        if (k <= D.sweeps) relax_body(D, i, j, kk, k);
     } else
-        update_E_body(D, q);
+        update_E_body(D, i, j, kk);
 }
 
-__global__ void __launch_bounds__(256) k_field(FieldDesc D, int phase, int k) {
-    field_phase(D, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, phase, k);
+__global__ void __launch_bounds__(FIELD_BS) k_field(FieldDesc D, int phase, int k) {
+    field_phase(D, blockIdx.x, phase, k);
 }
 
 // batched: block b belongs to run r with prefix[r] <= b < prefix[r+1] (prefix in blocks)
-__global__ void __launch_bounds__(256) k_field_batch(const FieldDesc* __restrict__ T, const int64_t* __restrict__ prefix,
-                                                     int nruns, int phase, int k) {
+__global__ void __launch_bounds__(FIELD_BS) k_field_batch(const FieldDesc* __restrict__ T,
+                                                          const int64_t* __restrict__ prefix, int nruns, int phase,
+                                                          int k) {
     const int64_t b = blockIdx.x;
     const int r = find_segment(prefix, nruns, b);
     if (r < 0) return;
-    field_phase(T[r], (b - prefix[r]) * blockDim.x + threadIdx.x, phase, k);
+    field_phase(T[r], b - prefix[r], phase, k);
 }
 
 static void fd_coeffs(int order, double a[3]) {
@@ -191,14 +229,39 @@ static FieldGeom make_geom(const pp_run* r) {
     G.R = r->lap_r;
     for (int d = 0; d < 3; ++d)
         for (int o = 0; o < 2 * G.R + 1; ++o) G.L[d][o] = r->lap[d][o];
+    const int nx = G.n[0];
+    if (nx >= FIELD_BS) {
+        G.xbits = 8;
+        G.xchunks = (nx + FIELD_BS - 1) / FIELD_BS;
+        G.rpb = 1;
+    } else {
+        G.xbits = 0;
+        while ((1 << G.xbits) < nx) ++G.xbits;
+        G.xchunks = 1;
+        G.rpb = FIELD_BS >> G.xbits;
+    }
+    G.rows = G.n[1] * G.n[2];
+    G.inv_ny = 1.0 / G.n[1];
+    G.small = 0;
+    for (int d = 0; d < 3; ++d)
+        if (G.n[d] < G.R || G.n[d] < G.M) G.small = 1;
     return G;
 }
 
+static int64_t blocks_of(const FieldGeom& G) { return (int64_t)G.xchunks * ((G.rows + G.rpb - 1) / G.rpb); }
+
+int64_t field_blocks(const pp_run* r) { return blocks_of(make_geom(r)); }
+
 // Host set-up of the field-step constants: the composed Laplacian stencil (d- after d+,
-// identical as a stencil to d+ after d-), the true diagonal of A = 1 - alpha^2 s lap on
-// this periodic grid, and the number of Jacobi sweeps from the exact spectral radius of
-// the (circulant) Jacobi iteration.
-void field_setup(pp_run* r) {
+// identical as a stencil to d+ after d-), the true diagonal of A = 1 - alpha^2 s lap on this
+// periodic grid, and the relaxation.  A is circulant, so the Jacobi iteration matrix
+// G = 1 - A / diag has its spectrum in [g0, g1] = [1 - amax/diag, 1 - 1/diag] exactly (amax
+// the largest eigenvalue of A, from the stencil's symbol).  The relaxation is Jacobi
+// extrapolated by gamma = 2 / (2 - g0 - g1), which centres that interval on 0 with radius
+// r = (g1 - g0) / (2 - g0 - g1), and accelerated by Chebyshev semi-iteration (Golub and
+// Varga 1961): after m sweeps the error is multiplied by at most 1 / T_m(1/r) (T_m the
+// Chebyshev polynomial), and m is the smallest count for which that is <= relax_tol.
+hipError_t field_setup(pp_run* r) {
     double a[3];
     fd_coeffs(r->p.field_order, a);
     const int M = r->p.field_order / 2;
@@ -234,18 +297,31 @@ void field_setup(pp_run* r) {
         amax -= al2s * mn;
     }
     r->diagA = diag;
-    double g1 = fabs(1.0 - 1.0 / diag), g2 = fabs(1.0 - amax / diag);
-    double rho = g1 > g2 ? g1 : g2;
-    r->jac_rho = rho;
+    const double g0 = 1.0 - amax / diag, g1 = 1.0 - 1.0 / diag;
+    r->jac_rho = fmax(fabs(g0), fabs(g1));
+    r->relax_gamma = 2.0 / (2.0 - g0 - g1);
+    const double rr = (g1 - g0) / (2.0 - g0 - g1);
+    r->relax_r = rr;
     int sweeps = 1;
-    if (rho > 0.0) {
-        double want = log(r->p.relax_tol) / log(rho);
-        sweeps = (int)ceil(want);
-        if (sweeps < 1) sweeps = 1;
+    double bound = 0.0;
+    if (rr > 1e-300) {
+        const double ac = acosh(1.0 / rr);
+        for (sweeps = 1; sweeps < r->p.relax_max_iter; ++sweeps)
+            if (1.0 / cosh(sweeps * ac) <= r->p.relax_tol) break;
+        bound = 1.0 / cosh(sweeps * ac);
     }
-    if (sweeps > r->p.relax_max_iter) sweeps = r->p.relax_max_iter;
     r->jac_sweeps = sweeps;
-    r->jac_bound = rho > 0.0 ? pow(rho, sweeps) : 0.0;
+    r->jac_bound = bound;
+    // omega_1 = 1, omega_2 = 1 / (1 - r^2/2), omega_{k+1} = 1 / (1 - r^2 omega_k / 4)
+    const int n_om = r->p.relax_max_iter + 2;
+    double* om = new (std::nothrow) double[n_om];
+    if (!om) return hipErrorOutOfMemory;
+    om[0] = 0.0;
+    om[1] = 1.0;
+    for (int k = 2; k < n_om; ++k) om[k] = k == 2 ? 1.0 / (1.0 - 0.5 * rr * rr) : 1.0 / (1.0 - 0.25 * rr * rr * om[k - 1]);
+    hipError_t e = hipMemcpy(r->omega, om, n_om * sizeof(double), hipMemcpyHostToDevice);
+    delete[] om;
+    return e;
 }
 
 void field_desc(const pp_run* r, FieldDesc* D) {
@@ -259,11 +335,12 @@ void field_desc(const pp_run* r, FieldDesc* D) {
     D->Bn = r->Bn;
     D->Bw = r->Bw;
     D->R = r->R;
+    D->omega = r->omega;
     D->cab = al * be * s;
     D->dt = dt;
     D->cj = al * c2 * mu0 * dt * dt;
     D->al2s = al * al * s;
-    D->inv_diag = 1.0 / r->diagA;
+    D->gdiag = r->relax_gamma / r->diagA;
     D->al = al;
     D->be = be;
     D->c2dt = c2 * dt;
@@ -276,8 +353,8 @@ size_t field_desc_size() { return sizeof(FieldDesc); }
 hipError_t launch_field_step(pp_run* r) {
     FieldDesc D;
     field_desc(r, &D);
-    const int bs = 256;
-    const dim3 grid((unsigned)((D.G.nc + bs - 1) / bs));
+    const int bs = FIELD_BS;
+    const dim3 grid((unsigned)blocks_of(D.G));
     hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_COPY, 0);
     hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_RHS, 0);
     for (int k = 1; k <= D.sweeps; ++k) hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_JACOBI, k);
@@ -291,11 +368,11 @@ hipError_t launch_field_step_batch(const void* table, const int64_t* prefix, int
     if (n == 0 || total_blocks == 0) return hipSuccess;
     const FieldDesc* T = (const FieldDesc*)table;
     const dim3 grid((unsigned)total_blocks);
-    hipLaunchKernelGGL(k_field_batch, grid, dim3(256), 0, st, T, prefix, n, (int)PH_COPY, 0);
-    hipLaunchKernelGGL(k_field_batch, grid, dim3(256), 0, st, T, prefix, n, (int)PH_RHS, 0);
+    hipLaunchKernelGGL(k_field_batch, grid, dim3(FIELD_BS), 0, st, T, prefix, n, (int)PH_COPY, 0);
+    hipLaunchKernelGGL(k_field_batch, grid, dim3(FIELD_BS), 0, st, T, prefix, n, (int)PH_RHS, 0);
     for (int k = 1; k <= max_sweeps; ++k)
-        hipLaunchKernelGGL(k_field_batch, grid, dim3(256), 0, st, T, prefix, n, (int)PH_JACOBI, k);
-    hipLaunchKernelGGL(k_field_batch, grid, dim3(256), 0, st, T, prefix, n, (int)PH_UPDATE_E, 0);
+        hipLaunchKernelGGL(k_field_batch, grid, dim3(FIELD_BS), 0, st, T, prefix, n, (int)PH_JACOBI, k);
+    hipLaunchKernelGGL(k_field_batch, grid, dim3(FIELD_BS), 0, st, T, prefix, n, (int)PH_UPDATE_E, 0);
     return hipGetLastError();
 }
 
@@ -307,43 +384,44 @@ hipError_t launch_field_step_batch(const void* table, const int64_t* prefix, int
 // coefficients; it is applied as a convolution along each component's own axis.
 // ---------------------------------------------------------------------------------------
 struct LineArgs {
-    int n[3];
-    int64_t nc;
+    FieldGeom G;
     const double* coef[3];
     int len[3], off[3];
     const double* J2;
     double* J;
 };
 
-__device__ __forceinline__ void line_body(const LineArgs& A, int64_t q) {
-    if (q >= A.nc) return;
-    const int ijk[3] = {(int)(q % A.n[0]), (int)((q / A.n[0]) % A.n[1]), (int)(q / ((int64_t)A.n[0] * A.n[1]))};
-    const int64_t stride[3] = {1, A.n[0], (int64_t)A.n[0] * A.n[1]};
+__device__ __forceinline__ void line_body(const LineArgs& A, int64_t b) {
+    int ijk[3];
+    if (!field_cell(A.G, b, threadIdx.x, ijk[0], ijk[1], ijk[2])) return;
+    const int nc = (int)A.G.nc;
+    const int q = lin(A.G, ijk[0], ijk[1], ijk[2]);
+    const int stride[3] = {1, A.G.n[0], A.G.n[0] * A.G.n[1]};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double* src = A.J2 + c * A.nc;
-        const int N = A.n[c];
-        const int64_t rowbase = q - (int64_t)ijk[c] * stride[c];
+        const double* src = A.J2 + (int64_t)c * nc;
+        const int N = A.G.n[c];
+        const int rowbase = q - ijk[c] * stride[c];
         double s = 0.0;
-        int idx = nb(ijk[c], A.off[c], N);
+        int idx = ijk[c] + A.off[c];
+        idx %= N;
+        if (idx < 0) idx += N;
         for (int jj = 0; jj < A.len[c]; ++jj) {
-            s += A.coef[c][jj] * src[rowbase + (int64_t)idx * stride[c]];
+            s += A.coef[c][jj] * src[rowbase + idx * stride[c]];
             if (++idx == N) idx = 0;
         }
-        A.J[c * A.nc + q] = s;
+        A.J[(int64_t)c * nc + q] = s;
     }
 }
 
-__global__ void __launch_bounds__(256) k_line_solve(LineArgs A) {
-    line_body(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-}
+__global__ void __launch_bounds__(FIELD_BS) k_line_solve(LineArgs A) { line_body(A, blockIdx.x); }
 
-__global__ void __launch_bounds__(256) k_line_solve_batch(const LineArgs* __restrict__ T, const int64_t* __restrict__ prefix,
-                                                          int nruns) {
+__global__ void __launch_bounds__(FIELD_BS) k_line_solve_batch(const LineArgs* __restrict__ T,
+                                                               const int64_t* __restrict__ prefix, int nruns) {
     const int64_t b = blockIdx.x;
     const int r = find_segment(prefix, nruns, b);
     if (r < 0) return;
-    line_body(T[r], (b - prefix[r]) * blockDim.x + threadIdx.x);
+    line_body(T[r], b - prefix[r]);
 }
 
 // Host: coefficients of T^{-1} on a periodic line of N cells, by the discrete Fourier
@@ -383,13 +461,12 @@ int line_setup_axis(int order, int N, double* coef_host, int* off) {
 }
 
 void line_desc(const pp_run* r, const double* J2, double* J, LineArgs* A) {
+    A->G = make_geom(r);
     for (int d = 0; d < 3; ++d) {
-        A->n[d] = r->p.n[d];
         A->coef[d] = r->line[d].coef;
         A->len[d] = r->line[d].len;
         A->off[d] = r->line[d].off;
     }
-    A->nc = r->g.ncell;
     A->J2 = J2;
     A->J = J;
 }
@@ -399,14 +476,14 @@ size_t line_desc_size() { return sizeof(LineArgs); }
 hipError_t launch_line_solve(pp_run* r, const double* J2, double* J) {
     LineArgs A;
     line_desc(r, J2, J, &A);
-    const int bs = 256;
-    hipLaunchKernelGGL(k_line_solve, dim3((unsigned)((A.nc + bs - 1) / bs)), dim3(bs), 0, r->stream, A);
+    hipLaunchKernelGGL(k_line_solve, dim3((unsigned)blocks_of(A.G)), dim3(FIELD_BS), 0, r->stream, A);
     return hipGetLastError();
 }
 
 hipError_t launch_line_solve_batch(const void* table, const int64_t* prefix, int n, int64_t total_blocks, hipStream_t st) {
     if (n == 0 || total_blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_line_solve_batch, dim3((unsigned)total_blocks), dim3(256), 0, st, (const LineArgs*)table, prefix, n);
+    hipLaunchKernelGGL(k_line_solve_batch, dim3((unsigned)total_blocks), dim3(FIELD_BS), 0, st, (const LineArgs*)table,
+                       prefix, n);
     return hipGetLastError();
 }
 

@@ -86,9 +86,12 @@ struct pp_run {
     double lap[3][16] = {};  // Laplacian stencil per axis, offsets -R..R (1/d^2 folded)
     int lap_r = 0;
     double diagA = 1.0;      // diagonal of (1 - alpha^2 c^2 dt^2 lap) on this grid
-    double jac_rho = 0.0;    // spectral radius of the Jacobi iteration
-    int jac_sweeps = 0;
-    double jac_bound = 0.0;  // jac_rho^sweeps
+    double jac_rho = 0.0;    // spectral radius of the plain Jacobi iteration
+    double relax_gamma = 1.0;  // Jacobi extrapolation factor
+    double relax_r = 0.0;    // spectral radius of the extrapolated iteration
+    int jac_sweeps = 0;      // relaxation sweeps per field step
+    double jac_bound = 0.0;  // error reduction bound after jac_sweeps sweeps
+    double* omega = nullptr; // Chebyshev weights (device, relax_max_iter + 2)
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timing = false;
@@ -115,6 +118,7 @@ hipError_t launch_gpd64(pp_run* r, int s, double* J);
 hipError_t launch_gpd32(pp_run* r, double* J);
 hipError_t launch_line_solve(pp_run* r, const double* J2, double* J);
 hipError_t launch_field_step(pp_run* r);
+int64_t field_blocks(const pp_run* r);  // blocks of one field / line-solve launch of this run
 hipError_t launch_sort(pp_run* r, int s, bool reorder);
 hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
