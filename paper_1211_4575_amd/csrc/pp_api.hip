@@ -92,6 +92,12 @@ static void release(pp_run* r) {
     f(r->tile_max);
     f(r->qscale);
     f(r->omega);
+    f(r->rounds);
+    for (int s = 0; s < PP_MAX_SPECIES; ++s) {
+        f(r->sp[s].cell_cnt);
+        f(r->sp[s].rank);
+        f(r->sp[s].offsets_next);
+    }
     for (int d = 0; d < 3; ++d) f(r->line[d].coef);
     for (int s = 0; s < PP_MAX_SPECIES; ++s) f(r->sp[s].offsets);
     if (r->ev0) (void)hipEventDestroy(r->ev0);
@@ -145,6 +151,9 @@ static size_t internal_bytes(const pp_params* p, const Geom& g, int64_t nmax, in
     if (p->precision == PP_PREC_FP32_SPLIT) {
         b += n3 * sizeof(long long) + PP_MAX_SPECIES * sizeof(int32_t) + sizeof(double);
         b += 2 * (size_t)nmax * sizeof(int32_t);                           // sort scratch
+        b += (size_t)g.ntiles * SORT_RCAP * sizeof(RoundEntry);            // round tables
+        // per species: cell counts, particle ranks, next tile starts
+        b += (size_t)nsp * (nc * sizeof(int32_t) + (size_t)nmax * sizeof(int32_t) + ((size_t)g.ntiles + 1) * sizeof(int32_t));
     }
     if (p->field_order > 2)  // line-solve coefficients: at most min(N, 127) per axis
         for (int d = 0; d < 3; ++d) b += (size_t)(p->n[d] < 127 ? p->n[d] : 127) * sizeof(double);
@@ -201,6 +210,7 @@ pp_status pp_create(const pp_params* params, const pp_mesh* mesh, void* hip_stre
     okk = okk && dmalloc(&r->flags, 1) && dmalloc(&r->dacc, (size_t)diag_acc_count() + 8);
     okk = okk && dmalloc(&r->omega, (size_t)params->relax_max_iter + 2);
     if (params->precision == PP_PREC_FP32_SPLIT) {
+        okk = okk && dmalloc(&r->rounds, (size_t)g.ntiles * SORT_RCAP);
         okk = okk && dmalloc(&r->Jq, n3) && dmalloc(&r->tile_max, PP_MAX_SPECIES) && dmalloc(&r->qscale, 1) &&
               ok(hipMemset(r->tile_max, 0, PP_MAX_SPECIES * sizeof(int32_t)), "hipMemset");
     }
@@ -268,6 +278,14 @@ pp_status pp_init_species(pp_run* r, int32_t s, double q, double m, double w, co
     }
     Species& S = r->sp[s];
     if (!S.offsets && !dmalloc(&S.offsets, (size_t)r->g.nbins + 1)) return PP_E_HIP;
+    if (split) {
+        if (!S.offsets_next && !dmalloc(&S.offsets_next, (size_t)r->g.ntiles + 1)) return PP_E_HIP;
+        if (!S.cell_cnt && !dmalloc(&S.cell_cnt, (size_t)r->g.ncell)) return PP_E_HIP;
+        if (!ok(launch_fill_i32(S.cell_cnt, r->g.ncell, 0, r->stream), "fill")) return PP_E_HIP;
+        if (S.rank) (void)hipFree(S.rank);
+        S.rank = nullptr;
+        if (!dmalloc(&S.rank, (size_t)parts->n)) return PP_E_HIP;
+    }
     if (split && parts->n > r->sort_scratch_n) {
         if (r->sort_scratch) (void)hipFree(r->sort_scratch);
         r->sort_scratch = nullptr;
@@ -287,8 +305,9 @@ pp_status pp_init_species(pp_run* r, int32_t s, double q, double m, double w, co
     }
     if (!parts->id) S.cur.id_alt = nullptr;
     S.sorted = false;
+    S.ranked = false;
     // initial sort: the split form needs it before its first push
-    hipError_t e = launch_sort(r, s, true);
+    hipError_t e = launch_sort(r, s);
     if (!ok(e, "sort")) return PP_E_HIP;
     return PP_OK;
 }
@@ -321,7 +340,10 @@ pp_status pp_gather_push_deposit(pp_run* r) {
         r->t_pending = true;
     }
     for (int s = 0; s < PP_MAX_SPECIES; ++s)
-        if (split) r->sp[s].sorted = false;
+        if (split && r->sp[s].active) {
+            r->sp[s].sorted = false;
+            r->sp[s].ranked = true;  // the kernel counted the new cells for the next sort
+        }
     if (r->p.field_order > 2) {
         e = launch_line_solve(r, r->J2, r->mesh.J);
         if (!ok(e, "line_solve")) return PP_E_HIP;
@@ -344,11 +366,9 @@ pp_status pp_sort_particles(pp_run* r, int32_t s) {
             if (s >= 0) return PP_E_STATE;
             continue;
         }
-        const bool reorder = (r->sorts_done % REORDER_EVERY) == REORDER_EVERY - 1;
-        hipError_t e = launch_sort(r, k, reorder);
+        hipError_t e = launch_sort(r, k);
         if (!ok(e, "sort")) return PP_E_HIP;
     }
-    r->sorts_done += 1;
     return PP_OK;
 }
 

@@ -140,11 +140,11 @@ pp_status pp_batch_step(pp_batch* b) {
     const size_t o_fpre = L.take((n + 1) * sizeof(int64_t));
     const size_t o_line = L.take((nl + 1) * line_desc_size());
     const size_t o_lpre = L.take((nl + 1) * sizeof(int64_t));
-    size_t o_sort[PP_MAX_SPECIES], o_spre[PP_MAX_SPECIES][7];
+    size_t o_sort[PP_MAX_SPECIES], o_spre[PP_MAX_SPECIES][SORT_BATCH_PHASES];
     for (int s = 0; s < PP_MAX_SPECIES; ++s) {
         const int ns = (int)slot_segs[s].size();
         o_sort[s] = L.take((ns + 1) * sort_desc_size());
-        for (int ph = 0; ph < 7; ++ph) o_spre[s][ph] = L.take((ns + 1) * sizeof(int64_t));
+        for (int ph = 0; ph < SORT_BATCH_PHASES; ++ph) o_spre[s][ph] = L.take((ns + 1) * sizeof(int64_t));
     }
     const size_t o_field = L.take(n * field_desc_size());
     const size_t o_cpre = L.take((n + 1) * sizeof(int64_t));
@@ -179,27 +179,22 @@ pp_status pp_batch_step(pp_batch* b) {
         line_desc(r, r->J2, r->mesh.J, (LineArgs*)(H + o_line + j * line_desc_size()));
         lpre[j + 1] = lpre[j] + field_blocks(r);
     }
-    int64_t stot[PP_MAX_SPECIES][7];
-    std::vector<char> reorder(n, 0);
-    for (int i = 0; i < n; ++i) {
-        pp_run* r = b->runs[i];
-        reorder[i] = (r->sorts_done % REORDER_EVERY) == REORDER_EVERY - 1;
-    }
+    int64_t stot[PP_MAX_SPECIES][SORT_BATCH_PHASES];
     for (int s = 0; s < PP_MAX_SPECIES; ++s) {
         const int ns = (int)slot_segs[s].size();
-        int64_t* pre[7];
-        for (int ph = 0; ph < 7; ++ph) {
+        int64_t* pre[SORT_BATCH_PHASES];
+        for (int ph = 0; ph < SORT_BATCH_PHASES; ++ph) {
             pre[ph] = (int64_t*)(H + o_spre[s][ph]);
             pre[ph][0] = 0;
         }
         for (int j = 0; j < ns; ++j) {
             const int i = slot_segs[s][j];
             sort_desc(b->runs[i], s, (SortDesc*)(H + o_sort[s] + j * sort_desc_size()));
-            int64_t blocks[7];
-            sort_desc_blocks(b->runs[i], s, reorder[i] != 0, blocks);
-            for (int ph = 0; ph < 7; ++ph) pre[ph][j + 1] = pre[ph][j] + blocks[ph];
+            int64_t blocks[SORT_BATCH_PHASES];
+            sort_desc_blocks(b->runs[i], s, blocks);
+            for (int ph = 0; ph < SORT_BATCH_PHASES; ++ph) pre[ph][j + 1] = pre[ph][j] + blocks[ph];
         }
-        for (int ph = 0; ph < 7; ++ph) stot[s][ph] = pre[ph][ns];
+        for (int ph = 0; ph < SORT_BATCH_PHASES; ++ph) stot[s][ph] = pre[ph][ns];
     }
 
     // ---- upload and launch -------------------------------------------------------------
@@ -217,9 +212,14 @@ pp_status pp_batch_step(pp_batch* b) {
     for (int s = 0; s < PP_MAX_SPECIES; ++s) {
         const int ns = (int)slot_segs[s].size();
         if (ns == 0) continue;
-        const int64_t* pre[7];
-        for (int ph = 0; ph < 7; ++ph) pre[ph] = (const int64_t*)(D + o_spre[s][ph]);
-        e = launch_sort_batch(D + o_sort[s], pre, stot[s], ns, b->stream);
+        const int64_t* pre[SORT_BATCH_PHASES];
+        for (int ph = 0; ph < SORT_BATCH_PHASES; ++ph) pre[ph] = (const int64_t*)(D + o_spre[s][ph]);
+        int maxcap = 0;
+        for (int j = 0; j < ns; ++j) {
+            const int c = move_capacity(b->runs[slot_segs[s][j]], s);
+            maxcap = c > maxcap ? c : maxcap;
+        }
+        e = launch_sort_batch(D + o_sort[s], pre, stot[s], ns, maxcap, b->stream);
         if (!ok(e, "batch sort")) return PP_E_HIP;
     }
     e = launch_field_step_batch(D + o_field, (const int64_t*)(D + o_cpre), n, cpre[n], max_sweeps, b->stream);
@@ -228,13 +228,8 @@ pp_status pp_batch_step(pp_batch* b) {
     // ---- host bookkeeping (buffer roles after the sort) ----------------------------------
     for (int i = 0; i < n; ++i) {
         pp_run* r = b->runs[i];
-        for (int s = 0; s < PP_MAX_SPECIES; ++s) {
-            Species& S = r->sp[s];
-            if (!S.active) continue;
-            if (S.n > 0 && !reorder[i]) swap_buffers(S.cur);  // the rebuild wrote back into cur
-            S.sorted = true;
-        }
-        r->sorts_done += 1;
+        for (int s = 0; s < PP_MAX_SPECIES; ++s)
+            if (r->sp[s].active) sort_done(r, s);
         r->step += 1;
     }
     return PP_OK;

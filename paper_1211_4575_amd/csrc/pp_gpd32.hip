@@ -17,6 +17,10 @@
 //      position -> Esirkepov current (registers) -> LDS accumulation of the tile's current
 //      block (halo of 2 nodes below and O + 1 above);
 //   3. flush the current block to the global accumulator with 64-bit integer atomics.
+// For the next sort each particle also gets its rank among the particles of its new cell:
+// an LDS counter per destination cell of the tile's neighbourhood hands out ranks inside
+// the tile, one global atomic per destination cell then reserves the tile's range in that
+// cell's count, and a second pass over the tile's particles adds the range start.
 // Current accumulation is exact 64-bit fixed point.  Each contribution P_a * F * fac is
 // formed in FP64 by one fused multiply-add with the rounding constant 1.5*2^52, whose bit
 // pattern is then (constant bits + round(contribution * 2^e)); that pattern is added to the
@@ -35,6 +39,8 @@ namespace pp {
 
 struct Sp32 {
     const int32_t* start;  // tile starts (ntiles + 1)
+    int32_t* cnt;          // particles per cell of the new positions (for the next sort)
+    int32_t* rank;         // rank of each particle in its new cell (for the next sort)
     int32_t* cell;
     float* pos[3];
     float* u[3];
@@ -62,6 +68,8 @@ struct Gpd32Args {
     const double* qscale;    // 2^e (device, set by k_fixed_scale)
     int32_t* flags;
     int per_xcd;
+    int sext[3];  // destination-cell window per axis (tile + 2 below + 2 above; 1 if collapsed)
+    int nslots;   // sext[0] * sext[1] * sext[2]
 };
 
 constexpr int GPD32_BS = 256;
@@ -212,6 +220,30 @@ __device__ __forceinline__ float gather_comp(const float* __restrict__ F, const 
     return acc;
 }
 
+// Rank of a particle among those bound for its destination cell: rel = destination cell
+// relative to the tile origin (unwrapped), gcell = its linear index.  Inside the tile's
+// window the rank comes from the LDS counter of that cell (slot << 20 | rank in the tile;
+// completed after the tile by the cell's range start); otherwise from the global count
+// directly (bit 31 set).
+__device__ __forceinline__ int32_t dest_rank(const Gpd32Args& A, const Sp32& S, int32_t* slots, const int rel[3],
+                                             int32_t gcell) {
+    int sl = 0, mul = 1;
+    bool win = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int e = A.sext[d];
+        const int x = e == 1 ? 0 : rel[d] + 2;
+        win = win && x >= 0 && x < e;
+        sl += x * mul;
+        mul *= e;
+    }
+    if (win) {
+        const int32_t r = atomicAdd(&slots[sl], 1);
+        if (r < (1 << 20)) return (sl << 20) | r;
+    }
+    return (int32_t)(0x80000000u | (uint32_t)atomicAdd(&S.cnt[gcell], 1));
+}
+
 // One tile of one run: the whole particle step of the tile's particles (the body shared by
 // the single-run kernel and the batched kernel, so both do identical arithmetic).
 template <int O, class TL>
@@ -243,6 +275,8 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
         fld[q] = (float)src[gq];
     }
     for (int q = threadIdx.x; q < 3 * L.cvol; q += GPD32_BS) cur[q] = 0ull;
+    int32_t* slots = (int32_t*)(cur + 3 * L.cvol);  // A.nslots destination-cell counters
+    for (int q = threadIdx.x; q < A.nslots; q += GPD32_BS) slots[q] = 0;
     __syncthreads();
 
     const int64_t base_cell = (int64_t)org[0] + (int64_t)n0 * (org[1] + (int64_t)n1 * org[2]);
@@ -277,8 +311,14 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
             const bool inside = rel >= 0 && li < L.tx && org[0] + li < n0 && org[1] + lj < n1 && org[2] + lk < n2 &&
                                 (int64_t)(org[0] + li) + (int64_t)n0 * ((org[1] + lj) + (int64_t)n1 * (org[2] + lk)) ==
                                     (int64_t)cell;
-            if (!inside || !offset_ok<O>(f[0]) || !offset_ok<O>(f[1]) || !offset_ok<O>(f[2])) {
+            if (!inside) {  // not this tile's particle: left out of the next sort
                 bad_all |= PP_FLAG_OUT_OF_TILE;
+                S.rank[p] = -1;
+                continue;
+            }
+            if (!offset_ok<O>(f[0]) || !offset_ok<O>(f[1]) || !offset_ok<O>(f[2])) {  // left in place
+                bad_all |= PP_FLAG_OUT_OF_TILE;
+                S.rank[p] = dest_rank(A, S, slots, loc, cell);
                 continue;
             }
 
@@ -320,8 +360,9 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
                 x1[d] = f[d] + dd;  // new position relative to the old cell's node
                 dxs[d] = dd;
             }
-            if (bad) {
+            if (bad) {  // left in place
                 bad_all |= bad;
+                S.rank[p] = dest_rank(A, S, slots, loc, cell);
                 continue;
             }
 
@@ -389,7 +430,7 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
 
             // renormalise: new cell and offset in [lo, lo + 1), or in [lo + 1, lo + 2) in the
             // cell below when the same displacement again would cross the lower face
-            int nc3[3];
+            int nc3[3], shv[3];
             float fn[3];
             const int gc[3] = {org[0] + li, org[1] + lj, org[2] + lk};
             const float lo = off_lo<O>();
@@ -411,19 +452,42 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
                     sh -= 1.0f;
                 }
                 fn[d] = o;
+                shv[d] = (int)sh;
                 nc3[d] = wrap(gc[d] + (int)sh, A.n[d]);
             }
-            S.cell[p] = nc3[0] + n0 * (nc3[1] + n1 * nc3[2]);
+            const int32_t newcell = nc3[0] + n0 * (nc3[1] + n1 * nc3[2]);
+            S.cell[p] = newcell;
             S.pos[0][p] = fn[0];
             S.pos[1][p] = fn[1];
             S.pos[2][p] = fn[2];
             S.u[0][p] = u.x;
             S.u[1][p] = u.y;
             S.u[2][p] = u.z;
+            const int dst[3] = {li + shv[0], lj + shv[1], lk + shv[2]};
+            S.rank[p] = dest_rank(A, S, slots, dst, newcell);
         }
+        // reserve the tile's range in each destination cell's count, then complete the ranks
+        __syncthreads();
+        for (int q = threadIdx.x; q < A.nslots; q += GPD32_BS) {
+            const int c = slots[q];
+            if (c == 0) continue;
+            const int x = q % A.sext[0], y = (q / A.sext[0]) % A.sext[1], z = q / (A.sext[0] * A.sext[1]);
+            const int gx = A.sext[0] == 1 ? 0 : wrap(org[0] + x - 2, n0);
+            const int gy = A.sext[1] == 1 ? 0 : wrap(org[1] + y - 2, n1);
+            const int gz = A.sext[2] == 1 ? 0 : wrap(org[2] + z - 2, n2);
+            slots[q] = atomicAdd(&S.cnt[gx + n0 * (gy + n1 * gz)], c);
+        }
+        __syncthreads();
+        for (int32_t p = start + threadIdx.x; p < end; p += GPD32_BS) {
+            const int32_t v = S.rank[p];
+            if (v == -1) continue;
+            S.rank[p] = v < 0 ? (v & 0x7FFFFFFF) : slots[v >> 20] + (v & 0xFFFFF);
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < A.nslots; q += GPD32_BS) slots[q] = 0;
+        __syncthreads();
     }
     if (bad_all) atomic_or_flag(A.flags, bad_all);
-    __syncthreads();
 
     // 3. flush the current block (integer adds commute: the sum is order-independent)
     for (int q = threadIdx.x; q < 3 * L.cvol; q += GPD32_BS) {
@@ -547,7 +611,9 @@ size_t gpd32_lds_bytes(const pp_run* r) {
     const size_t cv = kind == TILE_444       ? (size_t)cur_plane_444(r->p.shape_order) * ce[2]
                       : kind == TILE_881_FLAT ? (size_t)cur_row_881 * ce[1]
                                               : (size_t)ce[0] * ce[1] * ce[2];
-    return ((6 * fv * sizeof(float) + 15) & ~(size_t)15) + 3 * cv * sizeof(unsigned long long);
+    size_t slots = 1;
+    for (int d = 0; d < 3; ++d) slots *= r->p.n[d] == 1 ? 1 : (size_t)r->g.t[d] + 4;
+    return ((6 * fv * sizeof(float) + 15) & ~(size_t)15) + 3 * cv * sizeof(unsigned long long) + slots * sizeof(int32_t);
 }
 
 // Host part of the fixed-point exponent: e0 = 50 - ceil(log2(max |fac|)), every contribution
@@ -597,6 +663,8 @@ void gpd32_fill_args(const pp_run* r, Gpd32Args* Ap) {
         if (!S.active) continue;
         Sp32& D = A.sp[A.nsp++];
         D.start = S.offsets;
+        D.cnt = S.cell_cnt;
+        D.rank = S.rank;
         D.cell = S.cur.cell;
         for (int d = 0; d < 3; ++d) {
             D.pos[d] = (float*)S.cur.pos[d];
@@ -611,6 +679,11 @@ void gpd32_fill_args(const pp_run* r, Gpd32Args* Ap) {
     A.qscale = r->qscale;
     A.flags = r->flags;
     A.per_xcd = (int)((r->g.ntiles + 7) / 8);
+    A.nslots = 1;
+    for (int d = 0; d < 3; ++d) {
+        A.sext[d] = r->p.n[d] == 1 ? 1 : r->g.t[d] + 4;
+        A.nslots *= A.sext[d];
+    }
 }
 
 void gpd32_fixed_desc(const pp_run* r, double* J, FixedDesc* D) {

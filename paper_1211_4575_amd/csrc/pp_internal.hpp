@@ -22,10 +22,6 @@ constexpr int FLD_LO = 2;
 constexpr int fld_hi(int O) { return O == 2 ? 2 : 3; }
 constexpr int cur_lo(int) { return 2; }
 constexpr int cur_hi(int O) { return O + 1; }
-// split form: the round-major order is rebuilt every this many sorts of a species.  Every
-// sort: one step of motion moves about half of the particles to another cell, and a round
-// whose particles no longer sit one per cell makes the LDS accumulation conflict.
-constexpr int REORDER_EVERY = 1;
 
 struct Geom {
     int n[3];       // cells
@@ -45,7 +41,23 @@ struct Species {
     // FP64 form: nbins + 1 cell-bin starts.  Split form: ntiles + 1 tile starts of the
     // round-major order (valid when sorted).
     int32_t* offsets = nullptr;
+    // split form, filled by the particle kernel for the next sort: particles per cell of the
+    // new positions (ncell, zero between steps), each particle's rank among the particles of
+    // its new cell (n; -1 for a particle found outside its tile), the next tile starts
+    int32_t* cell_cnt = nullptr;
+    int32_t* rank = nullptr;
+    int32_t* offsets_next = nullptr;
+    bool ranked = false;  // cell_cnt / rank describe the current positions
 };
+
+// Round table of a tile (split-form sort): in round r, the cells holding more than r
+// particles (bit lc of mask), and the number of particles placed in rounds before r.
+struct RoundEntry {
+    uint64_t mask;
+    int32_t before;
+    int32_t pad;
+};
+constexpr int SORT_RCAP = 96;  // rounds per tile table; ranks beyond go to an overflow tail
 
 // Line-solve stencil of one axis: out[i] = sum_j coef[j] * in[(i + off + j) mod n].
 struct LineStencil {
@@ -71,10 +83,10 @@ struct pp_run {
     double* rho_prev = nullptr;
     int64_t rho_prev_step = -1;
     int32_t* sort_cursor = nullptr;   // nbins: scatter cursors (cell bins or tiles)
+    pp::RoundEntry* rounds = nullptr; // split form: ntiles * SORT_RCAP round tables
     int32_t* scan_tmp = nullptr;      // block sums of the scan
     int32_t* sort_scratch = nullptr;  // split form: rank and permutation of the round-major rebuild
     int64_t sort_scratch_n = 0;       // particles per half of sort_scratch
-    int64_t sorts_done = 0;           // split form: counts sorts to schedule the rebuilds
     long long* Jq = nullptr;          // split form: current in 64-bit fixed point (3*ncell)
     int32_t* tile_max = nullptr;      // split form: largest particle count of a tile, per species
     double* qscale = nullptr;         // split form: 2^e of the fixed-point current (device)
@@ -119,7 +131,12 @@ hipError_t launch_gpd32(pp_run* r, double* J);
 hipError_t launch_line_solve(pp_run* r, const double* J2, double* J);
 hipError_t launch_field_step(pp_run* r);
 int64_t field_blocks(const pp_run* r);  // blocks of one field / line-solve launch of this run
-hipError_t launch_sort(pp_run* r, int s, bool reorder);
+// Sort species s: FP64 form, counting sort by cell; split form, round-major order per tile,
+// from the particle kernel's counts and ranks when it has run since the last sort, otherwise
+// (first sort, arbitrary order) by bucketing and a per-tile rebuild.
+hipError_t launch_sort(pp_run* r, int s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+void sort_done(pp_run* r, int s);  // host bookkeeping after a ranked sort was enqueued
 hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void swap_buffers(pp_particles& c);
@@ -148,8 +165,10 @@ void line_desc(const pp_run* r, const double* J2, double* J, LineArgs* A);
 hipError_t launch_line_solve_batch(const void* table, const int64_t* prefix, int n, int64_t total_blocks, hipStream_t st);
 size_t sort_desc_size();
 void sort_desc(const pp_run* r, int s, SortDesc* D);
-void sort_desc_blocks(const pp_run* r, int s, bool reorder, int64_t blocks[7]);
-hipError_t launch_sort_batch(const void* table, const int64_t* const prefixes[7], const int64_t totals[7], int nseg,
-                             hipStream_t st);
+constexpr int SORT_BATCH_PHASES = 4;
+void sort_desc_blocks(const pp_run* r, int s, int64_t blocks[SORT_BATCH_PHASES]);
+hipError_t launch_sort_batch(const void* table, const int64_t* const prefixes[SORT_BATCH_PHASES],
+                             const int64_t totals[SORT_BATCH_PHASES], int nseg, int maxcap, hipStream_t st);
+int move_capacity(const pp_run* r, int s);
 
 }  // namespace pp

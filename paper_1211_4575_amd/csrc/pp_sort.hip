@@ -4,17 +4,16 @@
 // FP64 form: counting sort by tile-major cell key (histogram -> exclusive scan -> scatter
 // with atomic cursors; order inside a cell unspecified).
 //
-// Split form: particles are bucketed by tile (64 cells): a count per tile, a scan over
-// tiles, and a scatter whose positions come from wavefront-aggregated atomics (one atomic per
-// destination tile per wavefront, so a wavefront's particles that stay in their tile are
-// written as one contiguous, coalesced block and keep their previous relative order).  The
-// particle kernel only needs each tile's particles to be contiguous.  It runs fastest when
-// 64 consecutive particles sit in 64 different cells, so at initialisation and then every
-// few sorts a per-tile pass rebuilds the "round-major" order: every particle gets a rank r
-// inside its cell, and the tile's particles are laid out round by round (all rank-0
-// particles of the tile's cells, then all rank-1 particles, ...), cells ascending inside a
-// round.  Between rebuilds the bucketing keeps most of that order because most particles
-// stay in their tile and their block keeps its order.
+// Split form: particles are laid out tile by tile (64 cells) in "round-major" order: every
+// particle has a rank r inside its cell, and a tile's particles are laid out round by round
+// (the rank-0 particles of the tile's cells, then the rank-1 particles, ...), cells
+// ascending inside a round, so that 64 consecutive particles sit in 64 different cells.
+// After a push the particle kernel has already counted the particles of every new cell and
+// ranked each particle inside it, so the sort is a per-tile round table, a scan over tiles
+// and one scatter straight to the final positions (ranked sort).  The first sort of a
+// species (arbitrary order) buckets by tile -- a count per tile, a scan, and a scatter whose
+// positions come from block-aggregated atomics -- and then rebuilds the round-major order
+// tile by tile.
 #include "pp_device.hpp"
 #include "pp_internal.hpp"
 
@@ -347,6 +346,189 @@ __global__ void __launch_bounds__(256) k_tile_reorder(ReorderArgs<T> A) {
     tile_reorder_tile(A, blockIdx.x);
 }
 
+// ---- ranked sort (split form, after a push) ---------------------------------------------
+// The particle kernel left, for species s, the number of particles of each cell at the new
+// positions (cnt) and each particle's rank among the particles of its new cell.  Round r of
+// a tile holds the rank-r particle of every cell with more than r particles, in cell order,
+// so the particle of rank r in local cell lc goes to
+//   tile start + sum over cells of min(count, r) + #{cells c < lc with count > r};
+// the first two terms come from a per-tile round table.  Ranks of SORT_RCAP and beyond go
+// to an overflow tail of the tile (order there unspecified).
+
+struct RankedArgs {
+    KeyGeom G;
+    int64_t ntiles;
+    int32_t* cnt;           // per cell (read and cleared by the table kernel)
+    RoundEntry* rounds;     // ntiles * SORT_RCAP
+    int32_t* tot;           // ntiles + 1: tile totals, scanned into the next tile starts
+    int32_t* rtot;          // ntiles: particles in the table's rounds
+    int32_t* ovf;           // ntiles: overflow cursors
+    int32_t* tile_max;      // largest tile population
+    const int32_t* start;   // current tile starts (source order)
+    const int32_t* rank;
+    int64_t n;
+    const int32_t* cell;
+    const float* pos[3];
+    const float* u[3];
+    const int64_t* id;
+    int32_t* cell_o;
+    float* pos_o[3];
+    float* u_o[3];
+    int64_t* id_o;
+};
+
+// one wavefront per tile: lane = local cell
+__device__ __forceinline__ void round_table_tile(const RankedArgs& A, int64_t t) {
+    const int lane = threadIdx.x & 63;
+    if (t >= A.ntiles) return;
+    const KeyGeom& G = A.G;
+    const int ti = (int)(t % G.nt[0]), tj = (int)((t / G.nt[0]) % G.nt[1]), tk = (int)(t / ((int64_t)G.nt[0] * G.nt[1]));
+    const int li = lane % G.t[0], lj = (lane / G.t[0]) % G.t[1], lk = lane / (G.t[0] * G.t[1]);
+    const int i = ti * G.t[0] + li, j = tj * G.t[1] + lj, k = tk * G.t[2] + lk;
+    int c = 0;
+    if (i < G.n[0] && j < G.n[1] && k < G.n[2]) {
+        const int64_t g = (int64_t)i + (int64_t)G.n[0] * (j + (int64_t)G.n[1] * k);
+        c = A.cnt[g];
+        A.cnt[g] = 0;
+    }
+    int tot = c, mx = c;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        tot += __shfl_xor(tot, o, 64);
+        const int other = __shfl_xor(mx, o, 64);
+        mx = other > mx ? other : mx;
+    }
+    const int rmax = mx < SORT_RCAP ? mx : SORT_RCAP;
+    int run = 0;
+    for (int r = 0; r < rmax; ++r) {
+        const uint64_t m = __ballot(c > r);
+        if (lane == 0) {
+            RoundEntry e;
+            e.mask = m;
+            e.before = run;
+            e.pad = 0;
+            A.rounds[t * SORT_RCAP + r] = e;
+        }
+        run += (int)__popcll(m);
+    }
+    if (lane == 0) {
+        A.tot[t] = tot;
+        A.rtot[t] = run;
+        A.ovf[t] = 0;
+        atomicMax(A.tile_max, tot);
+        if (t == A.ntiles - 1) A.tot[A.ntiles] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_round_tables(RankedArgs A) {
+    round_table_tile(A, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
+}
+
+// Destination slot of particle p of the current order (-1: not placed, a flagged particle);
+// tot holds the next tile starts.
+__device__ __forceinline__ int32_t ranked_pos(const RankedArgs& A, int32_t p) {
+    const int32_t r = A.rank[p];
+    if (r < 0) return -1;
+    const int32_t key = key_cell(A.G, A.cell[p]);
+    const int32_t t = key / TILE_CELLS;
+    const int lc = key % TILE_CELLS;
+    int32_t pos;
+    if (r < SORT_RCAP) {
+        const RoundEntry e = A.rounds[(int64_t)t * SORT_RCAP + r];
+        pos = A.tot[t] + e.before + (int32_t)__popcll(lc == 0 ? 0ull : (e.mask & ((1ull << lc) - 1ull)));
+    } else {
+        pos = A.tot[t] + A.rtot[t] + atomicAdd(&A.ovf[t], 1);
+    }
+    return pos < A.tot[t + 1] ? pos : -1;  // inconsistent counts (flagged state): never past the tile
+}
+
+// One workgroup per source tile T moves T's particles to their places.  Most of them stay in
+// tile T: the workgroup loads every attribute of its particles at once (coalesced, source
+// order), keeps the ones bound for tile T in an LDS image of T's destination range and
+// writes the image out coalesced (slots filled from neighbouring tiles are skipped: their
+// workgroups store those directly).  Tiles larger than the image scatter directly.
+constexpr int MOVE_BS = 1024;
+constexpr int MOVE_WORDS = 7;  // cell, pos[3], u[3]
+
+size_t move_lds_bytes(int cap) { return (size_t)cap * (sizeof(int32_t) * (1 + MOVE_WORDS) + 1); }
+
+__device__ __forceinline__ void move_one(const RankedArgs& A, int32_t p, int32_t pos) {
+    A.cell_o[pos] = A.cell[p];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        A.pos_o[d][pos] = A.pos[d][p];
+        A.u_o[d][pos] = A.u[d][p];
+    }
+    if (A.id) A.id_o[pos] = A.id[p];
+}
+
+__device__ __forceinline__ void ranked_move_tile(const RankedArgs& A, int64_t T, int cap, unsigned char* lds) {
+    if (T >= A.ntiles) return;
+    const int32_t ss = A.start[T], se = A.start[T + 1];
+    const int32_t d0 = A.tot[T], d1 = A.tot[T + 1];
+    if (se - ss > cap || d1 - d0 > cap) {  // a crowded tile
+        for (int32_t p = ss + threadIdx.x; p < se; p += blockDim.x) {
+            const int32_t pos = ranked_pos(A, p);
+            if (pos >= 0) move_one(A, p, pos);
+        }
+        return;
+    }
+    uint32_t* img = (uint32_t*)lds;                       // MOVE_WORDS * cap
+    uint8_t* filled = (uint8_t*)(img + MOVE_WORDS * cap);  // cap
+    const int32_t nd = d1 - d0;
+    for (int32_t q = threadIdx.x; q < nd; q += blockDim.x) filled[q] = 0;
+    __syncthreads();
+    for (int32_t p = ss + threadIdx.x; p < se; p += blockDim.x) {
+        uint32_t v[MOVE_WORDS];
+        v[0] = (uint32_t)A.cell[p];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            v[1 + d] = __float_as_uint(A.pos[d][p]);
+            v[4 + d] = __float_as_uint(A.u[d][p]);
+        }
+        const int32_t pos = ranked_pos(A, p);
+        if (pos < 0) continue;
+        if (A.id) A.id_o[pos] = A.id[p];
+        const int32_t q = pos - d0;
+        if (q >= 0 && q < nd) {
+#pragma unroll
+            for (int w = 0; w < MOVE_WORDS; ++w) img[w * cap + q] = v[w];
+            filled[q] = 1;
+        } else {
+            A.cell_o[pos] = (int32_t)v[0];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                A.pos_o[d][pos] = __uint_as_float(v[1 + d]);
+                A.u_o[d][pos] = __uint_as_float(v[4 + d]);
+            }
+        }
+    }
+    __syncthreads();
+    for (int32_t q = threadIdx.x; q < nd; q += blockDim.x) {
+        if (!filled[q]) continue;
+        const int32_t j = d0 + q;
+        A.cell_o[j] = (int32_t)img[q];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            A.pos_o[d][j] = __uint_as_float(img[(1 + d) * cap + q]);
+            A.u_o[d][j] = __uint_as_float(img[(4 + d) * cap + q]);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(MOVE_BS) k_ranked_move(RankedArgs A, int cap) {
+    extern __shared__ __align__(16) unsigned char lds_move[];
+    ranked_move_tile(A, blockIdx.x, cap, lds_move);
+}
+
+// LDS image capacity for a species: room for tiles somewhat above the mean population
+int move_capacity(const pp_run* r, int s) {
+    const double mean = (double)r->sp[s].n / (double)(r->g.ntiles > 0 ? r->g.ntiles : 1);
+    int cap = (int)(1.25 * mean) + 256;
+    const int cmax = (int)((150 * 1024) / move_lds_bytes(1));
+    return cap < 256 ? 256 : (cap > cmax ? cmax : cap);
+}
+
 // ---- exclusive scan of int32, in place ------------------------------------------------
 constexpr int SCAN_BS = 256, SCAN_PER = 8, SCAN_CHUNK = SCAN_BS * SCAN_PER;
 
@@ -426,18 +608,13 @@ static KeyGeom key_geom(const pp_run* r) {
     return G;
 }
 
-// ---- batched split-form sort of one species slot over several runs ------------------------
+// ---- batched ranked sort of one species slot over several runs -----------------------------
 struct SortDesc {
-    KeyGeom G;
-    int64_t n, ntiles;
-    int32_t* offsets;   // ntiles + 1
-    int32_t* cursor;    // ntiles
-    int32_t* tile_max;  // the run's slot for this species
-    ScatterArgs<float> A;
-    ReorderArgs<float> B;
+    RankedArgs A;
+    int cap;  // LDS image capacity of the move
 };
 
-enum SortPhase { SP_FILL = 0, SP_COUNT = 1, SP_SCAN = 2, SP_MAX = 3, SP_CURSOR = 4, SP_SCATTER = 5, SP_REORDER = 6 };
+enum SortPhase { SP_RESET = 0, SP_TABLES = 1, SP_SCAN = 2, SP_MOVE = 3 };
 
 // whole-segment exclusive scan by one workgroup (segments are short: one entry per tile)
 __device__ __forceinline__ void scan_segment(int32_t* data, int64_t n) {
@@ -464,122 +641,104 @@ __device__ __forceinline__ void scan_segment(int32_t* data, int64_t n) {
     }
 }
 
-__device__ __forceinline__ void tile_max_segment(const int32_t* start, int64_t ntiles, int32_t* out) {
-    __shared__ int32_t sh[256];
-    int m = 0;
-    for (int64_t t = threadIdx.x; t < ntiles; t += 256) {
-        const int c = start[t + 1] - start[t];
-        m = c > m ? c : m;
-    }
-    sh[threadIdx.x] = m;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) sh[threadIdx.x] = sh[threadIdx.x] > sh[threadIdx.x + off] ? sh[threadIdx.x] : sh[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = sh[0];
-}
-
 __global__ void __launch_bounds__(256) k_sort_batch(const SortDesc* __restrict__ T, const int64_t* __restrict__ prefix,
                                                     int nseg, int phase) {
     const int64_t b = blockIdx.x;
     const int r = find_segment(prefix, nseg, b);
     if (r < 0) return;
-    const SortDesc& D = T[r];
+    const RankedArgs& A = T[r].A;
     const int64_t blk = b - prefix[r];
     switch (phase) {
-    case SP_FILL: {
-        const int64_t q = blk * 256 + threadIdx.x;
-        if (q <= D.ntiles) D.offsets[q] = 0;
+    case SP_RESET:
+        if (threadIdx.x == 0) *A.tile_max = 0;
         break;
-    }
-    case SP_COUNT:
-        tile_count_block(D.G, D.A.cell, D.n, D.offsets, blk);
+    case SP_TABLES:
+        round_table_tile(A, blk * 4 + (threadIdx.x >> 6));
         break;
     case SP_SCAN:
-        scan_segment(D.offsets, D.ntiles + 1);
-        break;
-    case SP_MAX:
-        tile_max_segment(D.offsets, D.ntiles, D.tile_max);
-        break;
-    case SP_CURSOR: {
-        const int64_t q = blk * 256 + threadIdx.x;
-        if (q < D.ntiles) D.cursor[q] = D.offsets[q];
-        break;
-    }
-    case SP_SCATTER:
-        scatter_tiles_block(D.A, blk);
+        scan_segment(A.tot, A.ntiles + 1);
         break;
     default:
-        tile_reorder_tile(D.B, blk);
         break;
     }
 }
 
-// Fill the descriptor of species s of run r (buffers: cur -> alt for the bucketing; the
-// rebuild reads alt and writes back into cur).
-void sort_desc(const pp_run* r, int s, SortDesc* D) {
+__global__ void __launch_bounds__(MOVE_BS) k_move_batch(const SortDesc* __restrict__ T, const int64_t* __restrict__ prefix,
+                                                        int nseg) {
+    extern __shared__ __align__(16) unsigned char lds_move[];
+    const int64_t b = blockIdx.x;
+    const int r = find_segment(prefix, nseg, b);
+    if (r < 0) return;
+    ranked_move_tile(T[r].A, b - prefix[r], T[r].cap, lds_move);
+}
+
+static hipError_t allow_large_lds() {
+    static bool done = false;
+    if (done) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)k_ranked_move, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_move_batch, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    done = e == hipSuccess;
+    return e;
+}
+
+
+static void ranked_args(const pp_run* r, int s, RankedArgs* A) {
     const Species& S = r->sp[s];
-    D->G = key_geom(r);
-    D->n = S.n;
-    D->ntiles = r->g.ntiles;
-    D->offsets = S.offsets;
-    D->cursor = r->sort_cursor;
-    D->tile_max = r->tile_max + s;
-    ScatterArgs<float>& A = D->A;
-    A.G = D->G;
-    A.n = S.n;
-    A.cell = S.cur.cell;
-    A.id = S.cur.id;
-    A.cell_o = S.cur.cell_alt;
-    A.id_o = S.cur.id ? S.cur.id_alt : nullptr;
+    const int64_t nt = r->g.ntiles;
+    A->G = key_geom(r);
+    A->ntiles = nt;
+    A->cnt = S.cell_cnt;
+    A->rounds = r->rounds;
+    A->tot = S.offsets_next;
+    A->rtot = r->sort_cursor;
+    A->ovf = r->sort_cursor + nt;
+    A->tile_max = r->tile_max + s;
+    A->start = S.offsets;
+    A->rank = S.rank;
+    A->n = S.n;
+    A->cell = S.cur.cell;
+    A->id = S.cur.id;
+    A->cell_o = S.cur.cell_alt;
+    A->id_o = S.cur.id ? S.cur.id_alt : nullptr;
     for (int d = 0; d < 3; ++d) {
-        A.pos[d] = (const float*)S.cur.pos[d];
-        A.u[d] = (const float*)S.cur.u[d];
-        A.pos_o[d] = (float*)S.cur.pos_alt[d];
-        A.u_o[d] = (float*)S.cur.u_alt[d];
+        A->pos[d] = (const float*)S.cur.pos[d];
+        A->u[d] = (const float*)S.cur.u[d];
+        A->pos_o[d] = (float*)S.cur.pos_alt[d];
+        A->u_o[d] = (float*)S.cur.u_alt[d];
     }
-    A.cursor = r->sort_cursor;
-    ReorderArgs<float>& B = D->B;
-    B.G = D->G;
-    B.ntiles = r->g.ntiles;
-    B.start = S.offsets;
-    B.cell = S.cur.cell_alt;
-    B.id = S.cur.id ? S.cur.id_alt : nullptr;
-    B.cell_o = S.cur.cell;
-    B.id_o = S.cur.id;
-    for (int d = 0; d < 3; ++d) {
-        B.pos[d] = (const float*)S.cur.pos_alt[d];
-        B.u[d] = (const float*)S.cur.u_alt[d];
-        B.pos_o[d] = (float*)S.cur.pos[d];
-        B.u_o[d] = (float*)S.cur.u[d];
-    }
-    B.rank = r->sort_scratch;
-    B.perm = r->sort_scratch + r->sort_scratch_n;
+}
+
+void sort_desc(const pp_run* r, int s, SortDesc* D) {
+    ranked_args(r, s, &D->A);
+    D->cap = move_capacity(r, s);
 }
 
 size_t sort_desc_size() { return sizeof(SortDesc); }
 
 // Blocks each phase needs for one descriptor.
-void sort_desc_blocks(const pp_run* r, int s, bool reorder, int64_t blocks[7]) {
-    const int64_t n = r->sp[s].n, nt = r->g.ntiles;
-    blocks[SP_FILL] = (nt + 1 + 255) / 256;
-    blocks[SP_COUNT] = (n + AGG_BLOCK - 1) / AGG_BLOCK;
+void sort_desc_blocks(const pp_run* r, int s, int64_t blocks[SORT_BATCH_PHASES]) {
+    const int64_t nt = r->g.ntiles;
+    blocks[SP_RESET] = 1;
+    blocks[SP_TABLES] = (nt + 3) / 4;
     blocks[SP_SCAN] = 1;
-    blocks[SP_MAX] = 1;
-    blocks[SP_CURSOR] = (nt + 255) / 256;
-    blocks[SP_SCATTER] = (n + AGG_BLOCK - 1) / AGG_BLOCK;
-    blocks[SP_REORDER] = reorder && n > 0 ? nt : 0;
+    blocks[SP_MOVE] = r->sp[s].n > 0 ? nt : 0;
 }
 
-// prefixes: 7 arrays of nseg + 1 block prefixes (device), totals: blocks per phase
-hipError_t launch_sort_batch(const void* table, const int64_t* const prefixes[7], const int64_t totals[7], int nseg,
-                             hipStream_t st) {
+// prefixes: one array of nseg + 1 block prefixes (device) per phase, totals: blocks per phase
+hipError_t launch_sort_batch(const void* table, const int64_t* const prefixes[SORT_BATCH_PHASES],
+                             const int64_t totals[SORT_BATCH_PHASES], int nseg, int maxcap, hipStream_t st) {
     if (nseg == 0) return hipSuccess;
     const SortDesc* T = (const SortDesc*)table;
-    for (int ph = SP_FILL; ph <= SP_REORDER; ++ph) {
+    for (int ph = 0; ph < SP_MOVE; ++ph) {
         if (totals[ph] == 0) continue;
         hipLaunchKernelGGL(k_sort_batch, dim3((unsigned)totals[ph]), dim3(256), 0, st, T, prefixes[ph], nseg, ph);
+    }
+    if (totals[SP_MOVE] > 0) {
+        hipError_t e = allow_large_lds();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_move_batch, dim3((unsigned)totals[SP_MOVE]), dim3(MOVE_BS), move_lds_bytes(maxcap), st, T,
+                           prefixes[SP_MOVE], nseg);
     }
     return hipGetLastError();
 }
@@ -601,8 +760,36 @@ void swap_buffers(pp_particles& c) {
     }
 }
 
+void sort_done(pp_run* r, int s) {
+    Species& S = r->sp[s];
+    if (S.n > 0) swap_buffers(S.cur);
+    int32_t* t = S.offsets;
+    S.offsets = S.offsets_next;
+    S.offsets_next = t;
+    S.ranked = false;
+    S.sorted = true;
+}
+
+static hipError_t sort_ranked(pp_run* r, int s) {
+    RankedArgs A;
+    ranked_args(r, s, &A);
+    const int64_t nt = r->g.ntiles;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, r->stream, r->tile_max + s, (int64_t)1, 0);
+    hipLaunchKernelGGL(k_round_tables, dim3((unsigned)((nt + 3) / 4)), dim3(256), 0, r->stream, A);
+    scan_inplace(A.tot, nt + 1, r->scan_tmp, r->stream);
+    if (r->sp[s].n > 0) {
+        hipError_t e0 = allow_large_lds();
+        if (e0 != hipSuccess) return e0;
+        const int cap = move_capacity(r, s);
+        hipLaunchKernelGGL(k_ranked_move, dim3((unsigned)nt), dim3(MOVE_BS), move_lds_bytes(cap), r->stream, A, cap);
+    }
+    hipError_t e = hipGetLastError();
+    sort_done(r, s);
+    return e;
+}
+
 template <typename T>
-static hipError_t sort_species(pp_run* r, int s, bool reorder) {
+static hipError_t sort_species(pp_run* r, int s) {
     Species& S = r->sp[s];
     const KeyGeom G = key_geom(r);
     const int64_t nbins = r->g.nbins;
@@ -649,7 +836,7 @@ static hipError_t sort_species(pp_run* r, int s, bool reorder) {
         else
             hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((S.n + bs - 1) / bs)), dim3(bs), 0, r->stream, A);
         swap_buffers(S.cur);
-        if (split && reorder) {
+        if (split) {
             ReorderArgs<T> B;
             B.G = G;
             B.ntiles = ntiles;
@@ -671,12 +858,18 @@ static hipError_t sort_species(pp_run* r, int s, bool reorder) {
         }
     }
     S.sorted = true;
+    S.ranked = false;
     return hipGetLastError();
 }
 
-hipError_t launch_sort(pp_run* r, int s, bool reorder) {
-    if (r->p.precision == PP_PREC_FP32_SPLIT) return sort_species<float>(r, s, reorder);
-    return sort_species<double>(r, s, false);
+hipError_t launch_sort(pp_run* r, int s) {
+    if (r->p.precision == PP_PREC_FP32_SPLIT) return r->sp[s].ranked ? sort_ranked(r, s) : sort_species<float>(r, s);
+    return sort_species<double>(r, s);
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
 }
 
 }  // namespace pp
