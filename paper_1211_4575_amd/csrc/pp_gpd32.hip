@@ -92,6 +92,10 @@ __device__ __forceinline__ long long fixed_sum(unsigned long long v) {
 constexpr int cur_row_444 = 12;
 constexpr int cur_plane_444(int O) { return O == 2 ? 112 : 128; }
 constexpr int cur_row_881 = 24;
+// Row and plane strides (floats) of the field tile of a 4x4x4 tile (cubic weights: padded
+// from 9 and 81, which measured a few per cent faster).
+constexpr int fld_row_444(int O) { return O == 3 ? 10 : O + 6; }
+constexpr int fld_plane_444(int O) { return O == 3 ? 90 : (O + 6) * (O + 6); }
 
 // LDS layout of a tile: compile-time for the common shapes, runtime otherwise.  A
 // single-cell axis is collapsed (extent 1, stride 0): every node offset maps to plane 0.
@@ -105,7 +109,10 @@ struct TileCT {
     static constexpr int fez = CZ ? 1 : TZ + FLD_LO + fld_hi(O);
     static constexpr int cex = TX + cur_lo(O) + cur_hi(O), cey = TY + cur_lo(O) + cur_hi(O);
     static constexpr int cez = CZ ? 1 : TZ + cur_lo(O) + cur_hi(O);
-    static constexpr int fsx = 1, fsy = fex, fsz = CZ ? 0 : fex * fey;
+    static constexpr bool f444 = TX == 4 && TY == 4 && TZ == 4 && !CZ;
+    static constexpr int frow = f444 ? fld_row_444(O) : fex;
+    static constexpr int fplane = f444 ? fld_plane_444(O) : frow * fey;
+    static constexpr int fsx = 1, fsy = frow, fsz = CZ ? 0 : fplane;
     static constexpr bool t444 = TX == 4 && TY == 4 && TZ == 4 && !CZ;
     static constexpr bool t881 = TX == 8 && TY == 8 && CZ;
     static constexpr int crow = t444 ? cur_row_444 : (t881 ? cur_row_881 : cex);
@@ -113,7 +120,8 @@ struct TileCT {
     static_assert(crow >= cex, "current row padding");
     static_assert(cplane >= crow * cey, "current plane padding");
     static constexpr int csx = 1, csy = crow, csz = CZ ? 0 : cplane;
-    static constexpr int fvol = fex * fey * fez, cvol = cplane * cez;
+    static_assert(frow >= fex && fplane >= frow * fey, "field tile padding");
+    static constexpr int fvol = fplane * fez, cvol = cplane * cez;
     __device__ TileCT(const Gpd32Args&) {}
 };
 
@@ -122,7 +130,7 @@ struct TileRT {
     int flox, floy, floz, clox, cloy, cloz;
     int fex, fey, fez, cex, cey, cez;
     int fsx, fsy, fsz, csx, csy, csz;
-    int crow, cplane;
+    int crow, cplane, frow, fplane;
     int fvol, cvol;
     __device__ TileRT(const Gpd32Args& A) {
         tx = A.t[0];
@@ -141,14 +149,16 @@ struct TileRT {
         cey = A.ce[1];
         cez = A.ce[2];
         fsx = A.n[0] > 1 ? 1 : 0;
-        fsy = A.n[1] > 1 ? fex : 0;
-        fsz = A.n[2] > 1 ? fex * fey : 0;
+        frow = fex;
+        fplane = fex * fey;
+        fsy = A.n[1] > 1 ? frow : 0;
+        fsz = A.n[2] > 1 ? fplane : 0;
         crow = cex;
         cplane = cex * cey;
         csx = A.n[0] > 1 ? 1 : 0;
         csy = A.n[1] > 1 ? crow : 0;
         csz = A.n[2] > 1 ? cplane : 0;
-        fvol = fex * fey * fez;
+        fvol = fplane * fez;
         cvol = cplane * cez;
     }
 };
@@ -264,9 +274,11 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
     for (int q = threadIdx.x; q < 6 * L.fvol; q += GPD32_BS) {
         const int comp = q / L.fvol;
         const int r = q - comp * L.fvol;
-        const int a = r % L.fex;
-        const int bb = (r / L.fex) % L.fey;
-        const int c = r / (L.fex * L.fey);
+        const int c = r / L.fplane;
+        const int rr = r - c * L.fplane;
+        const int bb = rr / L.frow;
+        const int a = rr - bb * L.frow;
+        if (a >= L.fex || bb >= L.fey) continue;  // padding
         const int gi = wrap(org[0] - L.flox + a, n0);
         const int gj = wrap(org[1] - L.floy + bb, n1);
         const int gk = wrap(org[2] - L.floz + c, n2);
@@ -606,7 +618,8 @@ static void lds_extents(const pp_run* r, int fe[3], int ce[3], int flo[3], int c
 size_t gpd32_lds_bytes(const pp_run* r) {
     int fe[3], ce[3], flo[3], clo[3];
     lds_extents(r, fe, ce, flo, clo);
-    const size_t fv = (size_t)fe[0] * fe[1] * fe[2];
+    const size_t fv = tile_kind(r) == TILE_444 ? (size_t)fld_plane_444(r->p.shape_order) * fe[2]
+                                                : (size_t)fe[0] * fe[1] * fe[2];
     const int kind = tile_kind(r);
     const size_t cv = kind == TILE_444       ? (size_t)cur_plane_444(r->p.shape_order) * ce[2]
                       : kind == TILE_881_FLAT ? (size_t)cur_row_881 * ce[1]
