@@ -232,7 +232,7 @@ def main(argv=None):
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--workload", choices=("pair_mj", "serving"), default="pair_mj")
     ap.add_argument("--requests", type=int, default=256)
-    ap.add_argument("--rate", type=float, default=1.0, help="serving: mean arrivals per second")
+    ap.add_argument("--rate", type=float, default=2.0, help="serving: mean arrivals per second")
     ap.add_argument("--slots", type=int, default=64, help="serving: most runs in the batch")
     ap.add_argument("--mem-gib", type=float, default=160.0, help="serving: device memory budget for runs")
     ap.add_argument("--ref-steps", type=int, default=3, help="serving: timed steps per class for the references")
