@@ -151,6 +151,113 @@ def measured_traffic(particles):
         return None
 
 
+def two_stream_rate(k, v0, wb2=0.5):
+    """Growth rate at wavenumber k of the symmetric cold relativistic two-stream instability
+    (two beams at +-v0, each of plasma frequency^2 wb2, longitudinal mass gamma0^3 m): the
+    unstable root of 1 = wb2/gamma0^3 [1/(w - k v0)^2 + 1/(w + k v0)^2], i.e. with
+    a = wb2/gamma0^3 and x = k v0, gamma^2 = sqrt(a^2 + 4 a x^2) - x^2 - a."""
+    a = wb2 * (1.0 - v0 * v0) ** 1.5
+    x2 = (k * v0) ** 2
+    g2 = math.sqrt(a * a + 4.0 * a * x2) - x2 - a
+    return math.sqrt(g2) if g2 > 0 else 0.0
+
+
+def growth_rate_fit(t, w, width=4.0):
+    """Growth rate of the field amplitude (half the log slope of the E_x energy W) in the linear
+    phase, which starts when W first exceeds 10x its mean over t <= 2 and ends when W first
+    reaches 10 % of its maximum.  Returns (largest least-squares rate over windows of the given
+    width inside that phase, least-squares rate over the whole phase, phase (t0, t1))."""
+    import numpy as np
+    t = np.asarray(t, dtype=float)
+    w = np.asarray(w, dtype=float)
+    base = w[t <= 2.0].mean()
+    i0 = int(np.argmax(w > 10.0 * base))
+    i1 = int(np.argmax(w >= 0.1 * w.max()))
+    nan = float("nan")
+    if not (w[i0] > 10.0 * base) or i1 <= i0 + 2:
+        return nan, nan, (float(t[i0]), float(t[i1]))
+    lw = np.log(np.maximum(w, np.finfo(float).tiny))
+    whole = 0.5 * float(np.polyfit(t[i0:i1 + 1], lw[i0:i1 + 1], 1)[0])
+    best = nan
+    j = i0
+    while j < i1:
+        k = int(np.searchsorted(t, t[j] + width))
+        if k > i1 + 1:
+            break
+        if k - j >= 3:
+            r = 0.5 * float(np.polyfit(t[j:k], lw[j:k], 1)[0])
+            best = r if not (best >= r) else best
+        j += max(1, (k - j) // 8)
+    return best, whole, (float(t[i0]), float(t[i1]))
+
+
+def run_two_stream(torch, pp, ind, n, per_dim, v_beam, uth, steps, split, dx=0.1, cfl=0.4, seed=SEED):
+    """Two-stream run generated on the device; returns (times, E_x energy per step, wall s,
+    particles)."""
+    npart = n[0] * n[1] * n[2] * per_dim[0] * per_dim[1] * per_dim[2]
+    dev = torch.device("cuda:0")
+    rt = torch.float32 if split else torch.float64
+    cells = [torch.empty(npart, dtype=torch.int32, device=dev) for _ in range(2)] if split else None
+    offs = [torch.empty((3, npart), dtype=rt, device=dev) for _ in range(2)]
+    us = [torch.empty((3, npart), dtype=rt, device=dev) for _ in range(2)]
+    ind.two_stream_lattice(seed, 2, n, per_dim, v_beam, uth, ind.split_mode(split, 3), cells,
+                           [[o[d] for d in range(3)] for o in offs], [[u[d] for d in range(3)] for u in us],
+                           torch.cuda.current_stream().cuda_stream)
+    ppc = per_dim[0] * per_dim[1] * per_dim[2]
+    species = []
+    for s in range(2):
+        sp = dict(q=-1.0, m=1.0, w=0.5 / ppc, u=us[s])
+        sp.update(dict(cell=cells[s], off=offs[s]) if split else dict(pos=offs[s]))
+        species.append(sp)
+    P = pp.make_params(n, d=(dx, dx, dx), dt=cfl * dx, shape_order=3, field_order=6, alpha=0.55,
+                       precision=pp.PP_PREC_FP32_SPLIT if split else pp.PP_PREC_FP64,
+                       relax_tol=1e-8 if split else 1e-14, relax_max_iter=100, rho_background=1.0)
+    run = pp.Run(P, species, with_id=False)
+    del cells, offs, us
+    t, w = [0.0], [run.diagnostics(pp.PP_DIAG_FIELDS).field_Ex]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        run.step()
+        w.append(run.diagnostics(pp.PP_DIAG_FIELDS).field_Ex)
+        t.append((i + 1) * cfl * dx)
+        if (i + 1) % 500 == 0:
+            log(f"[two-stream] {'FP32' if split else 'FP64'} step {i + 1}/{steps}, W_Ex {w[-1]:.3e}")
+    wall = time.perf_counter() - t0
+    d = run.diagnostics(pp.PP_DIAG_ALL)
+    run.close()
+    torch.cuda.empty_cache()
+    return t, w, wall, 2 * npart, d
+
+
+def two_stream_bench(args, torch, pp):
+    """The cold-beam / two-stream test: 128x32x32 cells of 0.1 c/w_pe, two electron beams at
+    +-0.2c (32 particles per cell each, quiet lattice, u_th = 0.01c) over a fixed ion
+    background, cubic weights, 6th-order fields, 2000 steps of 0.04; growth rate of the E_x
+    energy, FP64 then FP32, against linear theory at the box mode nearest the fastest one."""
+    from paper_1211_4575_amd import inputs_device as ind
+    n, per_dim, v0 = (args.grid_x, 32, 32), (4, 4, 2), 0.2
+    L = n[0] * 0.1
+    kmax = math.sqrt(3.0) / 2.0 * math.sqrt(0.5) * (1 - v0 * v0) ** 0.75 / v0
+    m = max(1, round(kmax * L / (2 * math.pi)))
+    theory = two_stream_rate(2 * math.pi * m / L, v0)
+    out = {"metric": "two-stream growth rate of the E_x energy / linear theory", "theory_rate": theory,
+           "theory_mode": m, "theory_max": math.sqrt(0.5) * (1 - v0 * v0) ** 0.75 / 2}
+    for split in ((False, True) if not args.no_fp64 else (True,)):
+        t, w, wall, npart, d = run_two_stream(torch, pp, ind, n, per_dim, v0, 0.01, args.ts_steps, split)
+        rate, whole, window = growth_rate_fit(t, w)
+        key = "fp32_split" if split else "fp64_plain"
+        if args.save_history:
+            import numpy as np
+            np.savez(f"{args.save_history}_{key}.npz", t=np.asarray(t), w=np.asarray(w))
+        out[key] = {"rate": rate, "rate_over_theory": rate / theory, "linear_phase": window,
+                    "rate_whole_phase": whole,
+                    "updates_per_s": npart * args.ts_steps / wall, "wall_s": wall,
+                    "final_gauss_rel": d.gauss_max / d.rho_ref, "flags": d.flags}
+        log(f"[two-stream] {key}: {out[key]}")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def serving_bench(args, torch, pp):
     """The serving ensemble: a Poisson stream of two-stream requests (grids 32^3, 64x32x32,
     128x16x16; 8-64 particles per cell per beam; beam speed 0.1-0.5 c; 200-2000 steps), served
@@ -230,7 +337,10 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
-    ap.add_argument("--workload", choices=("pair_mj", "serving"), default="pair_mj")
+    ap.add_argument("--workload", choices=("pair_mj", "serving", "two_stream"), default="pair_mj")
+    ap.add_argument("--grid-x", type=int, default=128, help="two-stream: cells along the beams")
+    ap.add_argument("--ts-steps", type=int, default=2000, help="two-stream: steps")
+    ap.add_argument("--save-history", default="", help="two-stream: save the E_x energy history to PATH_<form>.npz")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--rate", type=float, default=2.0, help="serving: mean arrivals per second")
     ap.add_argument("--slots", type=int, default=64, help="serving: most runs in the batch")
@@ -249,6 +359,8 @@ def main(argv=None):
 
     if args.workload == "serving":
         return serving_bench(args, torch, pp)
+    if args.workload == "two_stream":
+        return two_stream_bench(args, torch, pp)
 
     if args.calib_copy_gib > 0:
         nb = int(args.calib_copy_gib * (1 << 30))
