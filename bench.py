@@ -258,6 +258,55 @@ def two_stream_bench(args, torch, pp):
     return 0
 
 
+def kh_bench(args, torch, pp):
+    """Kelvin-Helmholtz shear layers: 1024x512x1 cells, electrons and ions (mass ratio 25),
+    64 particles per cell each (67,108,864 particles), bulk flows +-0.2c, u_th = 0.02c,
+    cubic weights, 6th-order fields, dt 0.4: whole-step throughput of the FP32 split form on
+    the flat (8x8x1) tile path, and of the FP64 plain form."""
+    from paper_1211_4575_amd import inputs_device as ind
+    n, ppc = (1024, 512, 1), 64
+    npart = n[0] * n[1] * n[2] * ppc
+    dev = torch.device("cuda:0")
+    res = {}
+    for split in ((True, False) if not args.no_fp64 else (True,)):
+        rt = torch.float32 if split else torch.float64
+        cells = [torch.empty(npart, dtype=torch.int32, device=dev) for _ in range(2)] if split else None
+        offs = [torch.empty((3, npart), dtype=rt, device=dev) for _ in range(2)]
+        us = [torch.empty((3, npart), dtype=rt, device=dev) for _ in range(2)]
+        ind.kelvin_helmholtz(SEED, n, 0, npart, 0.2, 8.0, 0.02, ind.split_mode(split, 3), cells,
+                             [[o[d] for d in range(3)] for o in offs], [[u[d] for d in range(3)] for u in us],
+                             torch.cuda.current_stream().cuda_stream)
+        species = []
+        for s, (q, m) in enumerate(((-1.0, 1.0), (1.0, 25.0))):
+            sp = dict(q=q, m=m, w=1.0 / ppc, u=us[s])
+            sp.update(dict(cell=cells[s], off=offs[s]) if split else dict(pos=offs[s]))
+            species.append(sp)
+        P = pp.make_params(n, shape_order=3, field_order=6, dt=0.4, alpha=0.55,
+                           precision=pp.PP_PREC_FP32_SPLIT if split else pp.PP_PREC_FP64,
+                           relax_tol=1e-8 if split else 1e-14, relax_max_iter=100)
+        run = pp.Run(P, species, with_id=False)
+        del cells, offs, us
+        steps = args.steps if split else max(1, args.fp64_steps)
+        wall, gpd_ms = time_steps(run, torch, steps, args.warmup if split else 1)
+        d = run.diagnostics(pp.PP_DIAG_MOMENTS | pp.PP_DIAG_FIELDS)
+        key = "fp32_split" if split else "fp64_plain"
+        res[key] = dict(updates_per_s=2 * npart * steps / wall, ms_per_step=1e3 * wall / steps,
+                        gpd_updates_per_s=2 * npart / (gpd_ms * 1e-3), flags=d.flags)
+        log(f"[kh] {key}: {res[key]}")
+        run.close()
+        del run
+        torch.cuda.empty_cache()
+    out = {"metric": "particle updates/s (gather+push+deposit) FP32 vs FP64; ensemble p50/p99",
+           "value": res["fp32_split"]["updates_per_s"], "unit": "particle updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["fp32_split"]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "Kelvin-Helmholtz 1024x512x1, 64 ppc/species, mass ratio 25, flows +-0.2c, "
+                                  "cubic weights, 6th-order fields, FP32 split positions (flat 8x8x1 tiles)",
+                      "particles": 2 * npart, "results": res}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def serving_bench(args, torch, pp):
     """The serving ensemble: a Poisson stream of two-stream requests (grids 32^3, 64x32x32,
     128x16x16; 8-64 particles per cell per beam; beam speed 0.1-0.5 c; 200-2000 steps), served
@@ -337,7 +386,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
-    ap.add_argument("--workload", choices=("pair_mj", "serving", "two_stream"), default="pair_mj")
+    ap.add_argument("--workload", choices=("pair_mj", "serving", "two_stream", "kh"), default="pair_mj")
     ap.add_argument("--grid-x", type=int, default=128, help="two-stream: cells along the beams")
     ap.add_argument("--ts-steps", type=int, default=2000, help="two-stream: steps")
     ap.add_argument("--save-history", default="", help="two-stream: save the E_x energy history to PATH_<form>.npz")
@@ -361,6 +410,8 @@ def main(argv=None):
         return serving_bench(args, torch, pp)
     if args.workload == "two_stream":
         return two_stream_bench(args, torch, pp)
+    if args.workload == "kh":
+        return kh_bench(args, torch, pp)
 
     if args.calib_copy_gib > 0:
         nb = int(args.calib_copy_gib * (1 << 30))

@@ -49,6 +49,15 @@ int ppi_two_stream_lattice(uint64_t seed, int32_t wl, const int32_t n[3], const 
                            double uth, int32_t split, int32_t* const cell[2], void* const off[2][3],
                            void* const u[2][3], void* hip_stream);
 
+/* Kelvin-Helmholtz shear layers (as inputs.kelvin_helmholtz): particle indices [start,
+ * start + count) of a box of n[0] x n[1] x n[2] cells, electrons (species 0) and ions
+ * (species 1) at the same uniform-random positions, bulk flow
+ * vx(y) = v0 (tanh((y - Ly/4)/width) - tanh((y - 3Ly/4)/width) - 1) and thermal proper
+ * velocities of spread uth per component.  Output layout and split modes as above. */
+int ppi_kelvin_helmholtz(uint64_t seed, const int32_t n[3], int64_t start, int64_t count, double v0, double width,
+                         double uth, int32_t split, int32_t* const cell[2], void* const off[2][3], void* const u[2][3],
+                         void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

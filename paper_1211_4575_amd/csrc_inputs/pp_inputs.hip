@@ -189,6 +189,61 @@ __global__ void __launch_bounds__(256) k_two_stream(TSArgs A) {
     }
 }
 
+struct KHArgs {
+    uint64_t seed;
+    int n[3];
+    int64_t start, count;
+    double v0, width, uth;
+    int split;
+    int32_t* cell[2];
+    void* off[2][3];
+    void* u[2][3];
+};
+
+// Kelvin-Helmholtz load (inputs.kelvin_helmholtz): uniform positions (stream 4/0/0, draw
+// blocks 0 and 1), bulk flow vx(y) = v0 (tanh((y - Ly/4)/width) - tanh((y - 3Ly/4)/width) - 1)
+// for both species at the same positions, thermal proper velocities (streams 4/s/1) plus
+// gamma(vx) vx along x.
+__global__ void __launch_bounds__(256) k_kelvin_helmholtz(KHArgs A) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= A.count) return;
+    const uint64_t idx = (uint64_t)(A.start + l);
+    double U[4];
+    uniform_pair(A.seed, idx, 0, stream_id(4, 0, 0), U[0], U[1]);
+    uniform_pair(A.seed, idx, 1, stream_id(4, 0, 0), U[2], U[3]);
+    double pos[3];
+    for (int d = 0; d < 3; ++d) {
+        double x = U[d] * A.n[d];
+        pos[d] = x >= A.n[d] ? 0.0 : x;
+    }
+    const double Ly = (double)A.n[1];
+    const double vx = A.v0 * (tanh((pos[1] - Ly / 4) / A.width) - tanh((pos[1] - 3 * Ly / 4) / A.width) - 1.0);
+    const double g = 1.0 / sqrt(1.0 - vx * vx);
+    int32_t cellv = 0;
+    float offf[3];
+    if (A.split) cellv = to_split(pos, A.n, A.split, offf);
+    for (int s = 0; s < 2; ++s) {
+        double V[4];
+        uniform_pair(A.seed, idx, 0, stream_id(4, s, 1), V[0], V[1]);
+        uniform_pair(A.seed, idx, 1, stream_id(4, s, 1), V[2], V[3]);
+        const double r0 = sqrt(-2.0 * log(V[0])), t0 = 2.0 * M_PI * V[1];
+        const double r1 = sqrt(-2.0 * log(V[2])), t1 = 2.0 * M_PI * V[3];
+        const double uv[3] = {A.uth * r0 * cos(t0) + vx * g, A.uth * r0 * sin(t0), A.uth * r1 * cos(t1)};
+        if (A.split) {
+            A.cell[s][l] = cellv;
+            for (int d = 0; d < 3; ++d) {
+                ((float*)A.off[s][d])[l] = offf[d];
+                ((float*)A.u[s][d])[l] = (float)uv[d];
+            }
+        } else {
+            for (int d = 0; d < 3; ++d) {
+                ((double*)A.off[s][d])[l] = pos[d];
+                ((double*)A.u[s][d])[l] = uv[d];
+            }
+        }
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -264,6 +319,37 @@ int ppi_pair_maxwell_juttner(uint64_t seed, const int32_t n[3], int64_t start, i
     }
     const int bs = 256;
     hipLaunchKernelGGL(k_pair_mj, dim3((unsigned)((count + bs - 1) / bs)), dim3(bs), 0, (hipStream_t)hip_stream, A);
+    return hipGetLastError() == hipSuccess ? 0 : -6;
+}
+
+int ppi_kelvin_helmholtz(uint64_t seed, const int32_t n[3], int64_t start, int64_t count, double v0, double width,
+                         double uth, int32_t split, int32_t* const cell[2], void* const off[2][3], void* const u[2][3],
+                         void* hip_stream) {
+    if (!n || start < 0 || count < 0 || !(v0 >= 0.0 && v0 < 0.5) || !(width > 0.0) || !(uth >= 0.0)) return -1;
+    for (int d = 0; d < 3; ++d)
+        if (n[d] < 1) return -1;
+    if (split < 0 || split > 2) return -1;
+    if (count == 0) return 0;
+    KHArgs A;
+    A.seed = seed;
+    for (int d = 0; d < 3; ++d) A.n[d] = n[d];
+    A.start = start;
+    A.count = count;
+    A.v0 = v0;
+    A.width = width;
+    A.uth = uth;
+    A.split = split;
+    for (int s = 0; s < 2; ++s) {
+        A.cell[s] = cell ? cell[s] : nullptr;
+        if (split && !A.cell[s]) return -1;
+        for (int d = 0; d < 3; ++d) {
+            A.off[s][d] = off[s][d];
+            A.u[s][d] = u[s][d];
+            if (!A.off[s][d] || !A.u[s][d]) return -1;
+        }
+    }
+    const int bs = 256;
+    hipLaunchKernelGGL(k_kelvin_helmholtz, dim3((unsigned)((count + bs - 1) / bs)), dim3(bs), 0, (hipStream_t)hip_stream, A);
     return hipGetLastError() == hipSuccess ? 0 : -6;
 }
 

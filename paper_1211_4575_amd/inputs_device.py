@@ -39,6 +39,11 @@ def lib():
                                              ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                              ctypes.POINTER(vp), vp]
         L.ppi_two_stream_lattice.restype = ctypes.c_int
+        L.ppi_kelvin_helmholtz.argtypes = [ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
+                                           ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                           ctypes.POINTER(vp), vp]
+        L.ppi_kelvin_helmholtz.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -76,3 +81,17 @@ def two_stream_lattice(seed, wl, n, per_dim, v_beam, uth, split, cells, offs, us
                                       hip_stream)
     if rc:
         raise RuntimeError(f"ppi_two_stream_lattice failed ({rc})")
+
+
+def kelvin_helmholtz(seed, n, start, count, v0, width, uth, split, cells, offs, us, hip_stream):
+    """Shear-layer load of particle indices [start, start + count) into device tensors (see
+    inputs.kelvin_helmholtz)."""
+    vp = ctypes.c_void_p
+    n_arr = (ctypes.c_int32 * 3)(*[int(v) for v in n])
+    cell_arr = (vp * 2)(*([c.data_ptr() for c in cells] if cells is not None else [None, None]))
+    off_arr = (vp * 6)(*[offs[s][d].data_ptr() for s in range(2) for d in range(3)])
+    u_arr = (vp * 6)(*[us[s][d].data_ptr() for s in range(2) for d in range(3)])
+    rc = lib().ppi_kelvin_helmholtz(seed, n_arr, start, count, v0, width, uth, int(split), cell_arr, off_arr, u_arr,
+                                    hip_stream)
+    if rc:
+        raise RuntimeError(f"ppi_kelvin_helmholtz failed ({rc})")

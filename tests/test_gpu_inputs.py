@@ -76,3 +76,30 @@ def test_device_two_stream_matches_host(split):
         else:
             assert np.array_equal(offs[s].cpu().numpy(), wl.species[s].pos)
             assert np.max(np.abs(u - uref)) <= 1e-14 * np.max(np.abs(uref))
+
+
+@pytest.mark.parametrize("split", [0, 2])
+def test_device_kelvin_helmholtz_matches_host(split):
+    import torch
+    from paper_1211_4575_amd import inputs_device as ind
+    n, ppc = (32, 24, 1), 4
+    wl = I.kelvin_helmholtz(n=n, ppc=ppc, width=3.0)
+    cnt = wl.species[0].pos.shape[1]
+    rt = torch.float32 if split else torch.float64
+    cells = [torch.empty(cnt, dtype=torch.int32, device="cuda") for _ in range(2)] if split else None
+    offs = [torch.empty((3, cnt), dtype=rt, device="cuda") for _ in range(2)]
+    us = [torch.empty((3, cnt), dtype=rt, device="cuda") for _ in range(2)]
+    ind.kelvin_helmholtz(I.SEED_BASE, n, 0, cnt, 0.2, 3.0, 0.02, split, cells, [[o[d] for d in range(3)] for o in offs],
+                         [[u[d] for d in range(3)] for u in us], torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    for s in range(2):
+        u = us[s].cpu().numpy().astype(np.float64)
+        uref = wl.species[s].u
+        if split:
+            cell, off = I.to_split(wl.species[s].pos, n, origin="floor")
+            assert np.array_equal(cells[s].cpu().numpy(), cell)
+            assert np.array_equal(offs[s].cpu().numpy(), off)
+            assert np.max(np.abs(u - uref)) <= 1e-7 * np.max(np.abs(uref))
+        else:
+            assert np.array_equal(offs[s].cpu().numpy(), wl.species[s].pos)
+            assert np.max(np.abs(u - uref)) <= 1e-14 * np.max(np.abs(uref))
