@@ -1,6 +1,17 @@
 // FP64 diagnostics: kinetic energy and momentum per species, field energies, the charge
 // density (eq. "rho2", same weights as the gather), the Gauss-law residual with the
 // field-order divergence, the discrete continuity residual (eq. "cc1") and div B.
+//
+// Charge density of the split form, once the particles are stored tile by tile: one
+// workgroup per tile adds the (O+1)^3 contributions q w W of each of its particles to an LDS
+// block of the tile plus its support halo (1 node below, O above), in 64-bit fixed point
+// (the contribution scaled by 2^e and rounded by one fused multiply-add with 1.5*2^52, whose
+// bit pattern is added with an integer atomic; the node sum is the sign-extended low 51
+// bits).  The block is then added to a global 64-bit accumulator, and a last pass writes
+// rho = sum * 2^-e.  A particle found outside the tile it is stored with (after a push, before
+// the sort) adds its rounded contributions straight to the global accumulator.  The result
+// is the exact sum of the rounded contributions, whatever the order.  The FP64 form, and a
+// split species never sorted, use one thread per particle with FP64 global atomics.
 #include "pp_device.hpp"
 #include "pp_internal.hpp"
 
@@ -18,6 +29,8 @@ enum {
     ACC_DIVB,
     ACC_COUNT
 };
+// device-only slot after the copied accumulators: 2^e of the fixed-point charge density
+constexpr int ACC_RHO_SCALE = ACC_COUNT;
 
 __device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
     atomicMax((unsigned long long*)p, (unsigned long long)__double_as_longlong(v));
@@ -154,6 +167,148 @@ __global__ void __launch_bounds__(256) k_deposit_rho(int nx, int ny, int nz, con
     }
 }
 
+// ---- split form: tiled fixed-point charge deposit ------------------------------------------
+struct Rho32Sp {
+    const int32_t* start;  // tile starts of the stored order (ntiles + 1)
+    const int32_t* cell;
+    const float* pos[3];
+    double qw;
+};
+
+struct Rho32Args {
+    int n[3], t[3], nt[3];
+    int ext[3];  // LDS block extent per axis: t + O + 1 (1 on a single-cell axis)
+    int lo[3];   // halo below the tile: 1 (0 on a single-cell axis)
+    int64_t nc;
+    int nsp;
+    Rho32Sp sp[PP_MAX_SPECIES];
+    unsigned long long* acc;  // nc, zero on entry
+    const double* scale;      // 2^e
+};
+
+constexpr double RHO_MAGIC = 6755399441055744.0;  // 1.5 * 2^52
+constexpr unsigned long long RHO_LOW51 = (1ull << 51) - 1ull;
+constexpr long long RHO_BIT50 = 1ll << 50;
+
+// sum of the rounded values held in the low 51 bits of a sum of bit patterns
+__device__ __forceinline__ long long rho_fixed_sum(unsigned long long v) {
+    return (long long)((v & RHO_LOW51) ^ (unsigned long long)RHO_BIT50) - RHO_BIT50;
+}
+
+// bit pattern of 1.5*2^52 + round(x), |x| < 2^50
+__device__ __forceinline__ unsigned long long rho_pattern(double a, double b) {
+    return (unsigned long long)__double_as_longlong(fma(a, b, RHO_MAGIC));
+}
+
+// 2^e with e = e0 - ceil(log2(N)), N the sum of the largest tile populations of the
+// deposited species: a contribution is at most 2^(50 - ceil log2 N) and an LDS node sum at
+// most 2^50 in magnitude.
+__global__ void k_rho_scale(const int32_t* __restrict__ tile_max, unsigned mask, int e0, double* scale) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    long long nb = 0;
+    for (int s = 0; s < PP_MAX_SPECIES; ++s)
+        if (mask & (1u << s)) nb += tile_max[s];
+    int lg = 0;
+    while ((1ll << lg) < nb) ++lg;
+    *scale = ldexp(1.0, e0 - lg);
+}
+
+template <int O>
+__global__ void __launch_bounds__(256) k_rho32(Rho32Args A) {
+    extern __shared__ unsigned long long rho_blk[];
+    const int64_t tile = blockIdx.x;
+    const int ti = (int)(tile % A.nt[0]);
+    const int tj = (int)((tile / A.nt[0]) % A.nt[1]);
+    const int tk = (int)(tile / ((int64_t)A.nt[0] * A.nt[1]));
+    const int org[3] = {ti * A.t[0], tj * A.t[1], tk * A.t[2]};
+    const int vol = A.ext[0] * A.ext[1] * A.ext[2];
+    for (int q = threadIdx.x; q < vol; q += blockDim.x) rho_blk[q] = 0ull;
+    __syncthreads();
+    const double sc = *A.scale;
+    const float flo = O == 2 ? -0.5f : 0.0f;
+    const int nxy = A.n[0] * A.n[1];
+    for (int s = 0; s < A.nsp; ++s) {
+        const Rho32Sp& S = A.sp[s];
+        const double v = S.qw * sc;
+        const int32_t end = S.start[tile + 1];
+        for (int32_t p = S.start[tile] + threadIdx.x; p < end; p += blockDim.x) {
+            const int32_t cell = S.cell[p];
+            if (cell < 0 || (int64_t)cell >= A.nc) continue;  // reported by the error flags
+            const int g[3] = {cell % A.n[0], (cell / A.n[0]) % A.n[1], cell / nxy};
+            const float f[3] = {S.pos[0][p], S.pos[1][p], S.pos[2][p]};
+            bool finite = true, in_block = true;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                finite = finite && fabsf(f[d]) <= 1048576.0f;  // false for NaN and Inf as well
+                const int l = g[d] - org[d];
+                in_block = in_block && l >= 0 && l < A.t[d] && f[d] >= flo && f[d] < flo + 2.0f;
+            }
+            if (!finite) continue;  // reported by the error flags
+            double w[3][O + 1];
+            int i0[3];
+            if (in_block) {
+                // support inside the block: nodes g - 1 .. g + O, i.e. block indices 0 .. t + O
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    i0[d] = weights_abs<O>((double)(g[d] - org[d] + A.lo[d]) + (double)f[d], w[d]);
+#pragma unroll
+                for (int c = 0; c <= O; ++c) {
+                    const int zc = A.ext[2] == 1 ? 0 : i0[2] + c;
+#pragma unroll
+                    for (int b = 0; b <= O; ++b) {
+                        const int yb = A.ext[1] == 1 ? 0 : i0[1] + b;
+                        const double vzy = v * w[2][c] * w[1][b];
+                        const int row = A.ext[0] * (yb + A.ext[1] * zc);
+#pragma unroll
+                        for (int a = 0; a <= O; ++a) {
+                            const int xa = A.ext[0] == 1 ? 0 : i0[0] + a;
+                            atomicAdd(&rho_blk[row + xa], rho_pattern(vzy, w[0][a]));
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) i0[d] = weights_abs<O>((double)g[d] + (double)f[d], w[d]);
+#pragma unroll
+                for (int c = 0; c <= O; ++c) {
+                    const int k = wrap(i0[2] + c, A.n[2]);
+#pragma unroll
+                    for (int b = 0; b <= O; ++b) {
+                        const int j = wrap(i0[1] + b, A.n[1]);
+                        const double vzy = v * w[2][c] * w[1][b];
+#pragma unroll
+                        for (int a = 0; a <= O; ++a) {
+                            const int i = wrap(i0[0] + a, A.n[0]);
+                            const long long x = rho_fixed_sum(rho_pattern(vzy, w[0][a]));
+                            atomicAdd(A.acc + (int64_t)i + (int64_t)A.n[0] * (j + (int64_t)A.n[1] * k),
+                                      (unsigned long long)x);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < vol; q += blockDim.x) {
+        const long long x = rho_fixed_sum(rho_blk[q]);
+        if (x == 0) continue;
+        const int a = q % A.ext[0];
+        const int b = (q / A.ext[0]) % A.ext[1];
+        const int c = q / (A.ext[0] * A.ext[1]);
+        const int i = wrap(org[0] - A.lo[0] + a, A.n[0]);
+        const int j = wrap(org[1] - A.lo[1] + b, A.n[1]);
+        const int k = wrap(org[2] - A.lo[2] + c, A.n[2]);
+        atomicAdd(A.acc + (int64_t)i + (int64_t)A.n[0] * (j + (int64_t)A.n[1] * k), (unsigned long long)x);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_rho_from_fixed(const unsigned long long* __restrict__ acc, int64_t nc,
+                                                        const double* __restrict__ scale, double* rho) {
+    const double inv = 1.0 / *scale;  // exact: a power of two
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nc; q += (int64_t)gridDim.x * blockDim.x)
+        rho[q] = (double)(long long)acc[q] * inv;
+}
+
 struct DivGeom {
     int n[3];
     int64_t nc;
@@ -253,6 +408,56 @@ static void deposit_rho_species(pp_run* r, const Species& S) {
                            (const T*)S.cur.pos[2], S.n, qw, r->rho, split);
 }
 
+// Tiled charge deposit of the split species in mask (each stored tile by tile); writes rho.
+static hipError_t launch_rho32(pp_run* r, unsigned mask) {
+    Rho32Args A;
+    const int O = r->p.shape_order;
+    double qwmax = 0.0;
+    A.nsp = 0;
+    for (int s = 0; s < PP_MAX_SPECIES; ++s) {
+        if (!(mask & (1u << s))) continue;
+        const Species& S = r->sp[s];
+        Rho32Sp& D = A.sp[A.nsp++];
+        D.start = S.offsets;
+        D.cell = (const int32_t*)S.cur.cell;
+        for (int d = 0; d < 3; ++d) D.pos[d] = (const float*)S.cur.pos[d];
+        D.qw = S.q * S.w;
+        qwmax = fabs(D.qw) > qwmax ? fabs(D.qw) : qwmax;
+    }
+    int vol = 1;
+    for (int d = 0; d < 3; ++d) {
+        A.n[d] = r->p.n[d];
+        A.t[d] = r->g.t[d];
+        A.nt[d] = r->g.nt[d];
+        const bool single = r->p.n[d] == 1;
+        A.ext[d] = single ? 1 : r->g.t[d] + O + 1;
+        A.lo[d] = single ? 0 : 1;
+        vol *= A.ext[d];
+    }
+    A.nc = r->g.ncell;
+    A.acc = (unsigned long long*)r->Jq;  // free between steps: the particle kernel clears it
+    A.scale = r->dacc + ACC_RHO_SCALE;
+    // every contribution is at most |q w| (the weights of a node are at most 1)
+    int e0 = 50 - (int)ceil(log2(qwmax));
+    if (e0 > 1000) e0 = 1000;
+    hipLaunchKernelGGL(k_rho_scale, dim3(1), dim3(64), 0, r->stream, (const int32_t*)r->tile_max, mask, e0,
+                       r->dacc + ACC_RHO_SCALE);
+    hipError_t e = launch_fill((double*)r->Jq, A.nc, 0.0, r->stream);  // all-zero bits
+    if (e != hipSuccess) return e;
+    const size_t lds = (size_t)vol * sizeof(unsigned long long);
+    if (O == 2)
+        hipLaunchKernelGGL(k_rho32<2>, dim3((unsigned)r->g.ntiles), dim3(256), lds, r->stream, A);
+    else
+        hipLaunchKernelGGL(k_rho32<3>, dim3((unsigned)r->g.ntiles), dim3(256), lds, r->stream, A);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int64_t g = (A.nc + 255) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_rho_from_fixed, dim3((unsigned)g), dim3(256), 0, r->stream,
+                       (const unsigned long long*)r->Jq, A.nc, (const double*)(r->dacc + ACC_RHO_SCALE), r->rho);
+    return hipGetLastError();
+}
+
 // Fills host_out[0..ACC_COUNT) with the accumulators and [ACC_COUNT] with the flag word.
 hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out) {
     const int bs = 256;
@@ -290,11 +495,24 @@ hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out) {
     const bool want_divb = (what & PP_DIAG_DIVB) != 0;
     bool have_prev = false;
     if (want_rho) {
-        e = launch_fill(r->rho, nc, 0.0, r->stream);
+        // split species stored tile by tile (sorted, or pushed since the last sort) go through
+        // the tiled fixed-point deposit, which writes every node of rho; the others are added
+        // with FP64 atomics
+        unsigned tiled = 0;
+        if (split)
+            for (int s = 0; s < PP_MAX_SPECIES; ++s) {
+                const Species& S = r->sp[s];
+                if (S.active && S.n > 0 && S.q * S.w != 0.0 && (S.sorted || S.ranked)) tiled |= 1u << s;
+            }
+        if (tiled) {
+            e = launch_rho32(r, tiled);
+        } else {
+            e = launch_fill(r->rho, nc, 0.0, r->stream);
+        }
         if (e != hipSuccess) return e;
         for (int s = 0; s < PP_MAX_SPECIES; ++s) {
             const Species& S = r->sp[s];
-            if (!S.active || S.n == 0) continue;
+            if (!S.active || S.n == 0 || S.q * S.w == 0.0 || (tiled & (1u << s))) continue;
             if (split)
                 deposit_rho_species<float>(r, S);
             else

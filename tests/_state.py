@@ -44,3 +44,20 @@ def rel_inf(a, b):
 def rel_l2(a, b):
     den = np.linalg.norm(b.ravel())
     return np.linalg.norm((a - b).ravel()) / (den if den > 0 else 1.0)
+
+
+def poisson_E(orc, P, rho):
+    """E = (up derivatives of phi) with div_down E = rho - mean(rho): the potential solves the
+    field-order discrete Poisson equation by FFT, with the exact symbol of the composed
+    down(up) stencils taken from the oracle's derivatives of a unit impulse."""
+    shape = rho.shape
+    sym = np.zeros(shape)
+    delta = np.zeros(shape)
+    delta[0, 0, 0] = 1.0
+    for d in range(3):
+        sym += np.fft.fftn(orc.deriv(P, orc.deriv(P, delta, d, True), d, False)).real
+    rh = np.fft.fftn(rho)
+    rh[0, 0, 0] = 0.0
+    sym[0, 0, 0] = 1.0
+    phi = np.ascontiguousarray(np.fft.ifftn(rh / sym).real)
+    return np.stack([orc.deriv(P, phi, d, True) for d in range(3)])

@@ -10,7 +10,7 @@ import sys
 import numpy as np
 import pytest
 
-from _state import periodic_diff, random_state, rel_inf, rel_l2
+from _state import periodic_diff, poisson_E, random_state, rel_inf, rel_l2
 from paper_1211_4575_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -176,6 +176,53 @@ def test_fp32_gauss_residual_one_step(ppm, orc):
     assert d1.gauss_max / d1.rho_ref < 1e-6
     assert d1.cc_max / d1.rho_ref < 1e-6
     run.close()
+
+
+RHO_CASES = [((16, 12, 8), 3), ((16, 12, 8), 2), ((20, 9, 1), 3), ((7, 10, 6), 2)]
+
+
+@pytest.mark.parametrize("ci", range(len(RHO_CASES)), ids=[str(c) for c in RHO_CASES])
+def test_fp32_charge_density_matches_oracle(ppm, orc, ci):
+    # the split form's charge density (unsorted: FP64 atomics; sorted and after a push without
+    # sort: the tiled fixed-point deposit) against the oracle's deposit of the same positions,
+    # read through the Gauss residual of an E field whose down divergence is the oracle's rho
+    n, O = RHO_CASES[ci]
+    _say("fp32 rho", n, O)
+    rng = np.random.default_rng(40 + ci)
+    ncell = n[0] * n[1] * n[2]
+    species = []
+    for q, m, ppc in ((-1.0, 1.0, 8), (1.0, 25.0, 4)):
+        npart = ncell * ppc
+        pos = rng.uniform(0, 1, (3, npart)) * np.array(n, dtype=np.float64)[:, None]
+        pos = np.where(pos >= np.array(n)[:, None], 0.0, pos)
+        species.append(dict(q=q, m=m, w=1.0 / 8, pos=pos, u=rng.normal(0, 0.3, (3, npart))))
+    sp32 = _split_species(species, n, O)
+    mean = sum(s["q"] * s["w"] * s["cell"].size for s in sp32) / ncell
+    P = orc.make_params(n=n, shape_order=O, field_order=6)
+    run = ppm.Run(ppm.make_params(n=n, shape_order=O, field_order=6, precision=ppm.PP_PREC_FP32_SPLIT,
+                                  rho_background=-mean), sp32)
+
+    def check(tag):
+        rho = np.zeros((n[2], n[1], n[0]))
+        for s, sp in enumerate(sp32):
+            g = run.particles(s)
+            orc.deposit_rho(P, sp["q"], sp["w"], np.ascontiguousarray(I.from_split(g["cell"], g["pos"], n)), rho)
+        run.E.copy_(ppm_tensor(run, poisson_E(orc, P, rho)))
+        d = run.diagnostics(ppm.PP_DIAG_RHO)
+        assert d.gauss_max / d.rho_ref < 1e-10, (tag, d.gauss_max)
+
+    check("unsorted")
+    run.sort()
+    check("sorted")
+    run.gather_push_deposit()
+    check("pushed")
+    run.sort()
+    check("sorted again")
+    run.close()
+
+
+def ppm_tensor(run, a):
+    return run.torch.as_tensor(np.ascontiguousarray(a)).to(run.E.device)
 
 
 def test_fp64_whole_run_plain_heating(ppm, orc):

@@ -156,3 +156,29 @@ def test_field_step_matches_fft_solve(orc):
     rhs = B0 + al * (1 - al) * s * lapB0 - dt * orc.curl_up(P, E0) + al * dt * dt * orc.curl_up(P, J)
     Bx = np.real(np.fft.ifftn(np.fft.fftn(rhs, axes=(1, 2, 3)) / (1 + al * al * s * K2)[None], axes=(1, 2, 3)))
     assert np.max(np.abs(B - Bx)) < 1e-12 * np.max(np.abs(Bx))
+
+
+@pytest.mark.parametrize("fo", [2, 6])
+def test_poisson_helper_inverts_the_down_divergence(orc, fo):
+    # the test helper that builds an E field with a given down divergence: div_down E equals
+    # rho minus its mean, and its stencil symbol is minus the sum of K_d^2 (closed form above)
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from _state import poisson_E
+    rng = np.random.default_rng(11)
+    N = (10, 6, 8)
+    d = (1.0, 0.8, 1.2)
+    P = orc.make_params(n=N, d=d, field_order=fo)
+    rho = rng.normal(size=(N[2], N[1], N[0]))
+    E = poisson_E(orc, P, rho)
+    assert np.max(np.abs(orc.div_down(P, E) - (rho - rho.mean()))) < 1e-12 * np.max(np.abs(rho))
+    a = orc.fd_coeffs(fo)
+    delta = np.zeros((N[2], N[1], N[0]))
+    delta[0, 0, 0] = 1.0
+    for dim in range(3):
+        k = 2 * math.pi * np.fft.fftfreq(N[dim])
+        K = (2 / d[dim]) * sum(a[i] * np.sin((i + 0.5) * k) for i in range(3))
+        sym = np.fft.fftn(orc.deriv(P, orc.deriv(P, delta, dim, True), dim, False))
+        line = sym[(0,) * (2 - dim) + (slice(None),) + (0,) * dim]
+        assert np.max(np.abs(line - (-K * K))) < 1e-12
