@@ -177,7 +177,7 @@ pp_status pp_batch_step(pp_batch* b) {
     for (int j = 0; j < nl; ++j) {
         pp_run* r = b->runs[line_runs[j]];
         line_desc(r, r->J2, r->mesh.J, (LineArgs*)(H + o_line + j * line_desc_size()));
-        lpre[j + 1] = lpre[j] + field_blocks(r);
+        lpre[j + 1] = lpre[j] + line_blocks(r);
     }
     int64_t stot[PP_MAX_SPECIES][SORT_BATCH_PHASES];
     for (int s = 0; s < PP_MAX_SPECIES; ++s) {

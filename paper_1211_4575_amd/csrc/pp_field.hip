@@ -387,10 +387,16 @@ struct LineArgs {
     FieldGeom G;
     const double* coef[3];
     int len[3], off[3];
+    // LDS form: W[c] lines of component c per block (a power of two, at most 64) and the
+    // blocks of each component; W[0] == 0 selects the global-memory form
+    int W[3];
+    int64_t nb[3];
     const double* J2;
     double* J;
 };
 
+// Global-memory form (lines too long for the LDS copy): one thread per cell, the stencil
+// read through the caches.
 __device__ __forceinline__ void line_body(const LineArgs& A, int64_t b) {
     int ijk[3];
     if (!field_cell(A.G, b, threadIdx.x, ijk[0], ijk[1], ijk[2])) return;
@@ -414,14 +420,108 @@ __device__ __forceinline__ void line_body(const LineArgs& A, int64_t b) {
     }
 }
 
-__global__ void __launch_bounds__(FIELD_BS) k_line_solve(LineArgs A) { line_body(A, blockIdx.x); }
+// LDS form.  A block takes W lines of one component along that component's axis, copies
+// each line, extended by the stencil's wrap-around (ext = N + len - 1 values starting at
+// offset off), into LDS with coalesced loads, then writes J[j] = sum_t coef[t] ext[j + t].
+// x lines are rows (stored line by line, j fastest); y and z lines are taken W consecutive
+// x at a time (stored with the W lines interleaved, x fastest), so loads and stores move
+// whole rows or W-wide row segments.
+constexpr int LINE_LDS_DOUBLES = 4096;  // 32 KiB
+
+__device__ __forceinline__ void line_lds_body(const LineArgs& A, int64_t b, double* e) {
+    const FieldGeom& G = A.G;
+    int c = 0;
+    if (b >= A.nb[0]) {
+        b -= A.nb[0];
+        c = 1;
+        if (b >= A.nb[1]) {
+            b -= A.nb[1];
+            c = 2;
+        }
+    }
+    if (c == 2 && b >= A.nb[2]) return;
+    const int n0 = G.n[0], n1 = G.n[1];
+    const int N = G.n[c], W = A.W[c], len = A.len[c], off = A.off[c];
+    const int ext = N + len - 1;
+    const int64_t nc = G.nc;
+    const double* src = A.J2 + (int64_t)c * nc;
+    double* dst = A.J + (int64_t)c * nc;
+    // first line of the block and the line count / axis stride
+    int64_t base0;
+    int stride, nlines;
+    if (c == 0) {
+        const int64_t L0 = b * W;
+        const int64_t rows = (int64_t)n1 * G.n[2];
+        base0 = L0 * n0;
+        stride = 1;
+        nlines = (int)(rows - L0 < W ? rows - L0 : W);
+    } else {
+        const int nbx = (n0 + W - 1) / W;
+        const int bx = (int)(b % nbx);
+        const int64_t other = b / nbx;  // k for y lines, j for z lines
+        const int i0 = bx * W;
+        base0 = c == 1 ? i0 + (int64_t)n0 * n1 * other : i0 + (int64_t)n0 * other;
+        stride = c == 1 ? n0 : n0 * n1;
+        nlines = n0 - i0 < W ? n0 - i0 : W;
+    }
+    // line w starts at base0 + w * (x lines: n0, else 1)
+    const int64_t lstep = c == 0 ? n0 : 1;
+    const int total = ext * W;
+    for (int q = threadIdx.x; q < total; q += FIELD_BS) {
+        int w, jj;
+        if (c == 0) {
+            w = q / ext;
+            jj = q - w * ext;
+        } else {
+            jj = q / W;
+            w = q - jj * W;
+        }
+        int sidx = (off + jj) % N;
+        if (sidx < 0) sidx += N;
+        e[q] = w < nlines ? src[base0 + w * lstep + (int64_t)sidx * stride] : 0.0;
+    }
+    __syncthreads();
+    const int outs = N * W;
+    for (int q = threadIdx.x; q < outs; q += FIELD_BS) {
+        int w, j, es, eb;
+        if (c == 0) {
+            w = q / N;
+            j = q - w * N;
+            eb = w * ext + j;
+            es = 1;
+        } else {
+            j = q / W;
+            w = q - j * W;
+            eb = j * W + w;
+            es = W;
+        }
+        if (w >= nlines) continue;
+        const double* cf = A.coef[c];
+        double s = 0.0;
+        for (int t = 0; t < len; ++t) s += cf[t] * e[eb + t * es];
+        dst[base0 + w * lstep + (int64_t)j * stride] = s;
+    }
+}
+
+__device__ __forceinline__ void line_any(const LineArgs& A, int64_t b, double* e) {
+    if (A.W[0] > 0)
+        line_lds_body(A, b, e);
+    else
+        line_body(A, b);
+}
+
+__global__ void __launch_bounds__(FIELD_BS) k_line_solve(LineArgs A) {
+    __shared__ double e[LINE_LDS_DOUBLES];
+    line_any(A, blockIdx.x, e);
+}
 
 __global__ void __launch_bounds__(FIELD_BS) k_line_solve_batch(const LineArgs* __restrict__ T,
                                                                const int64_t* __restrict__ prefix, int nruns) {
+    __shared__ double e[LINE_LDS_DOUBLES];
     const int64_t b = blockIdx.x;
     const int r = find_segment(prefix, nruns, b);
     if (r < 0) return;
-    line_body(T[r], b - prefix[r]);
+    line_any(T[r], b - prefix[r], e);
 }
 
 // Host: coefficients of T^{-1} on a periodic line of N cells, by the discrete Fourier
@@ -444,10 +544,12 @@ int line_setup_axis(int order, int N, double* coef_host, int* off) {
         }
         return s / N;
     };
+    // the coefficients decay geometrically down to the rounding noise of the sum (~1e-17);
+    // keep them while two consecutive ones stand above 1e-16 of the centre value
     const double g0 = g(0);
     int Rr = 0;
     while (Rr < N / 2 && Rr < 63) {
-        if (fabs(g(Rr + 1)) < 1e-18 * fabs(g0)) break;
+        if (fabs(g(Rr + 1)) < 1e-16 * fabs(g0) && fabs(g(Rr + 2)) < 1e-16 * fabs(g0)) break;
         ++Rr;
     }
     if (2 * Rr + 1 >= N) {  // full circulant: offsets 0..N-1
@@ -462,10 +564,26 @@ int line_setup_axis(int order, int N, double* coef_host, int* off) {
 
 void line_desc(const pp_run* r, const double* J2, double* J, LineArgs* A) {
     A->G = make_geom(r);
+    bool fits = true;
     for (int d = 0; d < 3; ++d) {
         A->coef[d] = r->line[d].coef;
         A->len[d] = r->line[d].len;
         A->off[d] = r->line[d].off;
+        const int ext = r->p.n[d] + r->line[d].len - 1;
+        int W = 64;
+        while (W > 1 && (int64_t)W * ext > LINE_LDS_DOUBLES) W >>= 1;
+        if ((int64_t)W * ext > LINE_LDS_DOUBLES) fits = false;
+        A->W[d] = W;
+        const int64_t n0 = r->p.n[0];
+        if (d == 0)
+            A->nb[d] = ((int64_t)r->p.n[1] * r->p.n[2] + W - 1) / W;
+        else
+            A->nb[d] = ((n0 + W - 1) / W) * (d == 1 ? r->p.n[2] : r->p.n[1]);
+    }
+    if (!fits) {
+        A->W[0] = 0;
+        A->nb[0] = blocks_of(A->G);
+        A->nb[1] = A->nb[2] = 0;
     }
     A->J2 = J2;
     A->J = J;
@@ -473,10 +591,17 @@ void line_desc(const pp_run* r, const double* J2, double* J, LineArgs* A) {
 
 size_t line_desc_size() { return sizeof(LineArgs); }
 
+int64_t line_blocks(const pp_run* r) {
+    LineArgs A;
+    line_desc(r, nullptr, nullptr, &A);
+    return A.nb[0] + A.nb[1] + A.nb[2];
+}
+
 hipError_t launch_line_solve(pp_run* r, const double* J2, double* J) {
     LineArgs A;
     line_desc(r, J2, J, &A);
-    hipLaunchKernelGGL(k_line_solve, dim3((unsigned)blocks_of(A.G)), dim3(FIELD_BS), 0, r->stream, A);
+    hipLaunchKernelGGL(k_line_solve, dim3((unsigned)(A.nb[0] + A.nb[1] + A.nb[2])), dim3(FIELD_BS), 0, r->stream,
+                       A);
     return hipGetLastError();
 }
 

@@ -130,7 +130,7 @@ hipError_t launch_gpd64(pp_run* r, int s, double* J);
 hipError_t launch_gpd32(pp_run* r, double* J);
 hipError_t launch_line_solve(pp_run* r, const double* J2, double* J);
 hipError_t launch_field_step(pp_run* r);
-int64_t field_blocks(const pp_run* r);  // blocks of one field / line-solve launch of this run
+int64_t field_blocks(const pp_run* r);  // blocks of one field launch of this run
 // Sort species s: FP64 form, counting sort by cell; split form, round-major order per tile,
 // from the particle kernel's counts and ranks when it has run since the last sort, otherwise
 // (first sort, arbitrary order) by bucketing and a per-tile rebuild.
@@ -161,6 +161,7 @@ void field_desc(const pp_run* r, FieldDesc* D);
 hipError_t launch_field_step_batch(const void* table, const int64_t* prefix, int n, int64_t total_blocks,
                                    int max_sweeps, hipStream_t st);
 size_t line_desc_size();
+int64_t line_blocks(const pp_run* r);  // blocks of one line-solve launch of this run
 void line_desc(const pp_run* r, const double* J2, double* J, LineArgs* A);
 hipError_t launch_line_solve_batch(const void* table, const int64_t* prefix, int n, int64_t total_blocks, hipStream_t st);
 size_t sort_desc_size();

@@ -399,23 +399,39 @@ __device__ __forceinline__ void round_table_tile(const RankedArgs& A, int64_t t)
         mx = other > mx ? other : mx;
     }
     const int rmax = mx < SORT_RCAP ? mx : SORT_RCAP;
+    // rounds base .. base + 63: lane l keeps the mask of round base + l, a scan over the lanes
+    // gives the counts before it, and the entries are stored together
     int run = 0;
-    for (int r = 0; r < rmax; ++r) {
-        const uint64_t m = __ballot(c > r);
-        if (lane == 0) {
-            RoundEntry e;
-            e.mask = m;
-            e.before = run;
-            e.pad = 0;
-            A.rounds[t * SORT_RCAP + r] = e;
+    for (int base = 0; base < rmax; base += 64) {
+        const int nr = rmax - base < 64 ? rmax - base : 64;
+        uint64_t mine = 0;
+        for (int r = 0; r < nr; ++r) {
+            const uint64_t m = __ballot(c > base + r);
+            mine = lane == r ? m : mine;
         }
-        run += (int)__popcll(m);
+        const int pc = (int)__popcll(mine);  // 0 for lanes past the last round
+        int incl = pc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int up = __shfl_up(incl, o, 64);
+            incl += lane >= o ? up : 0;
+        }
+        if (lane < nr) {
+            RoundEntry e;
+            e.mask = mine;
+            e.before = run + incl - pc;
+            e.pad = 0;
+            A.rounds[t * SORT_RCAP + base + lane] = e;
+        }
+        run += __shfl(incl, 63, 64);
     }
     if (lane == 0) {
         A.tot[t] = tot;
         A.rtot[t] = run;
         A.ovf[t] = 0;
-        atomicMax(A.tile_max, tot);
+        // one address for every tile: read first (the value only grows, so a stale read
+        // can only cause an unneeded atomic), so that few of the atomics are issued
+        if (tot > *(volatile int32_t*)A.tile_max) atomicMax(A.tile_max, tot);
         if (t == A.ntiles - 1) A.tot[A.ntiles] = 0;
     }
 }
@@ -450,7 +466,9 @@ __device__ __forceinline__ int32_t ranked_pos(const RankedArgs& A, int32_t p) {
 constexpr int MOVE_BS = 1024;
 constexpr int MOVE_WORDS = 7;  // cell, pos[3], u[3]
 
-size_t move_lds_bytes(int cap) { return (size_t)cap * (sizeof(int32_t) * (1 + MOVE_WORDS) + 1); }
+// image words plus one "filled" byte per slot; at 32 ppc per species (mean tile 2048, cap
+// 2816) two workgroups fit in a CU's 160 KiB
+size_t move_lds_bytes(int cap) { return (size_t)cap * (sizeof(int32_t) * MOVE_WORDS + 1); }
 
 __device__ __forceinline__ void move_one(const RankedArgs& A, int32_t p, int32_t pos) {
     A.cell_o[pos] = A.cell[p];
