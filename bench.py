@@ -258,6 +258,149 @@ def two_stream_bench(args, torch, pp):
     return 0
 
 
+def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress=250):
+    """Mixed-mode two-stream run on g^3 cells of a cubic box of ``box`` skin depths, generated
+    on the device (FP32 split form).  Returns (times, energies [steps + 1, 4], wall s,
+    particles, final diagnostics): per step the energy of E projected on the MMI direction
+    (74 degrees from the beam: |E_perp| sin + E_z cos), of E_z, and of the x-y mean of E_z
+    (wave vectors along the beam); every half time unit (NaN otherwise) the longitudinal field
+    energy E.k/|k| of the Fourier modes 60-80 degrees from the beam with 1 <= |k| <= 8."""
+    import numpy as np
+
+    from paper_1211_4575_amd import inputs as I
+    n, dx = (g, g, g), box / g
+    dt = cfl * dx
+    npart = n[0] * n[1] * n[2] * ppc
+    dev = torch.device("cuda:0")
+    cells = [torch.empty(npart, dtype=torch.int32, device=dev) for _ in range(4)]
+    offs = [torch.empty((3, npart), dtype=torch.float32, device=dev) for _ in range(4)]
+    us = [torch.empty((3, npart), dtype=torch.float32, device=dev) for _ in range(4)]
+    st = torch.cuda.current_stream().cuda_stream
+    chunk = 1 << 25
+    for start in range(0, npart, chunk):
+        cnt = min(chunk, npart - start)
+        ind.mmi(SEED, n, start, cnt, 4.0, T_b, T_p, 1836.0, ind.split_mode(True, 3), [c[start:] for c in cells],
+                [[o[d, start:] for d in range(3)] for o in offs], [[u[d, start:] for d in range(3)] for u in us], st)
+    species = []
+    for s, (nm, q, ion, beam) in enumerate(I.MMI_SPECIES):
+        species.append(dict(q=q, m=1836.0 if ion else 1.0, w=(0.1 if beam else 0.9) / ppc, u=us[s], cell=cells[s],
+                            off=offs[s]))
+    P = pp.make_params(n, d=(dx, dx, dx), dt=dt, shape_order=3, field_order=6, alpha=0.55,
+                       precision=pp.PP_PREC_FP32_SPLIT, relax_tol=1e-8, relax_max_iter=100)
+    run = pp.Run(P, species, with_id=False)
+    del cells, offs, us
+    th = math.radians(74.0)
+    dV = dx ** 3
+    hist = torch.zeros((steps + 1, 4), dtype=torch.float64, device=dev)
+    k1 = torch.fft.fftfreq(g, d=dx, device=dev, dtype=torch.float64) * (2 * math.pi)
+    KZ, KY, KX = torch.meshgrid(k1, k1, k1, indexing="ij")
+    KK = torch.sqrt(KX * KX + KY * KY + KZ * KZ)
+    ang = torch.rad2deg(torch.atan2(torch.sqrt(KX * KX + KY * KY), KZ.abs()))
+    band = ((ang >= 60) & (ang <= 80) & (KK >= 1) & (KK <= 8)).to(torch.float64)
+    KKs = torch.where(KK > 0, KK, torch.ones_like(KK))
+    spec_every = max(1, int(round(0.5 / dt)))
+
+    def record(i):
+        Ex, Ey, Ez = run.E[0], run.E[1], run.E[2]
+        proj = torch.sqrt(Ex * Ex + Ey * Ey) * math.sin(th) + Ez * math.cos(th)
+        ezm = Ez.mean(dim=(1, 2))
+        hist[i, 0] = 0.5 * dV * (proj * proj).sum()
+        hist[i, 1] = 0.5 * dV * (Ez * Ez).sum()
+        hist[i, 2] = 0.5 * dV * n[0] * n[1] * (ezm * ezm).sum()
+        if i % spec_every == 0:
+            lon = (torch.fft.fftn(Ex) * KX + torch.fft.fftn(Ey) * KY + torch.fft.fftn(Ez) * KZ) / KKs
+            hist[i, 3] = 0.5 * dV / (n[0] * n[1] * n[2]) * (band * lon.abs() ** 2).sum()
+        else:
+            hist[i, 3] = float("nan")
+
+    record(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        run.step()
+        record(i + 1)
+        if progress and (i + 1) % progress == 0:
+            torch.cuda.synchronize()
+            log(f"[mmi] step {i + 1}/{steps}, W_mmi {hist[i + 1, 0].item():.3e}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    d = run.diagnostics(pp.PP_DIAG_ALL)
+    run.close()
+    t = np.arange(steps + 1) * dt
+    return t, hist.cpu().numpy(), wall, 4 * npart, d
+
+
+def max_growth(t, w, width):
+    """Largest half log slope of the energy w (least squares over windows of the given width)
+    between the first time w exceeds 3x its mean over 0 < t <= 2 and the time of its maximum:
+    the growth rate of the field amplitude in the steepest part of the growth.  Returns
+    (rate, (window start, window end))."""
+    import numpy as np
+    t = np.asarray(t, dtype=float)
+    w = np.asarray(w, dtype=float)
+    early = w[(t > 0) & (t <= 2.0)]
+    base = early.mean() if early.size else w[w > 0].min()
+    above = np.nonzero(w > 3.0 * base)[0]
+    i1 = int(np.argmax(w))
+    if above.size == 0 or above[0] >= i1:
+        return float("nan"), (float("nan"), float("nan"))
+    lw = np.log(np.maximum(w, np.finfo(float).tiny))
+    best, win = float("nan"), (float("nan"), float("nan"))
+    for j in range(int(above[0]), i1):
+        k = int(np.searchsorted(t, t[j] + width, side="right"))
+        if k > i1 + 1:
+            break
+        if k - j >= 3:
+            r = 0.5 * float(np.polyfit(t[j:k], lw[j:k], 1)[0])
+            if not (best >= r):
+                best, win = r, (float(t[j]), float(t[k - 1]))
+    return best, win
+
+
+def mmi_rates_fit(t, H, width):
+    """Growth rates of the four energies of :func:`run_mmi` (NaN samples skipped): the
+    steepest-window rate and the least-squares rate over the whole growth phase."""
+    import numpy as np
+    out = {}
+    for k, col in (("mmi", 0), ("tsi_all_kz", 1), ("tsi", 2), ("mmi_band", 3)):
+        ok = np.isfinite(H[:, col])
+        rate, window = max_growth(t[ok], H[ok, col], width)
+        _, whole, phase = growth_rate_fit(t[ok], H[ok, col], width=width)
+        out[k] = {"rate": rate, "window": window, "rate_whole_phase": whole, "growth_phase": phase}
+    return out
+
+
+def mmi_bench(args, torch, pp):
+    """Relativistic mixed-mode two-stream test: a neutral beam (n_b = 0.1, Lorentz factor 4
+    along z) through a neutral background (n_p = 0.9), ion mass 1836 (ions at their
+    population's temperature), 128^3 cells of 0.1 c/w_pe (12.8 skin depths), 20 particles per
+    cell per species (four species, 167,772,160 particles), cubic weights, 6th-order fields,
+    charge-conserving current, FP32 split form; growth rates of the projected-field energies
+    against the paper's theory values and its measured values for this scheme."""
+    import numpy as np
+
+    from paper_1211_4575_amd import inputs as I
+    from paper_1211_4575_amd import inputs_device as ind
+    t, H, wall, npart, d = run_mmi(torch, pp, ind, args.mmi_grid, args.mmi_ppc, args.mmi_steps, args.mmi_tb,
+                                   args.mmi_tp)
+    if args.save_history:
+        np.savez(f"{args.save_history}_mmi.npz", t=t, w=H)
+    theory = I.mmi_rates()
+    fits = mmi_rates_fit(t, H, args.mmi_fit_width)
+    for k, v in fits.items():
+        v["rate_over_theory"] = v["rate"] / (theory["tsi"] if k.startswith("tsi") else theory["mmi"])
+        log(f"[mmi] {k}: {v}")
+    g = args.mmi_grid
+    out = {"metric": "relativistic mixed-mode two-stream growth rates / theory and paper",
+           "theory": theory, "paper_cubic_cc_6th": {"mmi": 0.205, "tsi": 0.088},
+           "config": {"grid": [g, g, g], "ppc_per_species": args.mmi_ppc, "particles": npart, "dx": 12.8 / g,
+                      "dt": 0.4 * 12.8 / g, "steps": args.mmi_steps, "T_b": args.mmi_tb, "T_p": args.mmi_tp},
+           "updates_per_s": npart * args.mmi_steps / wall, "wall_s": wall,
+           "final_gauss_rel": d.gauss_max / d.rho_ref, "flags": d.flags, **fits}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def kh_bench(args, torch, pp):
     """Kelvin-Helmholtz shear layers: 1024x512x1 cells, electrons and ions (mass ratio 25),
     64 particles per cell each (67,108,864 particles), bulk flows +-0.2c, u_th = 0.02c,
@@ -386,7 +529,15 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
-    ap.add_argument("--workload", choices=("pair_mj", "serving", "two_stream", "kh"), default="pair_mj")
+    ap.add_argument("--workload", choices=("pair_mj", "serving", "two_stream", "kh", "mmi"), default="pair_mj")
+    ap.add_argument("--mmi-grid", type=int, default=128, help="mmi: cells per axis (box 12.8 skin depths)")
+    ap.add_argument("--mmi-ppc", type=int, default=20, help="mmi: particles per cell per species")
+    ap.add_argument("--mmi-steps", type=int, default=1500, help="mmi: steps")
+    ap.add_argument("--mmi-fit-width", type=float, default=6.0, help="mmi: fit window (1/w_pe)")
+    ap.add_argument("--mmi-tb", type=float, default=1e-4,
+                    help="mmi: beam temperature (m_e c^2); the default reads the paper's 0.01 as u_th")
+    ap.add_argument("--mmi-tp", type=float, default=0.01,
+                    help="mmi: background temperature (m_e c^2); the default reads the paper's 0.1 as u_th")
     ap.add_argument("--grid-x", type=int, default=128, help="two-stream: cells along the beams")
     ap.add_argument("--ts-steps", type=int, default=2000, help="two-stream: steps")
     ap.add_argument("--save-history", default="", help="two-stream: save the E_x energy history to PATH_<form>.npz")
@@ -412,6 +563,8 @@ def main(argv=None):
         return two_stream_bench(args, torch, pp)
     if args.workload == "kh":
         return kh_bench(args, torch, pp)
+    if args.workload == "mmi":
+        return mmi_bench(args, torch, pp)
 
     if args.calib_copy_gib > 0:
         nb = int(args.calib_copy_gib * (1 << 30))

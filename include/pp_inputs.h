@@ -58,6 +58,17 @@ int ppi_kelvin_helmholtz(uint64_t seed, const int32_t n[3], int64_t start, int64
                          double uth, int32_t split, int32_t* const cell[2], void* const off[2][3], void* const u[2][3],
                          void* hip_stream);
 
+/* Relativistic mixed-mode two-stream set-up (as inputs.mmi): particle indices [start, start +
+ * count) of each of four species with the same count per species: beam electrons (0) and
+ * beam ions (1) at shared uniform-random positions, background electrons (2) and background
+ * ions (3) at other shared positions; Gaussian rest-frame proper velocities of variance T/m
+ * per component (T_b for the beam, T_p for the background, in units of m_e c^2, ion mass
+ * mass_ratio), the beam then boosted along +z with Lorentz factor gamma_b.  Output layout and
+ * split modes as above, for four species. */
+int ppi_mmi(uint64_t seed, const int32_t n[3], int64_t start, int64_t count, double gamma_b, double T_b, double T_p,
+            double mass_ratio, int32_t split, int32_t* const cell[4], void* const off[4][3], void* const u[4][3],
+            void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -244,6 +244,65 @@ __global__ void __launch_bounds__(256) k_kelvin_helmholtz(KHArgs A) {
     }
 }
 
+struct MMIArgs {
+    uint64_t seed;
+    int n[3];
+    int64_t start, count;
+    double gamma_b, sig[4];  // beam Lorentz factor, thermal spread per species
+    int split;
+    int32_t* cell[4];
+    void* off[4][3];
+    void* u[4][3];
+};
+
+// Mixed-mode two-stream load (inputs.mmi): beam positions (stream 5/0/0) shared by species 0
+// and 1, background positions (stream 5/2/0) shared by species 2 and 3; Gaussian rest-frame
+// proper velocities (streams 5/s/1) of spread sig[s], species 0 and 1 boosted along +z.
+__global__ void __launch_bounds__(256) k_mmi(MMIArgs A) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= A.count) return;
+    const uint64_t idx = (uint64_t)(A.start + l);
+    const double beta = sqrt(1.0 - 1.0 / (A.gamma_b * A.gamma_b));
+    for (int pop = 0; pop < 2; ++pop) {
+        double U[4];
+        uniform_pair(A.seed, idx, 0, stream_id(5, 2 * pop, 0), U[0], U[1]);
+        uniform_pair(A.seed, idx, 1, stream_id(5, 2 * pop, 0), U[2], U[3]);
+        double pos[3];
+        for (int d = 0; d < 3; ++d) {
+            const double x = U[d] * A.n[d];
+            pos[d] = x >= A.n[d] ? 0.0 : x;
+        }
+        int32_t cellv = 0;
+        float offf[3];
+        if (A.split) cellv = to_split(pos, A.n, A.split, offf);
+        for (int h = 0; h < 2; ++h) {
+            const int s = 2 * pop + h;
+            double V[4];
+            uniform_pair(A.seed, idx, 0, stream_id(5, s, 1), V[0], V[1]);
+            uniform_pair(A.seed, idx, 1, stream_id(5, s, 1), V[2], V[3]);
+            const double r0 = sqrt(-2.0 * log(V[0])), t0 = 2.0 * M_PI * V[1];
+            const double r1 = sqrt(-2.0 * log(V[2])), t1 = 2.0 * M_PI * V[3];
+            double uv[3] = {A.sig[s] * r0 * cos(t0), A.sig[s] * r0 * sin(t0), A.sig[s] * r1 * cos(t1)};
+            if (pop == 0 && A.gamma_b != 1.0) {
+                const double g = sqrt(1.0 + uv[0] * uv[0] + uv[1] * uv[1] + uv[2] * uv[2]);
+                uv[2] = A.gamma_b * (uv[2] + beta * g);
+            }
+            if (A.split) {
+                A.cell[s][l] = cellv;
+                for (int d = 0; d < 3; ++d) {
+                    ((float*)A.off[s][d])[l] = offf[d];
+                    ((float*)A.u[s][d])[l] = (float)uv[d];
+                }
+            } else {
+                for (int d = 0; d < 3; ++d) {
+                    ((double*)A.off[s][d])[l] = pos[d];
+                    ((double*)A.u[s][d])[l] = uv[d];
+                }
+            }
+        }
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -350,6 +409,40 @@ int ppi_kelvin_helmholtz(uint64_t seed, const int32_t n[3], int64_t start, int64
     }
     const int bs = 256;
     hipLaunchKernelGGL(k_kelvin_helmholtz, dim3((unsigned)((count + bs - 1) / bs)), dim3(bs), 0, (hipStream_t)hip_stream, A);
+    return hipGetLastError() == hipSuccess ? 0 : -6;
+}
+
+int ppi_mmi(uint64_t seed, const int32_t n[3], int64_t start, int64_t count, double gamma_b, double T_b, double T_p,
+            double mass_ratio, int32_t split, int32_t* const cell[4], void* const off[4][3], void* const u[4][3],
+            void* hip_stream) {
+    if (!n || start < 0 || count < 0 || !(gamma_b >= 1.0) || !(T_b >= 0.0) || !(T_p >= 0.0) || !(mass_ratio > 0.0))
+        return -1;
+    for (int d = 0; d < 3; ++d)
+        if (n[d] < 1) return -1;
+    if (split < 0 || split > 2) return -1;
+    if (count == 0) return 0;
+    MMIArgs A;
+    A.seed = seed;
+    for (int d = 0; d < 3; ++d) A.n[d] = n[d];
+    A.start = start;
+    A.count = count;
+    A.gamma_b = gamma_b;
+    A.sig[0] = sqrt(T_b);
+    A.sig[1] = sqrt(T_b / mass_ratio);
+    A.sig[2] = sqrt(T_p);
+    A.sig[3] = sqrt(T_p / mass_ratio);
+    A.split = split;
+    for (int s = 0; s < 4; ++s) {
+        A.cell[s] = cell ? cell[s] : nullptr;
+        if (split && !A.cell[s]) return -1;
+        for (int d = 0; d < 3; ++d) {
+            A.off[s][d] = off[s][d];
+            A.u[s][d] = u[s][d];
+            if (!A.off[s][d] || !A.u[s][d]) return -1;
+        }
+    }
+    const int bs = 256;
+    hipLaunchKernelGGL(k_mmi, dim3((unsigned)((count + bs - 1) / bs)), dim3(bs), 0, (hipStream_t)hip_stream, A);
     return hipGetLastError() == hipSuccess ? 0 : -6;
 }
 

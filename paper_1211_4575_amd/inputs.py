@@ -277,6 +277,63 @@ def kelvin_helmholtz(seed=SEED_BASE, n=(1024, 512, 1), ppc=64, mass_ratio=25.0, 
     return Workload("kelvin_helmholtz", tuple(n), (1.0, 1.0, 1.0), dt, shape_order, field_order, sp, steps=5000)
 
 
+def boost_z(u, gamma_b):
+    """Four-velocities u (rest frame of a population, [3, n]) seen in the frame where that
+    population drifts along +z with Lorentz factor gamma_b: u_z' = G (u_z + beta gamma)."""
+    if gamma_b == 1.0:
+        return u
+    beta = math.sqrt(1.0 - 1.0 / (gamma_b * gamma_b))
+    g = np.sqrt(1.0 + (u * u).sum(axis=0))
+    out = u.copy()
+    out[2] = gamma_b * (u[2] + beta * g)
+    return out
+
+
+MMI_SPECIES = (("beam electron", -1.0, False, True), ("beam ion", 1.0, True, True),
+               ("background electron", -1.0, False, False), ("background ion", 1.0, True, False))
+
+
+def mmi(seed=SEED_BASE, n=(128, 128, 128), ppc=20, gamma_b=4.0, n_b=0.1, n_p=0.9, T_b=0.01, T_p=0.1,
+        mass_ratio=1836.0, dx=0.1, cfl=0.4, shape_order=3, field_order=6, index_range=None):
+    """Relativistic mixed-mode two-stream set-up (Sec. VI, relativistic two-stream test): a cold
+    thin neutral beam (electrons and ions, density n_b, Lorentz factor gamma_b along +z) through
+    a warm thick neutral background at rest (density n_p); each population's electrons and ions
+    share their uniform-random positions, so the initial charge and current vanish and no
+    field is loaded.  Thermal proper velocities are Gaussian with variance T/m per component in
+    the population's rest frame (temperatures in units of m_e c^2), then boosted.  ppc particles
+    per cell per species; species order: beam electron, beam ion, background electron,
+    background ion.  ``index_range`` = (start, stop) loads that slice of every species."""
+    npart = n[0] * n[1] * n[2] * ppc
+    lo, hi = (0, npart) if index_range is None else index_range
+    idx = np.arange(lo, hi, dtype=np.uint64)
+    pos = {}
+    for pop in (0, 1):  # 0 beam, 1 background
+        U = uniforms(seed, _stream(5, 2 * pop, 0), idx, 3)
+        pos[pop] = np.stack([np.where(U[d] * n[d] >= n[d], 0.0, U[d] * n[d]) for d in range(3)])
+    sp = []
+    for s, (nm, q, ion, beam) in enumerate(MMI_SPECIES):
+        m = mass_ratio if ion else 1.0
+        T = T_b if beam else T_p
+        G = normals(seed, _stream(5, s, 1), idx, 3)
+        u = boost_z(math.sqrt(T / m) * G, gamma_b if beam else 1.0)
+        dens = n_b if beam else n_p
+        sp.append(Species(nm, q, m, dens / ppc, pos[0 if beam else 1].copy(), u))
+    return Workload("mmi", tuple(n), (dx, dx, dx), cfl * dx, shape_order, field_order, sp, steps=1500)
+
+
+def mmi_rates(gamma_b=4.0, n_b=0.1, n_p=0.9):
+    """Cold-beam growth rates (units of the total electron plasma frequency) of the oblique
+    mixed mode, filamentation and two-stream branches for a thin beam (eqs. "mmigrowth",
+    "figrowth", "tsigrowth"), with alpha read as the beam's share of the total density, and
+    the angle of the MMI wave vector to the beam, which the paper gives as about 74 degrees.
+    Returns dict(mmi, fi, tsi, theta_deg)."""
+    alpha = n_b / (n_b + n_p)
+    beta = math.sqrt(1.0 - 1.0 / (gamma_b * gamma_b))
+    c = 2.0 ** (-4.0 / 3.0) * math.sqrt(3.0) * alpha ** (1.0 / 3.0)
+    return dict(mmi=c * gamma_b ** (-1.0 / 3.0), fi=beta * math.sqrt(alpha / gamma_b), tsi=c / gamma_b,
+                theta_deg=74.0)
+
+
 # ---------------------------------------------------------------------------------------------
 # Serving ensemble: a stream of small two-stream runs (a parameter scan)
 # ---------------------------------------------------------------------------------------------

@@ -103,3 +103,35 @@ def test_device_kelvin_helmholtz_matches_host(split):
         else:
             assert np.array_equal(offs[s].cpu().numpy(), wl.species[s].pos)
             assert np.max(np.abs(u - uref)) <= 1e-14 * np.max(np.abs(uref))
+
+
+@pytest.mark.parametrize("split", [0, 2])
+def test_device_mmi_matches_host(split):
+    import torch
+    from paper_1211_4575_amd import inputs_device as ind
+    n, ppc = (8, 6, 5), 3
+    start, stop = 37, 8 * 6 * 5 * 3
+    wl = I.mmi(n=n, ppc=ppc, index_range=(start, stop))
+    cnt = stop - start
+    rt = torch.float32 if split else torch.float64
+    cells = [torch.empty(cnt, dtype=torch.int32, device="cuda") for _ in range(4)] if split else None
+    offs = [torch.empty((3, cnt), dtype=rt, device="cuda") for _ in range(4)]
+    us = [torch.empty((3, cnt), dtype=rt, device="cuda") for _ in range(4)]
+    ind.mmi(I.SEED_BASE, n, start, cnt, 4.0, 0.01, 0.1, 1836.0, split, cells, [[o[d] for d in range(3)] for o in offs],
+            [[u[d] for d in range(3)] for u in us], torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    for s in range(4):
+        sp = wl.species[s]
+        u = us[s].cpu().numpy().astype(np.float64)
+        tol = 1e-7 if split else 1e-14
+        for d in range(3):  # per component: the ions' thermal spread is far below the beam drift
+            assert np.max(np.abs(u[d] - sp.u[d])) <= tol * np.max(np.abs(sp.u[d]))
+        if split:
+            cell, off = I.to_split(sp.pos, n, origin="floor")
+            assert np.array_equal(cells[s].cpu().numpy(), cell)
+            assert np.array_equal(offs[s].cpu().numpy(), off)
+        else:
+            assert np.array_equal(offs[s].cpu().numpy(), sp.pos)
+    # the two species of a population share positions
+    for a, b in ((0, 1), (2, 3)):
+        assert torch.equal(offs[a], offs[b])

@@ -183,9 +183,10 @@ RHO_CASES = [((16, 12, 8), 3), ((16, 12, 8), 2), ((20, 9, 1), 3), ((7, 10, 6), 2
 
 @pytest.mark.parametrize("ci", range(len(RHO_CASES)), ids=[str(c) for c in RHO_CASES])
 def test_fp32_charge_density_matches_oracle(ppm, orc, ci):
-    # the split form's charge density (unsorted: FP64 atomics; sorted and after a push without
-    # sort: the tiled fixed-point deposit) against the oracle's deposit of the same positions,
-    # read through the Gauss residual of an E field whose down divergence is the oracle's rho
+    # the split form's charge density (the tiled fixed-point deposit: after loading, which
+    # sorts, after a push without sort, when particles sit in tiles they have left, and after
+    # the next sort) against the oracle's deposit of the same positions, read through the
+    # Gauss residual of an E field whose down divergence is the oracle's rho
     n, O = RHO_CASES[ci]
     _say("fp32 rho", n, O)
     rng = np.random.default_rng(40 + ci)
@@ -211,9 +212,7 @@ def test_fp32_charge_density_matches_oracle(ppm, orc, ci):
         d = run.diagnostics(ppm.PP_DIAG_RHO)
         assert d.gauss_max / d.rho_ref < 1e-10, (tag, d.gauss_max)
 
-    check("unsorted")
-    run.sort()
-    check("sorted")
+    check("loaded")
     run.gather_push_deposit()
     check("pushed")
     run.sort()

@@ -175,3 +175,29 @@ def test_two_stream_growth_rate_oracle(orc):
     t = P.dt * np.arange(W.size)
     rate = np.polyfit(t, np.log(W), 1)[0] / 2
     assert abs(rate - p) < 0.03 * p, (rate, p)
+
+
+def test_mmi_loader_is_neutral_and_boosted():
+    # the mixed-mode two-stream set-up: each population's electrons and ions share positions
+    # (no charge, no current at t = 0 for equal drifts), the beam's mean four-velocity along z
+    # is the boost of a thermal population, and the growth rates reproduce the paper's values
+    from paper_1211_4575_amd import inputs as I
+    wl = I.mmi(n=(6, 5, 4), ppc=40)
+    e_b, i_b, e_p, i_p = wl.species
+    assert np.array_equal(e_b.pos, i_b.pos) and np.array_equal(e_p.pos, i_p.pos)
+    assert not np.array_equal(e_b.pos, e_p.pos)
+    assert e_b.w * e_b.pos.shape[1] / (6 * 5 * 4) == pytest.approx(0.1)
+    assert e_p.w * e_p.pos.shape[1] / (6 * 5 * 4) == pytest.approx(0.9)
+    # cold beam: gamma close to 4, all moving along +z
+    g = np.sqrt(1.0 + (e_b.u ** 2).sum(axis=0))
+    assert abs(np.mean(g) - 4.0) < 0.1 and np.all(e_b.u[2] > 0)
+    gi = np.sqrt(1.0 + (i_b.u ** 2).sum(axis=0))
+    assert abs(np.mean(gi) - 4.0) < 1e-3 and np.max(np.abs(gi - 4.0)) < 0.1  # G beta u_z' spread
+    # rest-frame boost: the boosted four-velocity has u_z = G (u_z' + beta gamma')
+    up = np.array([[0.1], [0.2], [0.3]])
+    b = I.boost_z(up, 4.0)
+    beta = np.sqrt(1 - 1 / 16.0)
+    assert b[2, 0] == pytest.approx(4.0 * (0.3 + beta * np.sqrt(1.14)))
+    assert np.sqrt(1 + (b ** 2).sum()) == pytest.approx(4.0 * (np.sqrt(1.14) + beta * 0.3))
+    r = I.mmi_rates()
+    assert round(r["mmi"], 3) == 0.201 and round(r["fi"], 3) == 0.153 and round(r["tsi"], 3) == 0.080
