@@ -35,6 +35,8 @@ typedef struct {
     double relax_tol;     /* relative residual target of the B relaxation      */
     int32_t relax_max_iter;
     double rho_background;/* fixed neutralising charge density                 */
+    double rad_tau;       /* radiative cooling constant mu0 q^2 / (6 pi m c) for */
+                          /* unit charge and mass (0: no cooling)                */
 } orc_params;
 
 /* ------------------------------------------------------------------ */
@@ -188,6 +190,43 @@ void orc_push(int pusher, double q, double m, double dt, double c, const double 
         push_vay(h, c, E, B, u);
 }
 
+/* Radiated power of a particle of proper velocity u and proper acceleration du/dt, over
+ * mu0 q^2 / (6 pi c): the proper-velocity form of the Larmor-Lienard power (Sec. "Radiative
+ * cooling", eq. "prad"): |du/dt|^2 + |du/dt x u|^2 / c^2. */
+double orc_rad_bracket(double c, const double u[3], const double udot[3]) {
+    double x[3];
+    cross3(udot, u, x);
+    return dot3(udot, udot) + dot3(x, x) / (c * c);
+}
+
+/* Radiative cooling of one step (Sec. "Radiative cooling", eqs. "prad", "udot" and the
+ * explicit update that follows them): with u_m the proper velocity before the push and u the
+ * one after the electromagnetic push, the time-centred state is u0 = (u + u_m)/2, gamma0 =
+ * sqrt(1 + u0^2/c^2), the proper acceleration is (u - u_m)/dt, and
+ *   u += -k (gamma0 / u0^2) [bracket] u0 dt,   k = rad_tau q^2 / m
+ * (the cooling acts against u0; no iteration). */
+void orc_rad_cool(double k, double dt, double c, const double u_m[3], double u[3]) {
+    if (k == 0.0) return;
+    double u0[3], ud[3];
+    for (int d = 0; d < 3; ++d) {
+        u0[d] = 0.5 * (u[d] + u_m[d]);
+        ud[d] = (u[d] - u_m[d]) / dt;
+    }
+    const double u02 = dot3(u0, u0);
+    if (!(u02 > 0.0)) return;
+    const double g0 = sqrt(1.0 + u02 / (c * c));
+    const double f = -k * g0 / u02 * orc_rad_bracket(c, u0, ud);
+    for (int d = 0; d < 3; ++d) u[d] += f * u0[d] * dt;
+}
+
+/* Electromagnetic push followed by the cooling of one step (species charge q, mass m). */
+void orc_push_rad(int pusher, double q, double m, double dt, double c, double rad_tau, const double E[3],
+                  const double B[3], double u[3]) {
+    double um[3] = {u[0], u[1], u[2]};
+    orc_push(pusher, q, m, dt, c, E, B, u);
+    orc_rad_cool(rad_tau * q * q / m, dt, c, um, u);
+}
+
 /* ------------------------------------------------------------------ */
 /* Charge-conserving current of one particle moving X0 -> X1, Sec. III.C:*/
 /* Esirkepov's directional split of the charge change (the paper cites  */
@@ -262,7 +301,7 @@ int orc_step_species(const orc_params* P, double q, double m, double w, int64_t 
             up[d] = u[d * n + p];
         }
         orc_gather(P, E, B, X0, Ep, Bp);
-        orc_push(P->pusher, q, m, P->dt, c, Ep, Bp, up);
+        orc_push_rad(P->pusher, q, m, P->dt, c, P->rad_tau, Ep, Bp, up);
         double g = sqrt(1.0 + dot3(up, up) / (c * c));
         for (int d = 0; d < 3; ++d) {
             X1[d] = X0[d] + P->dt * up[d] / (g * P->d[d]);

@@ -43,12 +43,13 @@ class Params(ctypes.Structure):
         ("relax_tol", ctypes.c_double),
         ("relax_max_iter", ctypes.c_int32),
         ("rho_background", ctypes.c_double),
+        ("rad_tau", ctypes.c_double),
     ]
 
 
 def make_params(n=(16, 16, 16), d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shape_order=2,
                 field_order=2, alpha=0.55, pusher=0, relax_tol=1e-14, relax_max_iter=200,
-                rho_background=0.0) -> Params:
+                rho_background=0.0, rad_tau=0.0) -> Params:
     p = Params()
     p.n[:] = [int(v) for v in n]
     p.d[:] = [float(v) for v in d]
@@ -57,6 +58,7 @@ def make_params(n=(16, 16, 16), d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shap
     p.alpha, p.pusher = float(alpha), int(pusher)
     p.relax_tol, p.relax_max_iter = float(relax_tol), int(relax_max_iter)
     p.rho_background = float(rho_background)
+    p.rad_tau = float(rad_tau)
     return p
 
 
@@ -75,6 +77,10 @@ def lib():
         L.orc_gather.argtypes = [_P, _D, _D, _D, _D, _D]
         L.orc_push.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, _D, _D, _D]
+        L.orc_push_rad.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, _D, _D, _D]
+        L.orc_rad_bracket.restype = ctypes.c_double
+        L.orc_rad_bracket.argtypes = [ctypes.c_double, _D, _D]
         L.orc_step_species.restype = ctypes.c_int
         L.orc_step_species.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_int64, _D, _D, _D, _D, _D]
@@ -125,6 +131,20 @@ def push(pusher: int, q: float, m: float, dt: float, c: float, E, B, u) -> np.nd
     uu = np.array(u, dtype=np.float64)
     lib().orc_push(int(pusher), q, m, dt, c, _ptr(E), _ptr(B), _ptr(uu))
     return uu
+
+
+def push_rad(pusher: int, q: float, m: float, dt: float, c: float, rad_tau: float, E, B, u) -> np.ndarray:
+    """Electromagnetic push followed by one step of radiative cooling."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    uu = np.array(u, dtype=np.float64)
+    lib().orc_push_rad(int(pusher), q, m, dt, c, rad_tau, _ptr(E), _ptr(B), _ptr(uu))
+    return uu
+
+
+def rad_bracket(c: float, u, udot) -> float:
+    """|du/dt|^2 + |du/dt x u|^2 / c^2 (radiated power over mu0 q^2 / (6 pi c))."""
+    return lib().orc_rad_bracket(c, _ptr(np.array(u, dtype=np.float64)), _ptr(np.array(udot, dtype=np.float64)))
 
 
 def deposit_current(P: Params, q: float, w: float, X0, X1, J: np.ndarray | None = None) -> np.ndarray:

@@ -74,3 +74,63 @@ def test_exb_drift_velocity(orc):
     t = dt * np.arange(1, nsteps + 1)
     slope = np.polyfit(t, xs[:, 1], 1)[0]
     assert abs(slope - vd[1]) < 0.02 * abs(vd[1])
+
+
+# ---- radiative cooling (Sec. "Radiative cooling") ----------------------------------------------
+@pytest.mark.parametrize("c", [1.0, 2.0])
+def test_rad_bracket_equals_the_three_velocity_larmor_form(orc, c):
+    # eq. "prad" (proper velocities) against eq. "pradv" (three-velocities):
+    # |du/dt|^2 + |du/dt x u|^2/c^2 = gamma^4 |dv/dt|^2 + gamma^6 (dv/dt . v)^2 / c^2
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        u = rng.normal(0, 3, 3)
+        ud = rng.normal(0, 2, 3)
+        g = math.sqrt(1 + u @ u / c ** 2)
+        gd = (u @ ud) / (g * c * c)
+        v = u / g
+        vd = ud / g - u * gd / g ** 2
+        p_three = g ** 4 * (vd @ vd) + g ** 6 * (vd @ v) ** 2 / c ** 2
+        assert abs(orc.rad_bracket(c, u, ud) / p_three - 1) < 1e-12
+
+
+def test_rad_cooling_off_is_the_plain_push(orc):
+    rng = np.random.default_rng(6)
+    for pusher in (0, 1):
+        E, B, u = rng.normal(0, 1, 3), rng.normal(0, 2, 3), rng.normal(0, 3, 3)
+        a = orc.push(pusher, -1.0, 1.0, 0.3, 1.0, E, B, u)
+        b = orc.push_rad(pusher, -1.0, 1.0, 0.3, 1.0, 0.0, E, B, u)
+        assert np.array_equal(a, b)
+
+
+def test_rad_cooling_acts_against_the_time_centred_velocity(orc):
+    rng = np.random.default_rng(7)
+    for pusher in (0, 1):
+        E, B, u = rng.normal(0, 1, 3), rng.normal(0, 2, 3), rng.normal(0, 3, 3)
+        uem = orc.push(pusher, 1.0, 2.0, 0.2, 1.0, E, B, u)
+        urad = orc.push_rad(pusher, 1.0, 2.0, 0.2, 1.0, 1e-3, E, B, u)
+        du, u0 = urad - uem, 0.5 * (uem + u)
+        assert du @ u0 < 0
+        assert np.linalg.norm(np.cross(du, u0)) < 1e-12 * np.linalg.norm(du) * np.linalg.norm(u0)
+        # size: k gamma0 |bracket| dt / |u0| with k = rad_tau q^2 / m
+        ud = (uem - u) / 0.2
+        g0 = math.sqrt(1 + u0 @ u0)
+        expect = 1e-3 * 1.0 / 2.0 * g0 * orc.rad_bracket(1.0, u0, ud) * 0.2 / math.sqrt(u0 @ u0)
+        assert abs(np.linalg.norm(du) / expect - 1) < 1e-12
+
+
+@pytest.mark.parametrize("pusher", [0, 1])
+def test_synchrotron_cooling_in_a_uniform_field(orc, pusher):
+    # u perpendicular to a uniform B: d|u|/dt = -k w_c^2 |u| sqrt(1 + u^2/c^2) (k = rad_tau q^2/m,
+    # w_c = |q| B / m), so asinh(c/|u|) grows at the constant rate k w_c^2; the explicit scheme
+    # follows it to first order in the step
+    q, m, B0, tau, x0, T = -1.0, 1.0, 1.0, 0.01, 10.0, 20.0
+    k, wc = tau * q * q / m, abs(q) * B0 / m
+    exact = 1.0 / math.sinh(math.asinh(1.0 / x0) + k * wc * wc * T)
+    errs = []
+    for dt in (0.02, 0.01):
+        u = np.array([x0, 0.0, 0.0])
+        for _ in range(int(round(T / dt))):
+            u = orc.push_rad(pusher, q, m, dt, 1.0, tau, np.zeros(3), np.array([0.0, 0.0, B0]), u)
+        assert abs(u[2]) < 1e-14  # stays in the plane
+        errs.append(abs(np.linalg.norm(u) / exact - 1))
+    assert errs[1] < 2e-3 and errs[0] / errs[1] > 1.8
