@@ -33,7 +33,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_pair_mj_run(pp, ind, torch, n, ppc, theta, split, with_id=False):
+def make_pair_mj_run(pp, ind, torch, n, ppc, theta, split, with_id=False, rad_tau=0.0):
     """Build a pp.Run for the pair-plasma workload with particles generated on the device.
     Returns the run and the number of particles per species."""
     npart = n[0] * n[1] * n[2] * ppc
@@ -53,7 +53,7 @@ def make_pair_mj_run(pp, ind, torch, n, ppc, theta, split, with_id=False):
     torch.cuda.synchronize()
     params = pp.make_params(n, shape_order=3, field_order=6, dt=0.4, alpha=0.55,
                             precision=pp.PP_PREC_FP32_SPLIT if split else pp.PP_PREC_FP64,
-                            relax_tol=1e-8 if split else 1e-14, relax_max_iter=100)
+                            relax_tol=1e-8 if split else 1e-14, relax_max_iter=100, rad_tau=rad_tau)
     species = []
     for s, q in enumerate((-1.0, 1.0)):
         sp = dict(q=q, m=1.0, w=1.0 / ppc, u=us[s])
@@ -527,6 +527,7 @@ def main(argv=None):
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rad-tau", type=float, default=0.0, help="radiative cooling constant (0: off)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--workload", choices=("pair_mj", "serving", "two_stream", "kh", "mmi"), default="pair_mj")
@@ -579,7 +580,7 @@ def main(argv=None):
 
     n = (args.grid, args.grid, args.grid)
     log(f"[bench] FP32 split: generating {n} x {args.ppc} ppc x 2 species on the device")
-    run, npart = make_pair_mj_run(pp, ind, torch, n, args.ppc, 1.0, split=True)
+    run, npart = make_pair_mj_run(pp, ind, torch, n, args.ppc, 1.0, split=True, rad_tau=args.rad_tau)
     npart *= 2  # electrons and positrons
     log(f"[bench] FP32 split: {npart} particles; warmup {args.warmup}, timing {args.steps} steps")
     wall, gpd_ms = time_steps(run, torch, args.steps, args.warmup)
@@ -604,7 +605,7 @@ def main(argv=None):
     fp64 = None
     if not args.no_fp64:
         log(f"[bench] FP64 plain: generating")
-        run, _ = make_pair_mj_run(pp, ind, torch, n, args.ppc, 1.0, split=False)
+        run, _ = make_pair_mj_run(pp, ind, torch, n, args.ppc, 1.0, split=False, rad_tau=args.rad_tau)
         log(f"[bench] FP64 plain: warmup 1, timing {args.fp64_steps} steps")
         wall64, gpd64_ms = time_steps(run, torch, args.fp64_steps, 1)
         fp64 = dict(value=npart * args.fp64_steps / wall64, ms_per_step=1e3 * wall64 / args.fp64_steps,
@@ -647,7 +648,7 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": f"pair plasma {n[0]}x{n[1]}x{n[2]}, {args.ppc} ppc/species, Maxwell-Juttner kT=mc^2, "
                                f"cubic weights, 6th-order fields, FP32 split positions",
-                   "particles": npart, "step": "gather/push/deposit + line solve + sort + field step",
+                   "particles": npart, "step": "gather/push/deposit + line solve + sort + field step", "rad_tau": args.rad_tau,
                    "gpd_updates_per_s": gpd_rate, "fp64_plain": fp64,
                    "fp32_over_fp64": (value / fp64["value"]) if fp64 else None, "diagnostics": diag32},
         "roofline": roofline,

@@ -91,6 +91,14 @@ typedef struct pp_params {
     double relax_tol;      /* target error reduction of the B relaxation, e.g. 1e-14 */
     int32_t relax_max_iter;/* upper bound on relaxation sweeps                        */
     double rho_background; /* fixed neutralising charge density (0 if none)          */
+    double rad_tau;        /* radiative cooling (Sec. "Radiative cooling", eqs. "prad",
+                            * "udot"): mu0 q^2 / (6 pi m c) for unit charge and mass in
+                            * the run's units, scaled by q^2/m per species; after the
+                            * electromagnetic push each particle loses
+                            * k (gamma0/u0^2)(|du/dt|^2 + |du/dt x u0|^2/c^2) u0 dt with
+                            * u0 the mean of the old and new proper velocities and du/dt
+                            * their difference over dt (explicit, no iteration).  0 (the
+                            * default) turns it off; must be finite and >= 0.          */
 } pp_params;
 
 /* Caller-owned FP64 mesh (device pointers, 3*ncell doubles each). */

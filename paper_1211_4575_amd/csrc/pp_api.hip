@@ -36,8 +36,9 @@ static pp_status validate(const pp_params* p) {
     const int64_t nc = (int64_t)p->n[0] * p->n[1] * p->n[2];
     if (nc > ((int64_t)1 << 30)) return PP_E_CAPACITY;
     if (!std::isfinite(p->dt) || !std::isfinite(p->c) || !std::isfinite(p->eps0) || !std::isfinite(p->alpha) ||
-        !std::isfinite(p->relax_tol) || !std::isfinite(p->rho_background))
+        !std::isfinite(p->relax_tol) || !std::isfinite(p->rho_background) || !std::isfinite(p->rad_tau))
         return PP_E_NONFINITE;
+    if (p->rad_tau < 0.0) return PP_E_ARG;
     if (!finite_pos(p->dt) || !finite_pos(p->c) || !finite_pos(p->eps0)) return PP_E_ARG;
     if (p->shape_order != 2 && p->shape_order != 3) return PP_E_ARG;
     if (p->field_order != 2 && p->field_order != 4 && p->field_order != 6) return PP_E_ARG;

@@ -130,6 +130,26 @@ __device__ __forceinline__ void push_boris(T h, T ic, const V3<T>& E, const V3<T
     u = V3<T>{um.x + c2.x + hh * E.x, um.y + c2.y + hh * E.y, um.z + c2.z + hh * E.z};
 }
 
+// Radiative cooling of one step (Sec. "Radiative cooling", eqs. "prad", "udot"): um is the
+// proper velocity before the push, u the one after the electromagnetic push; with u0 their
+// mean, gamma0 = sqrt(1 + u0^2/c^2) and a = (u - um)/dt the proper acceleration,
+//   u -= k (gamma0 / u0^2) (|a|^2 + |a x u0|^2 / c^2) u0 dt,   k = rad_tau q^2 / m.
+// Only proper velocities enter (no cancellation between gamma^2 and u^2 in FP32).
+template <typename T>
+__device__ __forceinline__ void rad_cool(T k, T dt, T ic, const V3<T>& um, V3<T>& u) {
+    const V3<T> u0{(T)0.5 * (u.x + um.x), (T)0.5 * (u.y + um.y), (T)0.5 * (u.z + um.z)};
+    const T idt = (T)1 / dt;
+    const V3<T> a{(u.x - um.x) * idt, (u.y - um.y) * idt, (u.z - um.z) * idt};
+    const T u02 = dot(u0, u0);
+    if (!(u02 > (T)0)) return;
+    const V3<T> x = cross(a, u0);
+    const T g0 = sqrt((T)1 + u02 * ic * ic);
+    const T f = -k * g0 / u02 * (dot(a, a) + dot(x, x) * ic * ic) * dt;
+    u.x += f * u0.x;
+    u.y += f * u0.y;
+    u.z += f * u0.z;
+}
+
 __device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
 
 // Segment of a batched launch: the largest r in [0, n) with prefix[r] <= b < prefix[r + 1]

@@ -45,6 +45,7 @@ struct Sp32 {
     float* pos[3];
     float* u[3];
     float h;        // q dt / m
+    float krad;     // radiative cooling constant rad_tau q^2 / m (0: off)
     double fac[3];  // -q w d_c / dt
 };
 
@@ -355,10 +356,12 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
             B.y = gather_comp<O>(fld + 4 * L.fvol, L, fs[0], fc[1], fs[2], ws[0], wc[1], ws[2]);
             B.z = gather_comp<O>(fld + 5 * L.fvol, L, fs[0], fs[1], fc[2], ws[0], ws[1], wc[2]);
 
+            const V3<float> um = u;
             if (A.pusher == PP_PUSH_BORIS)
                 push_boris<float>(S.h, A.ic, E, B, u);
             else
                 push_vay<float>(S.h, A.ic, E, B, u);
+            if (S.krad != 0.0f) rad_cool<float>(S.krad, A.dt, A.ic, um, u);
 
             const float ig = rsqrtf(1.0f + dot(u, u) * A.ic * A.ic);
             const float uu[3] = {u.x, u.y, u.z};
@@ -685,6 +688,7 @@ void gpd32_fill_args(const pp_run* r, Gpd32Args* Ap) {
             D.fac[d] = -S.q * S.w * r->p.d[d] / r->p.dt;
         }
         D.h = (float)(S.q * r->p.dt / S.m);
+        D.krad = (float)(r->p.rad_tau * S.q * S.q / S.m);
     }
     A.E = r->mesh.E;
     A.B = r->mesh.B;

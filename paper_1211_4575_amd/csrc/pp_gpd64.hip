@@ -12,6 +12,7 @@ struct Gpd64Args {
     double d[3];      // cell size
     double dt, ic;    // time step, 1/c
     double h;         // q dt / m
+    double krad;      // radiative cooling constant rad_tau q^2 / m (0: off)
     double fac[3];    // -q w d_c / dt, current prefactor per component
     int64_t np;
     double* pos[3];
@@ -78,10 +79,12 @@ __global__ void __launch_bounds__(256) k_gpd64(Gpd64Args A) {
     B.y = gather1<O>(A.B + nc, is0[0], ic0[1], is0[2], ws[0], wc[1], ws[2], nx, nxy);
     B.z = gather1<O>(A.B + 2 * nc, is0[0], is0[1], ic0[2], ws[0], ws[1], wc[2], nx, nxy);
 
+    const V3<double> um = u;
     if (A.pusher == PP_PUSH_BORIS)
         push_boris<double>(A.h, A.ic, E, B, u);
     else
         push_vay<double>(A.h, A.ic, E, B, u);
+    if (A.krad != 0.0) rad_cool<double>(A.krad, A.dt, A.ic, um, u);
 
     const double g = sqrt(1.0 + dot(u, u) * A.ic * A.ic);
     const double uu[3] = {u.x, u.y, u.z};
@@ -178,6 +181,7 @@ hipError_t launch_gpd64(pp_run* r, int s, double* J) {
     A.dt = r->p.dt;
     A.ic = 1.0 / r->p.c;
     A.h = S.q * r->p.dt / S.m;
+    A.krad = r->p.rad_tau * S.q * S.q / S.m;
     A.np = S.n;
     A.E = r->mesh.E;
     A.B = r->mesh.B;

@@ -42,6 +42,7 @@ class pp_params(ctypes.Structure):
         ("relax_tol", ctypes.c_double),
         ("relax_max_iter", ctypes.c_int32),
         ("rho_background", ctypes.c_double),
+        ("rad_tau", ctypes.c_double),
     ]
 
 
@@ -224,7 +225,8 @@ def pp_batch_destroy(batch):
 
 # ---- convenience owner of the torch tensors ---------------------------------------------
 def make_params(n, d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shape_order=2, field_order=2, alpha=0.55,
-                pusher=0, precision=PP_PREC_FP64, relax_tol=1e-14, relax_max_iter=200, rho_background=0.0):
+                pusher=0, precision=PP_PREC_FP64, relax_tol=1e-14, relax_max_iter=200, rho_background=0.0,
+                rad_tau=0.0):
     p = pp_params()
     p.n[:] = [int(v) for v in n]
     p.d[:] = [float(v) for v in d]
@@ -233,6 +235,7 @@ def make_params(n, d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shape_order=2, fi
     p.alpha, p.pusher, p.precision = float(alpha), int(pusher), int(precision)
     p.relax_tol, p.relax_max_iter = float(relax_tol), int(relax_max_iter)
     p.rho_background = float(rho_background)
+    p.rad_tau = float(rad_tau)
     return p
 
 

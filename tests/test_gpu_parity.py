@@ -178,6 +178,58 @@ def test_fp32_gauss_residual_one_step(ppm, orc):
     run.close()
 
 
+@pytest.mark.parametrize("split", [False, True], ids=["fp64", "fp32_split"])
+def test_radiative_cooling_steps_match_oracle(ppm, orc, split):
+    # strong fields and relativistic particles of four charge/mass ratios with radiative cooling
+    # on: three steps against the oracle (FP64 to 1e-12, split FP32 to the FP32 bars); the
+    # cooling must change the momenta well above those bars
+    n, ppc, O, fo, tau = (10, 8, 6), 3, 3, 6, 0.02
+    _say("radiative cooling", "split" if split else "fp64")
+    species, E, B = random_state(orc, n, ppc, seed=77, uth=2.0, e_amp=0.5, b_amp=3.0, nspecies=4, pair=False)
+    kw = dict(n=n, dt=0.3, shape_order=O, field_order=fo, relax_tol=1e-14, relax_max_iter=200)
+    if split:
+        species = _split_species(species, n, O)
+        ref_species = [dict(s, u=s["u64"]) for s in species]
+    else:
+        ref_species = species
+    ref = _orc_run(orc, orc.make_params(rad_tau=tau, **kw), ref_species, E, B)
+    plain = _orc_run(orc, orc.make_params(**kw), ref_species, E, B)
+    prec = ppm.PP_PREC_FP32_SPLIT if split else ppm.PP_PREC_FP64
+    run = ppm.Run(ppm.make_params(precision=prec, rad_tau=tau, **kw), species, E=E, B=B)
+    for step in range(3):
+        ref.step()
+        plain.step()
+        run.step()
+        Eg, Bg, Jg = run.fields()
+        if split:
+            assert rel_l2(Jg, ref.J) < 1e-5, step
+        else:
+            assert rel_inf(Jg, ref.J) < 1e-12, step
+            assert rel_inf(Eg, ref.E) < 1e-12 and rel_inf(Bg, ref.B) < 1e-12, step
+        for s, sp in enumerate(ref.species):
+            g = _by_id(run.particles(s))
+            if split:
+                X = I.from_split(g["cell"], g["pos"], n)
+                assert np.max(np.abs(periodic_diff(X, sp["pos"], n))) < 1e-5, (step, s)
+                assert rel_inf(g["u"].astype(np.float64), sp["u"]) < 2e-5, (step, s)
+            else:
+                assert np.max(np.abs(periodic_diff(g["pos"], sp["pos"], n))) < 1e-12, (step, s)
+                assert rel_inf(g["u"], sp["u"]) < 1e-12, (step, s)
+    # cooling acted, strongly on the light species (k = rad_tau q^2 / m: 25x weaker on m = 25)
+    for s in range(4):
+        change = rel_inf(ref.species[s]["u"], plain.species[s]["u"])
+        assert change > (1e-3 if s < 2 else 1e-6), (s, change)
+    assert run.diagnostics().flags == 0
+    run.close()
+
+
+def test_radiative_cooling_parameter_is_validated(ppm):
+    with pytest.raises(ppm.PPError):
+        ppm.Run(ppm.make_params(n=(4, 4, 4), rad_tau=-1.0), [])
+    with pytest.raises(ppm.PPError):
+        ppm.Run(ppm.make_params(n=(4, 4, 4), rad_tau=float("nan")), [])
+
+
 RHO_CASES = [((16, 12, 8), 3), ((16, 12, 8), 2), ((20, 9, 1), 3), ((7, 10, 6), 2)]
 
 

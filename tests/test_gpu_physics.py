@@ -58,3 +58,44 @@ def test_mmi_reduced_grows_and_saturates():
     print("fits", fits, "band growth", band.max() / band[1], file=sys.stderr, flush=True)
     assert band.max() / band[1] > 1e3
     assert 0.4 < fits["mmi_band"]["rate"] / theory < 1.3
+
+
+@pytest.mark.parametrize("split", [False, True], ids=["fp64", "fp32_split"])
+def test_synchrotron_cooling_in_a_run(split):
+    # particles of negligible weight gyrating in a uniform B with radiative cooling on: their
+    # speed follows the synchrotron cooling law asinh(c/|u|) = asinh(c/|u0|) + k w_c^2 t
+    # (k = rad_tau q^2/m) to the first-order accuracy of the explicit update (4e-4 at dt = 0.01)
+    import numpy as np
+
+    from paper_1211_4575_amd import inputs as I
+    from paper_1211_4575_amd import pp
+    n, B0, tau, x0, dt, steps = (16, 16, 16), 1.0, 0.01, 10.0, 0.01, 2000
+    rng = np.random.default_rng(3)
+    npart = 64
+    pos = rng.uniform(0, 16, (3, npart))
+    phi = rng.uniform(0, 2 * math.pi, npart)
+    u = np.stack([x0 * np.cos(phi), x0 * np.sin(phi), np.zeros(npart)])
+    B = np.zeros((3, 16, 16, 16))
+    B[2] = B0
+    sp = dict(q=-1.0, m=1.0, w=1e-12, u=u)
+    if split:
+        cell, off = I.to_split(pos, n, origin="floor")
+        sp.update(cell=cell, off=off, u=u.astype(np.float32))
+    else:
+        sp.update(pos=pos)
+    P = pp.make_params(n, dt=dt, shape_order=3, field_order=6, rad_tau=tau,
+                       precision=pp.PP_PREC_FP32_SPLIT if split else pp.PP_PREC_FP64, relax_tol=1e-12)
+    run = pp.Run(P, [sp], B=B)
+    print("synchrotron cooling", "split" if split else "fp64", file=sys.stderr, flush=True)
+    for _ in range(steps):
+        run.step()
+    g = run.particles(0)
+    speed = np.linalg.norm(g["u"].astype(np.float64), axis=0)
+    exact = 1.0 / math.sinh(math.asinh(1.0 / x0) + tau * B0 * B0 * steps * dt)
+    err = np.max(np.abs(speed / exact - 1.0))
+    print("speed", speed.mean(), "exact", exact, "max rel err", err, file=sys.stderr, flush=True)
+    assert err < 1e-3
+    assert np.max(np.abs(g["u"][2])) < 1e-6
+    assert run.diagnostics().flags == 0
+    run.close()
+
