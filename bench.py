@@ -115,6 +115,26 @@ def flops_per_update(O=3):
     return weights + gather + push + move + 3 * per_comp
 
 
+# LDS issue model of the tiled particle kernel (cubic weights, 4x4x4 tiles): per wavefront of
+# 64 particles it issues 300 64-bit integer atomic adds (the current) and 192 paired 32-bit
+# reads (the gather: 6 components x 64 nodes).  Measured on gfx950 with aligned addresses:
+# 6.3 clk per 64-lane 64-bit atomic add; a paired read moves 128 dwords at 32 banks per clk.
+LDS_CLK_PER_WAVE_ATOMIC = 6.3
+LDS_CLK_PER_WAVE_READ2 = 4.0
+CUS, CLOCK_HZ = 256, 2.4e9
+
+
+def lds_bound_updates_per_s(O=3):
+    """Particle updates/s at which the LDS pipe would be busy 100 % of the time with
+    conflict-free accesses (the kernel's binding resource): 256 CUs x 2.4 GHz over the LDS
+    cycles one particle needs."""
+    n1, n2 = O + 1, O + 2
+    atomics = 3 * n1 * n2 * n2
+    reads2 = 6 * n1 ** 3 // 2
+    clk = (atomics * LDS_CLK_PER_WAVE_ATOMIC + reads2 * LDS_CLK_PER_WAVE_READ2) / 64.0
+    return CUS * CLOCK_HZ / clk
+
+
 def kernel_source_digest():
     """Digest of the sources of the dominant kernel (so stored counter figures are only used
     while the kernel they were taken on is unchanged)."""
@@ -625,7 +645,12 @@ def main(argv=None):
                 "traffic": traffic, "kernel": "k_gpd32<3>", "flop_per_update": fl,
                 "algorithmic_bytes_per_launch": npart * bytes_per_update,
                 "hbm_gbs_algorithmic": round(achieved_gbs, 1), "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                "gpd_ms": round(gpd_ms, 3)}
+                "gpd_ms": round(gpd_ms, 3),
+                "lds_model": {"bound": "lds", "achieved": npart / (gpd_ms * 1e-3), "peak": lds_bound_updates_per_s(3),
+                              "unit": "particle updates/s",
+                              "frac": round(npart / (gpd_ms * 1e-3) / lds_bound_updates_per_s(3), 4),
+                              "basis": "300 ds_add_u64 at 6.3 clk + 192 ds_read2_b32 at 4 clk per 64 particles, "
+                                       "256 CU x 2.4 GHz, no bank conflicts"}}
 
     cpu = None
     if not args.no_cpu:

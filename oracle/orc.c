@@ -37,6 +37,9 @@ typedef struct {
     double rho_background;/* fixed neutralising charge density                 */
     double rad_tau;       /* radiative cooling constant mu0 q^2 / (6 pi m c) for */
                           /* unit charge and mass (0: no cooling)                */
+    int32_t current_scheme; /* 0 = charge-conserving (Esirkepov), 1 = direct     */
+                          /* (eq. "jj2" at the time-centred position)            */
+    int32_t gauss_passes; /* passes of the Gauss-law filter after the field step */
 } orc_params;
 
 /* ------------------------------------------------------------------ */
@@ -281,6 +284,40 @@ static void deposit_current_one(const orc_params* P, double q, double w, const d
 }
 
 /* ------------------------------------------------------------------ */
+/* Direct current of one particle (eq. "jj2"): J_d at its staggered      */
+/* position (i+1/2 along d, integer along the other axes) receives      */
+/* q w v_d W(node - X) with the same weights as the gather, taken at the */
+/* time-centred position X = (X^n + X^{n+1})/2 and the three-velocity   */
+/* v = u^{n+1/2} / gamma.  It does not satisfy eq. "cc1" in general.    */
+/* ------------------------------------------------------------------ */
+static void deposit_direct_one(const orc_params* P, double q, double w, const double X[3], const double v[3],
+                               double* J) {
+    const int O = P->shape_order;
+    const double r = support_radius(O);
+    const size_t nc = ncell(P);
+    for (int comp = 0; comp < 3; ++comp) {
+        double s[3] = {0.0, 0.0, 0.0};
+        s[comp] = 0.5;
+        int lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = (int)floor(X[d] - s[d] - r);
+            hi[d] = (int)ceil(X[d] - s[d] + r);
+        }
+        for (int k = lo[2]; k <= hi[2]; ++k)
+            for (int j = lo[1]; j <= hi[1]; ++j)
+                for (int i = lo[0]; i <= hi[0]; ++i) {
+                    double wt = orc_W(O, i + s[0] - X[0]) * orc_W(O, j + s[1] - X[1]) * orc_W(O, k + s[2] - X[2]);
+                    if (wt != 0.0) J[comp * nc + idx3(P, i, j, k)] += q * w * v[comp] * wt;
+                }
+    }
+}
+
+/* Direct current of a single particle at X with three-velocity v (test hook). */
+void orc_deposit_direct(const orc_params* P, double q, double w, const double X[3], const double v[3], double* J) {
+    deposit_direct_one(P, q, w, X, v, J);
+}
+
+/* ------------------------------------------------------------------ */
 /* Steps 1-3 of the time step (Sec. III list; eq. "pmotion" and the      */
 /* position update of Sec. III.A) for one species:                      */
 /*   gather E^n, B^n at X^n; push u^{n-1/2} -> u^{n+1/2};                */
@@ -309,7 +346,16 @@ int orc_step_species(const orc_params* P, double q, double m, double w, int64_t 
             if (!isfinite(X1[d]) || !isfinite(up[d])) flags |= 2;
         }
         if (flags & 2) continue;
-        deposit_current_one(P, q, w, X0, X1, J);
+        if (P->current_scheme == 1) {
+            double Xm[3], v[3];
+            for (int d = 0; d < 3; ++d) {
+                Xm[d] = 0.5 * (X0[d] + X1[d]);
+                v[d] = up[d] / g;
+            }
+            deposit_direct_one(P, q, w, Xm, v, J);
+        } else {
+            deposit_current_one(P, q, w, X0, X1, J);
+        }
         for (int d = 0; d < 3; ++d) {
             double x = fmod(X1[d], (double)P->n[d]);
             if (x < 0) x += P->n[d];
@@ -442,6 +488,52 @@ void orc_div_down(const orc_params* P, const double* F, double* out) {
         deriv(P, F + d * nc, t, d, 0);
         for (size_t q = 0; q < nc; ++q) out[q] += t[q];
     }
+    free(t);
+}
+
+/* ------------------------------------------------------------------ */
+/* Gauss-law filter (Sec. "Charge conservation": the paper corrects E   */
+/* iteratively after a non-conserving current and gives no formula).    */
+/* Each pass: r = div- E - (rho + rho_bg)/eps0 at the cell centres, then */
+/* E_d += kappa d+_d r.  A Fourier mode of r is multiplied by           */
+/* 1 - kappa K(k)^2 (K^2 = sum_d K_d^2, K_d the symbol magnitude of the */
+/* field-order first derivative), and kappa = 1 / max K^2 over the      */
+/* grid's wave numbers removes the largest (Nyquist) error in one pass  */
+/* and damps every other one.  The correction is a gradient: B and the  */
+/* curl of E are untouched.                                             */
+/* ------------------------------------------------------------------ */
+double orc_gauss_kappa(const orc_params* P) {
+    double a[3];
+    const int M = fd_coeffs(P->field_order, a);
+    double kmax2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double best = 0.0;
+        for (int m = 0; m < P->n[d]; ++m) {
+            const double k = 2.0 * 3.14159265358979323846 * m / P->n[d];
+            double sym = 0.0;
+            for (int l = 1; l <= M; ++l) sym += a[l - 1] * sin((l - 0.5) * k);
+            sym *= 2.0 / P->d[d];
+            if (sym * sym > best) best = sym * sym;
+        }
+        kmax2 += best;
+    }
+    return kmax2 > 0.0 ? 1.0 / kmax2 : 0.0;
+}
+
+void orc_gauss_filter(const orc_params* P, double* E, const double* rho, int passes) {
+    const size_t nc = ncell(P);
+    const double kappa = orc_gauss_kappa(P);
+    double* r = (double*)malloc(nc * sizeof(double));
+    double* t = (double*)malloc(nc * sizeof(double));
+    for (int it = 0; it < passes; ++it) {
+        orc_div_down(P, E, r);
+        for (size_t q = 0; q < nc; ++q) r[q] -= (rho[q] + P->rho_background) / P->eps0;
+        for (int d = 0; d < 3; ++d) {
+            deriv(P, r, t, d, 1);
+            for (size_t q = 0; q < nc; ++q) E[d * nc + q] += kappa * t[q];
+        }
+    }
+    free(r);
     free(t);
 }
 

@@ -44,12 +44,14 @@ class Params(ctypes.Structure):
         ("relax_max_iter", ctypes.c_int32),
         ("rho_background", ctypes.c_double),
         ("rad_tau", ctypes.c_double),
+        ("current_scheme", ctypes.c_int32),
+        ("gauss_passes", ctypes.c_int32),
     ]
 
 
 def make_params(n=(16, 16, 16), d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shape_order=2,
                 field_order=2, alpha=0.55, pusher=0, relax_tol=1e-14, relax_max_iter=200,
-                rho_background=0.0, rad_tau=0.0) -> Params:
+                rho_background=0.0, rad_tau=0.0, current_scheme=0, gauss_passes=0) -> Params:
     p = Params()
     p.n[:] = [int(v) for v in n]
     p.d[:] = [float(v) for v in d]
@@ -59,6 +61,7 @@ def make_params(n=(16, 16, 16), d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shap
     p.relax_tol, p.relax_max_iter = float(relax_tol), int(relax_max_iter)
     p.rho_background = float(rho_background)
     p.rad_tau = float(rad_tau)
+    p.current_scheme, p.gauss_passes = int(current_scheme), int(gauss_passes)
     return p
 
 
@@ -81,6 +84,10 @@ def lib():
                                    ctypes.c_double, ctypes.c_double, _D, _D, _D]
         L.orc_rad_bracket.restype = ctypes.c_double
         L.orc_rad_bracket.argtypes = [ctypes.c_double, _D, _D]
+        L.orc_deposit_direct.argtypes = [_P, ctypes.c_double, ctypes.c_double, _D, _D, _D]
+        L.orc_gauss_kappa.restype = ctypes.c_double
+        L.orc_gauss_kappa.argtypes = [_P]
+        L.orc_gauss_filter.argtypes = [_P, _D, _D, ctypes.c_int]
         L.orc_step_species.restype = ctypes.c_int
         L.orc_step_species.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_int64, _D, _D, _D, _D, _D]
@@ -145,6 +152,25 @@ def push_rad(pusher: int, q: float, m: float, dt: float, c: float, rad_tau: floa
 def rad_bracket(c: float, u, udot) -> float:
     """|du/dt|^2 + |du/dt x u|^2 / c^2 (radiated power over mu0 q^2 / (6 pi c))."""
     return lib().orc_rad_bracket(c, _ptr(np.array(u, dtype=np.float64)), _ptr(np.array(udot, dtype=np.float64)))
+
+
+def deposit_direct(P: Params, q: float, w: float, X, v, J: np.ndarray | None = None) -> np.ndarray:
+    """Direct current (eq. "jj2") of one particle at X with three-velocity v."""
+    if J is None:
+        J = np.zeros(_vec(P))
+    lib().orc_deposit_direct(ctypes.byref(P), q, w, _ptr(np.array(X, dtype=np.float64)),
+                             _ptr(np.array(v, dtype=np.float64)), _ptr(J))
+    return J
+
+
+def gauss_kappa(P: Params) -> float:
+    return lib().orc_gauss_kappa(ctypes.byref(P))
+
+
+def gauss_filter(P: Params, E: np.ndarray, rho: np.ndarray, passes: int) -> np.ndarray:
+    """Gauss-law filter passes on E in place (rho: charge density at E's time)."""
+    lib().orc_gauss_filter(ctypes.byref(P), _ptr(E), _ptr(rho), int(passes))
+    return E
 
 
 def deposit_current(P: Params, q: float, w: float, X0, X1, J: np.ndarray | None = None) -> np.ndarray:
@@ -256,10 +282,16 @@ class Run:
         self.J[:] = 0.0
         for s in self.species:
             self.flags |= step_species(self.P, s["q"], s["m"], s["w"], s["pos"], s["u"], self.E, self.B, self.J)
-        current_high_order(self.P, self.J)
+        if self.P.current_scheme == 0:  # the line solve belongs to the charge-conserving current
+            current_high_order(self.P, self.J)
 
     def fields_step(self):
         self.relax = field_step(self.P, self.E, self.B, self.J)
+        if self.P.gauss_passes > 0:  # Gauss-law filter with the charge density of x^{n+1}
+            r = np.zeros(_scal(self.P))
+            for s in self.species:
+                deposit_rho(self.P, s["q"], s["w"], s["pos"], r)
+            gauss_filter(self.P, self.E, r, self.P.gauss_passes)
 
     def step(self):
         self.particles_step()

@@ -123,3 +123,78 @@ def test_high_order_current_fourier_mode(orc, fo):
         Tk = sum(sum(a[mm - 1] for mm in range(abs(l) + 1, M + 1)) * math.cos(l * k) for l in range(-(M - 1), M))
         JO = orc.current_high_order(P, J.copy())
         assert np.max(np.abs(JO[0, 0, 0] - J[0, 0, 0] / Tk)) < 1e-14
+
+
+# ---- direct current (eq. "jj2") and the Gauss-law filter ---------------------------------------
+@pytest.mark.parametrize("O", [2, 3])
+def test_direct_current_moments(orc, O):
+    # J_d of one particle sums to q w v_d (partition of unity of the B-splines) and its first
+    # moment along every axis is q w v_d times the particle's coordinate (exact first moment;
+    # the staggered component's nodes sit at i + 1/2): pins the weights and the position used
+    N = (9, 8, 7)
+    P = orc.make_params(n=N, shape_order=O)
+    rng = np.random.default_rng(O)
+    for _ in range(5):
+        X = rng.uniform(3, 5, 3)
+        v = rng.normal(0, 0.3, 3)
+        J = orc.deposit_direct(P, -1.0, 0.5, X, v)
+        for d in range(3):
+            Jd = J[d]  # [z, y, x]
+            assert abs(Jd.sum() - (-0.5 * v[d])) < 1e-14
+            coords = [np.arange(N[a]) + (0.5 if a == d else 0.0) for a in range(3)]
+            for a in range(3):
+                axis = 2 - a
+                other = tuple(i for i in range(3) if i != axis)
+                first = (Jd.sum(axis=other) * coords[a]).sum()
+                assert abs(first - (-0.5 * v[d]) * X[a]) < 1e-12
+
+
+def test_direct_current_uses_the_time_centred_position(orc):
+    # a lone particle moving along x: its direct current is the deposit at (X0 + X1)/2
+    N = (12, 6, 6)
+    P = orc.make_params(n=N, shape_order=3, current_scheme=1, dt=0.5)
+    X0 = np.array([[5.3], [2.2], [3.7]])
+    u = np.array([[0.6], [0.0], [0.0]])
+    E = np.zeros((3, 6, 6, 12))
+    J = np.zeros_like(E)
+    pos, uu = X0.copy(), u.copy()
+    orc.step_species(P, 1.0, 1.0, 0.25, pos, uu, E, E, J)
+    g = math.sqrt(1 + 0.36)
+    Xm = X0[:, 0] + np.array([0.25 * 0.6 / g, 0, 0])
+    ref = orc.deposit_direct(P, 1.0, 0.25, Xm, np.array([0.6 / g, 0, 0]))
+    assert np.max(np.abs(J - ref)) < 1e-15
+    assert abs(pos[0, 0] - (5.3 + 0.5 * 0.6 / g)) < 1e-14
+
+
+@pytest.mark.parametrize("fo", [2, 6])
+def test_gauss_filter_damps_each_mode_by_its_symbol(orc, fo):
+    # one pass multiplies every Fourier mode of the residual div- E - rho by 1 - kappa K^2 with
+    # K_d = (2/d) sum_m a_m sin((m - 1/2) k) (closed form, Sec. III.B coefficients); the
+    # correction is a gradient (curl unchanged) and the largest-K mode is removed
+    rng = np.random.default_rng(fo)
+    N, d = (8, 6, 10), (1.0, 0.9, 1.2)
+    P = orc.make_params(n=N, d=d, field_order=fo)
+    E = rng.normal(size=(3, N[2], N[1], N[0]))
+    rho = rng.normal(size=(N[2], N[1], N[0]))
+    rho -= rho.mean()
+    r0 = orc.div_down(P, E) - rho
+    E1 = orc.gauss_filter(P, E.copy(), rho, 1)
+    r1 = orc.div_down(P, E1) - rho
+    a = orc.fd_coeffs(fo)
+    K2 = np.zeros(r0.shape)
+    for dim in range(3):
+        k = 2 * math.pi * np.fft.fftfreq(N[dim])
+        Kd = (2 / d[dim]) * sum(a[i] * np.sin((i + 0.5) * k) for i in range(3))
+        shape = [1, 1, 1]
+        shape[2 - dim] = N[dim]
+        K2 = K2 + (Kd ** 2).reshape(shape)
+    kappa = orc.gauss_kappa(P)
+    assert abs(kappa * K2.max() - 1.0) < 1e-12
+    want = np.fft.ifftn(np.fft.fftn(r0) * (1 - kappa * K2)).real
+    assert np.max(np.abs(r1 - want)) < 1e-11 * np.max(np.abs(r0))
+    assert np.max(np.abs(orc.curl_up(P, E1) - orc.curl_up(P, E))) < 1e-12 * np.max(np.abs(E))
+    # converges towards Gauss's law; no change where it already holds
+    r5 = orc.div_down(P, orc.gauss_filter(P, E.copy(), rho, 5)) - rho
+    assert np.max(np.abs(r5)) < np.max(np.abs(r1)) < np.max(np.abs(r0))
+    E2 = orc.gauss_filter(P, E1.copy(), orc.div_down(P, E1), 3)
+    assert np.max(np.abs(E2 - E1)) < 1e-13 * np.max(np.abs(E1))

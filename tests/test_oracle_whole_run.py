@@ -201,3 +201,24 @@ def test_mmi_loader_is_neutral_and_boosted():
     assert np.sqrt(1 + (b ** 2).sum()) == pytest.approx(4.0 * (np.sqrt(1.14) + beta * 0.3))
     r = I.mmi_rates()
     assert round(r["mmi"], 3) == 0.201 and round(r["fi"], 3) == 0.153 and round(r["tsi"], 3) == 0.080
+
+
+def test_direct_current_breaks_gauss_and_the_filter_restores_it(orc):
+    # the plain-heating workload with the direct current (eq. "jj2"): Gauss's law drifts away
+    # from its initial zero; five filter passes per step keep it orders of magnitude lower,
+    # and the charge-conserving current keeps it at rounding level
+    from paper_1211_4575_amd import inputs as I
+    wl = I.plain_heating(n=(8, 8, 8), ppc=8)
+    res = {}
+    for name, kw in (("direct", dict(current_scheme=1)), ("filtered", dict(current_scheme=1, gauss_passes=5)),
+                     ("cc", {})):
+        P = orc.make_params(**{**wl.params(), **kw})
+        run = orc.Run(P, [dict(q=s.q, m=s.m, w=s.w, pos=s.pos, u=s.u) for s in wl.species])
+        worst = 0.0
+        for _ in range(10):
+            run.step()
+            worst = max(worst, np.max(np.abs(orc.div_down(P, run.E) - run.rho())))
+        res[name] = worst
+    assert res["direct"] > 1e-3
+    assert res["filtered"] < 0.05 * res["direct"]
+    assert res["cc"] < 1e-12
