@@ -33,7 +33,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_pair_mj_run(pp, ind, torch, n, ppc, theta, split, with_id=False, rad_tau=0.0):
+def make_pair_mj_run(pp, ind, torch, n, ppc, theta, split, with_id=False, rad_tau=0.0, current_scheme=0,
+                     gauss_passes=0):
     """Build a pp.Run for the pair-plasma workload with particles generated on the device.
     Returns the run and the number of particles per species."""
     npart = n[0] * n[1] * n[2] * ppc
@@ -53,7 +54,8 @@ def make_pair_mj_run(pp, ind, torch, n, ppc, theta, split, with_id=False, rad_ta
     torch.cuda.synchronize()
     params = pp.make_params(n, shape_order=3, field_order=6, dt=0.4, alpha=0.55,
                             precision=pp.PP_PREC_FP32_SPLIT if split else pp.PP_PREC_FP64,
-                            relax_tol=1e-8 if split else 1e-14, relax_max_iter=100, rad_tau=rad_tau)
+                            relax_tol=1e-8 if split else 1e-14, relax_max_iter=100, rad_tau=rad_tau,
+                            current_scheme=current_scheme, gauss_filter_passes=gauss_passes)
     species = []
     for s, q in enumerate((-1.0, 1.0)):
         sp = dict(q=q, m=1.0, w=1.0 / ppc, u=us[s])
@@ -100,7 +102,7 @@ def cpu_baseline(n_sample=(16, 16, 16), ppc=32, steps=4):
                        f"({wl.n_particles} particles), {steps} full steps, {dt:.1f} s")
 
 
-def flops_per_update(O=3):
+def flops_per_update(O=3, direct=False):
     """Algorithmic floating-point operations of one particle update (FMA = 2), counted from the
     method as the tiled kernel formulates it: B-spline weight sets (centred and staggered at
     the old position, centred at the new one; 3 axes; ~17 flops each for cubic), factored
@@ -111,6 +113,9 @@ def flops_per_update(O=3):
     gather = 6 * 2 * (n1 ** 3 + n1 ** 2 + n1)
     push = 100
     move = 12
+    if direct:  # centred and staggered weight sets at the time-centred position, 2 flops per product
+        return weights - 3 * (17 if O == 3 else 9) + 6 * (17 if O == 3 else 9) + gather + push + move + \
+            3 * (2 * n1 * n1 * n1 + 2 * n1 * n1 + 1)
     per_comp = n2 + (n1 - 1) + 2 * n2 + 3 * n2 + 3 * n2 * n2 + 2 * n1 * n2 * n2
     return weights + gather + push + move + 3 * per_comp
 
@@ -548,6 +553,9 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rad-tau", type=float, default=0.0, help="radiative cooling constant (0: off)")
+    ap.add_argument("--current", choices=("cc", "direct"), default="cc",
+                    help="current scheme: charge-conserving (default) or direct")
+    ap.add_argument("--gauss-passes", type=int, default=0, help="Gauss-law filter passes per step")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--workload", choices=("pair_mj", "serving", "two_stream", "kh", "mmi"), default="pair_mj")
@@ -600,7 +608,9 @@ def main(argv=None):
 
     n = (args.grid, args.grid, args.grid)
     log(f"[bench] FP32 split: generating {n} x {args.ppc} ppc x 2 species on the device")
-    run, npart = make_pair_mj_run(pp, ind, torch, n, args.ppc, 1.0, split=True, rad_tau=args.rad_tau)
+    scheme = pp.PP_CURRENT_DIRECT if args.current == "direct" else pp.PP_CURRENT_CC
+    run, npart = make_pair_mj_run(pp, ind, torch, n, args.ppc, 1.0, split=True, rad_tau=args.rad_tau,
+                                  current_scheme=scheme, gauss_passes=args.gauss_passes)
     npart *= 2  # electrons and positrons
     log(f"[bench] FP32 split: {npart} particles; warmup {args.warmup}, timing {args.steps} steps")
     wall, gpd_ms = time_steps(run, torch, args.steps, args.warmup)
@@ -625,7 +635,8 @@ def main(argv=None):
     fp64 = None
     if not args.no_fp64:
         log(f"[bench] FP64 plain: generating")
-        run, _ = make_pair_mj_run(pp, ind, torch, n, args.ppc, 1.0, split=False, rad_tau=args.rad_tau)
+        run, _ = make_pair_mj_run(pp, ind, torch, n, args.ppc, 1.0, split=False, rad_tau=args.rad_tau,
+                                  current_scheme=scheme, gauss_passes=args.gauss_passes)
         log(f"[bench] FP64 plain: warmup 1, timing {args.fp64_steps} steps")
         wall64, gpd64_ms = time_steps(run, torch, args.fp64_steps, 1)
         fp64 = dict(value=npart * args.fp64_steps / wall64, ms_per_step=1e3 * wall64 / args.fp64_steps,
@@ -637,7 +648,7 @@ def main(argv=None):
 
     bytes_per_update = 56.0  # split state read + written: int32 cell + 3 FP32 offsets + 3 FP32 u
     achieved_gbs = npart * bytes_per_update / (gpd_ms * 1e-3) / 1e9
-    fl = flops_per_update(3)
+    fl = flops_per_update(3, direct=args.current == "direct")
     achieved_tf = npart * fl / (gpd_ms * 1e-3) / 1e12
     traffic = measured_traffic(npart)
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
@@ -674,6 +685,7 @@ def main(argv=None):
         "config": {"workload": f"pair plasma {n[0]}x{n[1]}x{n[2]}, {args.ppc} ppc/species, Maxwell-Juttner kT=mc^2, "
                                f"cubic weights, 6th-order fields, FP32 split positions",
                    "particles": npart, "step": "gather/push/deposit + line solve + sort + field step", "rad_tau": args.rad_tau,
+                   "current": args.current, "gauss_passes": args.gauss_passes,
                    "gpd_updates_per_s": gpd_rate, "fp64_plain": fp64,
                    "fp32_over_fp64": (value / fp64["value"]) if fp64 else None, "diagnostics": diag32},
         "roofline": roofline,

@@ -59,6 +59,11 @@ enum {
 
 enum { PP_PREC_FP64 = 0, PP_PREC_FP32_SPLIT = 1 };
 enum { PP_PUSH_VAY = 0, PP_PUSH_BORIS = 1 };
+/* Current schemes: charge-conserving (Esirkepov form, Sec. III.C, with the high-order line
+ * solve for field orders 4 and 6) or direct (eq. "jj2": q w v W at the staggered J nodes, at the
+ * time-centred position; no line solve; does not satisfy eq. "cc1"). */
+enum { PP_CURRENT_CC = 0, PP_CURRENT_DIRECT = 1 };
+enum { PP_MAX_GAUSS_PASSES = 64 };
 enum { PP_MAX_SPECIES = 8 };
 
 /* device flag bits reported in pp_diag.flags */
@@ -99,6 +104,15 @@ typedef struct pp_params {
                             * u0 the mean of the old and new proper velocities and du/dt
                             * their difference over dt (explicit, no iteration).  0 (the
                             * default) turns it off; must be finite and >= 0.          */
+    int32_t current_scheme;  /* PP_CURRENT_CC (default) or PP_CURRENT_DIRECT              */
+    int32_t gauss_filter_passes; /* 0..PP_MAX_GAUSS_PASSES passes of the Gauss-law filter
+                            * at the end of pp_field_step (Sec. "Charge conservation":
+                            * the paper corrects E after a non-conserving current): each
+                            * pass computes r = div- E - (rho + rho_bg)/eps0 with rho of
+                            * the current positions and adds kappa d+ r to E, kappa =
+                            * 1 / max |K|^2 over the grid's wave numbers (K the symbol of
+                            * the field-order first derivative).  Runs with passes > 0 are
+                            * not accepted by pp_batch_add.                           */
 } pp_params;
 
 /* Caller-owned FP64 mesh (device pointers, 3*ncell doubles each). */

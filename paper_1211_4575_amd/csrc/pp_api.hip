@@ -39,6 +39,8 @@ static pp_status validate(const pp_params* p) {
         !std::isfinite(p->relax_tol) || !std::isfinite(p->rho_background) || !std::isfinite(p->rad_tau))
         return PP_E_NONFINITE;
     if (p->rad_tau < 0.0) return PP_E_ARG;
+    if (p->current_scheme != PP_CURRENT_CC && p->current_scheme != PP_CURRENT_DIRECT) return PP_E_ARG;
+    if (p->gauss_filter_passes < 0 || p->gauss_filter_passes > PP_MAX_GAUSS_PASSES) return PP_E_ARG;
     if (!finite_pos(p->dt) || !finite_pos(p->c) || !finite_pos(p->eps0)) return PP_E_ARG;
     if (p->shape_order != 2 && p->shape_order != 3) return PP_E_ARG;
     if (p->field_order != 2 && p->field_order != 4 && p->field_order != 6) return PP_E_ARG;
@@ -319,7 +321,7 @@ pp_status pp_gather_push_deposit(pp_run* r) {
     for (int s = 0; s < PP_MAX_SPECIES; ++s)
         if (split && r->sp[s].active && !r->sp[s].sorted) return PP_E_STATE;
     if (flush_timing(r) != PP_OK) return PP_E_HIP;
-    double* target = r->p.field_order > 2 ? r->J2 : r->mesh.J;
+    double* target = uses_line_solve(r) ? r->J2 : r->mesh.J;
     hipError_t e = hipSuccess;
     if (!split) {  // the split kernel overwrites its target
         e = launch_fill(target, 3 * r->g.ncell, 0.0, r->stream);
@@ -345,7 +347,7 @@ pp_status pp_gather_push_deposit(pp_run* r) {
             r->sp[s].sorted = false;
             r->sp[s].ranked = true;  // the kernel counted the new cells for the next sort
         }
-    if (r->p.field_order > 2) {
+    if (uses_line_solve(r)) {
         e = launch_line_solve(r, r->J2, r->mesh.J);
         if (!ok(e, "line_solve")) return PP_E_HIP;
     }
@@ -356,7 +358,12 @@ pp_status pp_gather_push_deposit(pp_run* r) {
 pp_status pp_field_step(pp_run* r) {
     if (!r) return PP_E_ARG;
     hipError_t e = launch_field_step(r);
-    return ok(e, "field_step") ? PP_OK : PP_E_HIP;
+    if (!ok(e, "field_step")) return PP_E_HIP;
+    if (r->p.gauss_filter_passes > 0) {
+        e = launch_gauss_filter(r);
+        if (!ok(e, "gauss_filter")) return PP_E_HIP;
+    }
+    return PP_OK;
 }
 
 pp_status pp_sort_particles(pp_run* r, int32_t s) {

@@ -92,6 +92,7 @@ pp_status pp_batch_add(pp_batch* b, pp_run* r) {
         if (x == r) return PP_E_STATE;
     if (r->p.precision != PP_PREC_FP32_SPLIT || !gpd32_batchable(r)) return PP_E_ARG;
     if (r->stream != b->stream) return PP_E_ARG;
+    if (r->p.gauss_filter_passes > 0) return PP_E_ARG;  // the filter has no batched form
     if (!b->runs.empty() && b->runs[0]->p.shape_order != r->p.shape_order) return PP_E_ARG;
     for (int s = 0; s < PP_MAX_SPECIES; ++s)
         if (r->sp[s].active && !r->sp[s].sorted) return PP_E_STATE;
@@ -126,7 +127,7 @@ pp_status pp_batch_step(pp_batch* b) {
     // ---- layout of the step's descriptor tables --------------------------------------
     std::vector<int> line_runs;
     for (int i = 0; i < n; ++i)
-        if (b->runs[i]->p.field_order > 2) line_runs.push_back(i);
+        if (uses_line_solve(b->runs[i])) line_runs.push_back(i);
     const int nl = (int)line_runs.size();
     std::vector<int> slot_segs[PP_MAX_SPECIES];
     for (int s = 0; s < PP_MAX_SPECIES; ++s)
@@ -163,7 +164,7 @@ pp_status pp_batch_step(pp_batch* b) {
     int max_sweeps = 0;
     for (int i = 0; i < n; ++i) {
         pp_run* r = b->runs[i];
-        double* target = r->p.field_order > 2 ? r->J2 : r->mesh.J;
+        double* target = uses_line_solve(r) ? r->J2 : r->mesh.J;
         gpd32_fill_args(r, (Gpd32Args*)(H + o_gpd + i * gpd32_args_size()));
         gpd32_fixed_desc(r, target, (FixedDesc*)(H + o_fix + i * gpd32_fixed_desc_size()));
         field_desc(r, (FieldDesc*)(H + o_field + i * field_desc_size()));

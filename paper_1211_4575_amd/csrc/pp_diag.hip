@@ -458,6 +458,31 @@ static hipError_t launch_rho32(pp_run* r, unsigned mask) {
     return hipGetLastError();
 }
 
+// rho of the current particle positions into r->rho.  Split species stored tile by tile
+// (sorted, or pushed since the last sort) go through the tiled fixed-point deposit, which
+// writes every node of rho; the others are added with FP64 atomics.
+hipError_t deposit_rho_all(pp_run* r) {
+    const int64_t nc = r->g.ncell;
+    const bool split = r->p.precision == PP_PREC_FP32_SPLIT;
+    unsigned tiled = 0;
+    if (split)
+        for (int s = 0; s < PP_MAX_SPECIES; ++s) {
+            const Species& S = r->sp[s];
+            if (S.active && S.n > 0 && S.q * S.w != 0.0 && (S.sorted || S.ranked)) tiled |= 1u << s;
+        }
+    hipError_t e = tiled ? launch_rho32(r, tiled) : launch_fill(r->rho, nc, 0.0, r->stream);
+    if (e != hipSuccess) return e;
+    for (int s = 0; s < PP_MAX_SPECIES; ++s) {
+        const Species& S = r->sp[s];
+        if (!S.active || S.n == 0 || S.q * S.w == 0.0 || (tiled & (1u << s))) continue;
+        if (split)
+            deposit_rho_species<float>(r, S);
+        else
+            deposit_rho_species<double>(r, S);
+    }
+    return hipGetLastError();
+}
+
 // Fills host_out[0..ACC_COUNT) with the accumulators and [ACC_COUNT] with the flag word.
 hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out) {
     const int bs = 256;
@@ -495,29 +520,8 @@ hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out) {
     const bool want_divb = (what & PP_DIAG_DIVB) != 0;
     bool have_prev = false;
     if (want_rho) {
-        // split species stored tile by tile (sorted, or pushed since the last sort) go through
-        // the tiled fixed-point deposit, which writes every node of rho; the others are added
-        // with FP64 atomics
-        unsigned tiled = 0;
-        if (split)
-            for (int s = 0; s < PP_MAX_SPECIES; ++s) {
-                const Species& S = r->sp[s];
-                if (S.active && S.n > 0 && S.q * S.w != 0.0 && (S.sorted || S.ranked)) tiled |= 1u << s;
-            }
-        if (tiled) {
-            e = launch_rho32(r, tiled);
-        } else {
-            e = launch_fill(r->rho, nc, 0.0, r->stream);
-        }
+        e = deposit_rho_all(r);
         if (e != hipSuccess) return e;
-        for (int s = 0; s < PP_MAX_SPECIES; ++s) {
-            const Species& S = r->sp[s];
-            if (!S.active || S.n == 0 || S.q * S.w == 0.0 || (tiled & (1u << s))) continue;
-            if (split)
-                deposit_rho_species<float>(r, S);
-            else
-                deposit_rho_species<double>(r, S);
-        }
         have_prev = r->rho_prev_step >= 0 && r->rho_prev_step == r->step - 1;
     }
     if (want_rho || want_divb) {

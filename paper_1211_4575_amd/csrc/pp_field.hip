@@ -111,6 +111,8 @@ struct FieldDesc {
     double* Bw;  // relaxation partner
     double* R;   // right-hand side
     const double* omega;        // Chebyshev weights omega_k, k = 1..sweeps (device)
+    const double* rho;          // charge density (Gauss-law filter)
+    double rho_bg, ieps0, kappa;  // background density, 1/eps0, filter damping
     double cab, dt, cj;         // alpha beta s, dt, alpha c^2 mu0 dt^2   (s = c^2 dt^2)
     double al2s, gdiag;         // alpha^2 s, gamma / diagonal
     double al, be, c2dt, mu0;   // alpha, beta, c^2 dt, mu0
@@ -173,7 +175,25 @@ __device__ __forceinline__ void update_E_body(const FieldDesc& D, int i, int j, 
     }
 }
 
-enum FieldPhase { PH_COPY = 0, PH_RHS = 1, PH_JACOBI = 2, PH_UPDATE_E = 3 };
+// Gauss-law filter pass, first half: r = div- E - (rho + rho_bg)/eps0 into R
+__device__ __forceinline__ void gauss_res_body(const FieldDesc& D, int i, int j, int k) {
+    const FieldGeom& G = D.G;
+    const int q = lin(G, i, j, k);
+    double dv = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dv += ddn(G, D.E + c * G.nc, c, i, j, k);
+    D.R[q] = dv - (D.rho[q] + D.rho_bg) * D.ieps0;
+}
+
+// second half: E_c += kappa d+_c r
+__device__ __forceinline__ void gauss_corr_body(const FieldDesc& D, int i, int j, int k) {
+    const FieldGeom& G = D.G;
+    const int q = lin(G, i, j, k);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) D.E[c * G.nc + q] += D.kappa * dup(G, D.R, c, i, j, k);
+}
+
+enum FieldPhase { PH_COPY = 0, PH_RHS = 1, PH_JACOBI = 2, PH_UPDATE_E = 3, PH_GAUSS_RES = 4, PH_GAUSS_CORR = 5 };
 
 __device__ __forceinline__ void field_phase(const FieldDesc& D, int64_t b, int phase, int k) {
     int i, j, kk;
@@ -184,8 +204,12 @@ __device__ __forceinline__ void field_phase(const FieldDesc& D, int64_t b, int p
         rhs_body(D, i, j, kk);
     else if (phase == PH_JACOBI) {
         if (k <= D.sweeps) relax_body(D, i, j, kk, k);
-    } else
+    } else if (phase == PH_UPDATE_E)
         update_E_body(D, i, j, kk);
+    else if (phase == PH_GAUSS_RES)
+        gauss_res_body(D, i, j, kk);
+    else
+        gauss_corr_body(D, i, j, kk);
 }
 
 __global__ void __launch_bounds__(FIELD_BS) k_field(FieldDesc D, int phase, int k) {
@@ -312,6 +336,22 @@ hipError_t field_setup(pp_run* r) {
     }
     r->jac_sweeps = sweeps;
     r->jac_bound = bound;
+    // Gauss-law filter damping: 1 / max over the grid's wave numbers of sum_d K_d^2, K_d the
+    // symbol (2/d) sum_m a_m sin((m - 1/2) k) of the field-order first derivative
+    double kmax2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const int N = r->p.n[d];
+        double best = 0.0;
+        for (int mm = 0; mm < N; ++mm) {
+            const double k = 2.0 * M_PI * mm / N;
+            double sym = 0.0;
+            for (int l = 1; l <= M; ++l) sym += a[l - 1] * sin((l - 0.5) * k);
+            sym *= 2.0 / r->p.d[d];
+            best = sym * sym > best ? sym * sym : best;
+        }
+        kmax2 += best;
+    }
+    r->gauss_kappa = kmax2 > 0.0 ? 1.0 / kmax2 : 0.0;
     // omega_1 = 1, omega_2 = 1 / (1 - r^2/2), omega_{k+1} = 1 / (1 - r^2 omega_k / 4)
     const int n_om = r->p.relax_max_iter + 2;
     double* om = new (std::nothrow) double[n_om];
@@ -336,6 +376,10 @@ void field_desc(const pp_run* r, FieldDesc* D) {
     D->Bw = r->Bw;
     D->R = r->R;
     D->omega = r->omega;
+    D->rho = r->rho;
+    D->rho_bg = r->p.rho_background;
+    D->ieps0 = 1.0 / r->p.eps0;
+    D->kappa = r->gauss_kappa;
     D->cab = al * be * s;
     D->dt = dt;
     D->cj = al * c2 * mu0 * dt * dt;
@@ -359,6 +403,21 @@ hipError_t launch_field_step(pp_run* r) {
     hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_RHS, 0);
     for (int k = 1; k <= D.sweeps; ++k) hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_JACOBI, k);
     hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_UPDATE_E, 0);
+    return hipGetLastError();
+}
+
+// Gauss-law filter of a run (after its field step): rho of the current positions, then the
+// passes, each a residual launch and a correction launch.
+hipError_t launch_gauss_filter(pp_run* r) {
+    hipError_t e = deposit_rho_all(r);
+    if (e != hipSuccess) return e;
+    FieldDesc D;
+    field_desc(r, &D);
+    const dim3 grid((unsigned)blocks_of(D.G));
+    for (int it = 0; it < r->p.gauss_filter_passes; ++it) {
+        hipLaunchKernelGGL(k_field, grid, dim3(FIELD_BS), 0, r->stream, D, (int)PH_GAUSS_RES, 0);
+        hipLaunchKernelGGL(k_field, grid, dim3(FIELD_BS), 0, r->stream, D, (int)PH_GAUSS_CORR, 0);
+    }
     return hipGetLastError();
 }
 

@@ -47,6 +47,7 @@ struct Sp32 {
     float h;        // q dt / m
     float krad;     // radiative cooling constant rad_tau q^2 / m (0: off)
     double fac[3];  // -q w d_c / dt
+    double qw;      // q w (direct current)
 };
 
 struct Gpd32Args {
@@ -71,6 +72,7 @@ struct Gpd32Args {
     int per_xcd;
     int sext[3];  // destination-cell window per axis (tile + 2 below + 2 above; 1 if collapsed)
     int nslots;   // sext[0] * sext[1] * sext[2]
+    int direct;   // PP_CURRENT_DIRECT: eq. "jj2" instead of the Esirkepov current
 };
 
 constexpr int GPD32_BS = 256;
@@ -301,6 +303,7 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
         const int32_t start = S.start[tile];
         const int32_t end = S.start[tile + 1];
         const double facq[3] = {S.fac[0] * qs, S.fac[1] * qs, S.fac[2] * qs};
+        const double qwq = S.qw * qs;
         for (int32_t p = start + threadIdx.x; p < end; p += GPD32_BS) {
             const int32_t cell = S.cell[p];
             float f[3] = {S.pos[0][p], S.pos[1][p], S.pos[2][p]};
@@ -381,6 +384,45 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
                 continue;
             }
 
+            if (A.direct) {
+                // direct current (eq. "jj2"): q w v_c W at J_c's staggered nodes, at the
+                // time-centred offset f + dd/2 (its supports stay inside the block's halo)
+                float wcm[3][O + 1], wsm[3][O + 1];
+                int ncm[3], nsm[3];
+                const int clo[3] = {L.clox, L.cloy, L.cloz};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    int bc, bs;
+                    split_weights<O>(f[d] + 0.5f * dxs[d], wcm[d], bc, wsm[d], bs);
+                    ncm[d] = loc[d] + clo[d] + bc;
+                    nsm[d] = loc[d] + clo[d] + bs;
+                }
+                const int cst[3] = {L.csx, L.csy, L.csz};
+#pragma unroll
+                for (int comp = 0; comp < 3; ++comp) {
+                    unsigned long long* Jc = cur + comp * L.cvol;
+                    const double vq = qwq * (double)(uu[comp] * ig);
+                    const int n0x = comp == 0 ? nsm[0] : ncm[0];
+                    const int n0y = comp == 1 ? nsm[1] : ncm[1];
+                    const int n0z = comp == 2 ? nsm[2] : ncm[2];
+                    const float* wx = comp == 0 ? wsm[0] : wcm[0];
+                    const float* wy = comp == 1 ? wsm[1] : wcm[1];
+                    const float* wz = comp == 2 ? wsm[2] : wcm[2];
+#pragma unroll
+                    for (int c = 0; c <= O; ++c) {
+#pragma unroll
+                        for (int b = 0; b <= O; ++b) {
+                            const double wzy = vq * (double)(wz[c] * wy[b]);
+                            const int rowo = n0x * cst[0] + (n0y + b) * cst[1] + (n0z + c) * cst[2];
+#pragma unroll
+                            for (int a = 0; a <= O; ++a) {
+                                const double dq = fma(wzy, (double)wx[a], ROUND_MAGIC);
+                                atomicAdd(Jc + rowo + a * cst[0], (unsigned long long)__double_as_longlong(dq));
+                            }
+                        }
+                    }
+                }
+            } else {
             // Esirkepov current on the common window of O+2 centred nodes per axis
             float S0[3][O + 2], DS[3][O + 2];
             int wb[3];
@@ -441,6 +483,8 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
                         }
                     }
                 }
+            }
+
             }
 
             // renormalise: new cell and offset in [lo, lo + 1), or in [lo + 1, lo + 2) in the
@@ -689,6 +733,7 @@ void gpd32_fill_args(const pp_run* r, Gpd32Args* Ap) {
         }
         D.h = (float)(S.q * r->p.dt / S.m);
         D.krad = (float)(r->p.rad_tau * S.q * S.q / S.m);
+        D.qw = S.q * S.w;
     }
     A.E = r->mesh.E;
     A.B = r->mesh.B;
@@ -696,6 +741,7 @@ void gpd32_fill_args(const pp_run* r, Gpd32Args* Ap) {
     A.qscale = r->qscale;
     A.flags = r->flags;
     A.per_xcd = (int)((r->g.ntiles + 7) / 8);
+    A.direct = r->p.current_scheme == PP_CURRENT_DIRECT ? 1 : 0;
     A.nslots = 1;
     for (int d = 0; d < 3; ++d) {
         A.sext[d] = r->p.n[d] == 1 ? 1 : r->g.t[d] + 4;

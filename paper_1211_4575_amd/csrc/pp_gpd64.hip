@@ -23,6 +23,8 @@ struct Gpd64Args {
     int64_t ncell;
     int32_t* flags;
     int pusher;
+    int direct;       // PP_CURRENT_DIRECT: eq. "jj2" instead of the Esirkepov current
+    double qw;        // q w (direct current)
 };
 
 template <int O>
@@ -101,6 +103,44 @@ __global__ void __launch_bounds__(256) k_gpd64(Gpd64Args A) {
         return;
     }
 
+    if (A.direct) {
+        // direct current (eq. "jj2"): q w v_c W at J_c's staggered nodes, at the time-centred
+        // position, with the gather's weights
+        double Xm[3], wmc[3][O + 1], wms[3][O + 1];
+        int imc[3][O + 1], ims[3][O + 1];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            Xm[d] = 0.5 * (X0[d] + X1[d]);
+            const int c0 = weights_abs<O>(Xm[d], wmc[d]);
+            const int s0 = weights_abs<O>(Xm[d] - 0.5, wms[d]);
+#pragma unroll
+            for (int a = 0; a <= O; ++a) {
+                imc[d][a] = wrap(c0 + a, A.n[d]);
+                ims[d][a] = wrap(s0 + a, A.n[d]);
+            }
+        }
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) {
+            const double vq = A.qw * uu[comp] / g;
+            double* Jc = A.J + comp * nc;
+#pragma unroll
+            for (int c = 0; c <= O; ++c) {
+                const int k = comp == 2 ? ims[2][c] : imc[2][c];
+                const double wz = comp == 2 ? wms[2][c] : wmc[2][c];
+#pragma unroll
+                for (int b = 0; b <= O; ++b) {
+                    const int j = comp == 1 ? ims[1][b] : imc[1][b];
+                    const double wzy = vq * wz * (comp == 1 ? wms[1][b] : wmc[1][b]);
+#pragma unroll
+                    for (int a = 0; a <= O; ++a) {
+                        const int i = comp == 0 ? ims[0][a] : imc[0][a];
+                        const double v = wzy * (comp == 0 ? wms[0][a] : wmc[0][a]);
+                        if (v != 0.0) atomic_add_f64(Jc + (int64_t)i + (int64_t)nx * (j + (int64_t)ny * k), v);
+                    }
+                }
+            }
+        }
+    } else {
     // Esirkepov current (Sec. III.C) on the common window of O+2 centred nodes per axis
     double S0[3][O + 2], DS[3][O + 2];
     int base[3];
@@ -151,6 +191,7 @@ __global__ void __launch_bounds__(256) k_gpd64(Gpd64Args A) {
             }
         }
     }
+    }
     (void)ny;
     (void)nz;
 
@@ -189,6 +230,8 @@ hipError_t launch_gpd64(pp_run* r, int s, double* J) {
     A.ncell = r->g.ncell;
     A.flags = r->flags;
     A.pusher = r->p.pusher;
+    A.direct = r->p.current_scheme == PP_CURRENT_DIRECT ? 1 : 0;
+    A.qw = S.q * S.w;
     const int bs = 256;
     const int64_t nb = (S.n + bs - 1) / bs;
     if (r->p.shape_order == 2)

@@ -104,6 +104,7 @@ struct pp_run {
     int jac_sweeps = 0;      // relaxation sweeps per field step
     double jac_bound = 0.0;  // error reduction bound after jac_sweeps sweeps
     double* omega = nullptr; // Chebyshev weights (device, relax_max_iter + 2)
+    double gauss_kappa = 0.0; // damping of the Gauss-law filter: 1 / max |K|^2
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timing = false;
@@ -115,6 +116,12 @@ struct pp_run {
 };
 
 namespace pp {
+
+// the high-order line solve turns the second-order charge-conserving current into the
+// field-order one; the direct current is deposited as it is
+inline bool uses_line_solve(const pp_run* r) {
+    return r->p.field_order > 2 && r->p.current_scheme == PP_CURRENT_CC;
+}
 
 void set_hip_error(hipError_t e, const char* where);
 inline bool ok(hipError_t e, const char* where) {
@@ -138,6 +145,8 @@ hipError_t launch_sort(pp_run* r, int s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 void sort_done(pp_run* r, int s);  // host bookkeeping after a ranked sort was enqueued
 hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out);
+hipError_t deposit_rho_all(pp_run* r);  // rho of the current positions into r->rho
+hipError_t launch_gauss_filter(pp_run* r);  // the run's Gauss-law filter passes on E
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void swap_buffers(pp_particles& c);
 

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpp.so")
 PP_OK, PP_E_ARG, PP_E_CFL, PP_E_NONFINITE, PP_E_NOCONV, PP_E_CAPACITY, PP_E_HIP, PP_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 PP_PREC_FP64, PP_PREC_FP32_SPLIT = 0, 1
 PP_PUSH_VAY, PP_PUSH_BORIS = 0, 1
+PP_CURRENT_CC, PP_CURRENT_DIRECT = 0, 1
 PP_MAX_SPECIES = 8
 PP_FLAG_CFL, PP_FLAG_NONFINITE, PP_FLAG_OUT_OF_TILE = 1, 2, 4
 PP_DIAG_MOMENTS, PP_DIAG_FIELDS, PP_DIAG_RHO, PP_DIAG_DIVB, PP_DIAG_ALL = 1, 2, 4, 8, 15
@@ -43,6 +44,8 @@ class pp_params(ctypes.Structure):
         ("relax_max_iter", ctypes.c_int32),
         ("rho_background", ctypes.c_double),
         ("rad_tau", ctypes.c_double),
+        ("current_scheme", ctypes.c_int32),
+        ("gauss_filter_passes", ctypes.c_int32),
     ]
 
 
@@ -226,7 +229,7 @@ def pp_batch_destroy(batch):
 # ---- convenience owner of the torch tensors ---------------------------------------------
 def make_params(n, d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shape_order=2, field_order=2, alpha=0.55,
                 pusher=0, precision=PP_PREC_FP64, relax_tol=1e-14, relax_max_iter=200, rho_background=0.0,
-                rad_tau=0.0):
+                rad_tau=0.0, current_scheme=0, gauss_filter_passes=0):
     p = pp_params()
     p.n[:] = [int(v) for v in n]
     p.d[:] = [float(v) for v in d]
@@ -236,6 +239,7 @@ def make_params(n, d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shape_order=2, fi
     p.relax_tol, p.relax_max_iter = float(relax_tol), int(relax_max_iter)
     p.rho_background = float(rho_background)
     p.rad_tau = float(rad_tau)
+    p.current_scheme, p.gauss_filter_passes = int(current_scheme), int(gauss_filter_passes)
     return p
 
 

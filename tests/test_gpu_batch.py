@@ -47,11 +47,15 @@ def _split_species(species, n, O):
     return out
 
 
+DIRECT_RUNS = (1,)  # runs with the direct current (no line solve) in the batch
+
+
 def _make(ppm, orc, k):
     n, ppc, fo, pusher, d, dt, _, _ = RUNS[k]
     species, E, B = random_state(orc, n, ppc, seed=700 + k, d=d)
     P = ppm.make_params(n=n, d=d, dt=dt, shape_order=3, field_order=fo, pusher=pusher,
-                        precision=ppm.PP_PREC_FP32_SPLIT, relax_tol=1e-14, relax_max_iter=200)
+                        precision=ppm.PP_PREC_FP32_SPLIT, relax_tol=1e-14, relax_max_iter=200,
+                        current_scheme=ppm.PP_CURRENT_DIRECT if k in DIRECT_RUNS else ppm.PP_CURRENT_CC)
     return ppm.Run(P, _split_species(species, n, 3), E=E, B=B)
 
 
@@ -135,6 +139,13 @@ def test_batch_rejects_what_it_cannot_batch(ppm, orc):
         rf = ppm.Run(Pf, _split_species(species, (16, 16, 1), 3), E=E, B=B)
         with pytest.raises(ppm.PPError):
             ppm.pp_batch_add(batch, rf.handle)
+        # a run with Gauss-law filter passes
+        species, E, B = random_state(orc, (8, 8, 8), 2, seed=6)
+        Pg = ppm.make_params(n=(8, 8, 8), shape_order=3, field_order=2, precision=ppm.PP_PREC_FP32_SPLIT,
+                             current_scheme=ppm.PP_CURRENT_DIRECT, gauss_filter_passes=2)
+        rg = ppm.Run(Pg, _split_species(species, (8, 8, 8), 3), E=E, B=B)
+        with pytest.raises(ppm.PPError):
+            ppm.pp_batch_add(batch, rg.handle)
         # capacity, duplicates, other weight order
         ra, rb = _make(ppm, orc, 0), _make(ppm, orc, 1)
         ppm.pp_batch_add(batch, ra.handle)

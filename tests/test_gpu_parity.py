@@ -223,6 +223,59 @@ def test_radiative_cooling_steps_match_oracle(ppm, orc, split):
     run.close()
 
 
+DIRECT_CASES = [((10, 8, 6), 3, 6, 0, False), ((9, 7, 5), 2, 2, 0, False), ((10, 8, 6), 3, 6, 3, False),
+                ((10, 8, 6), 3, 6, 0, True), ((12, 6, 1), 2, 4, 3, True)]
+
+
+@pytest.mark.parametrize("ci", range(len(DIRECT_CASES)), ids=[str(c) for c in DIRECT_CASES])
+def test_direct_current_and_gauss_filter_match_oracle(ppm, orc, ci):
+    # the direct current (eq. "jj2", no line solve) and the Gauss-law filter passes after the
+    # field step: three steps against the oracle (FP64 to 1e-12, split FP32 to its bars)
+    n, O, fo, passes, split = DIRECT_CASES[ci]
+    _say("direct current", DIRECT_CASES[ci])
+    species, E, B = random_state(orc, n, 3, seed=300 + ci, uth=0.3, nspecies=3, pair=False)
+    kw = dict(n=n, dt=0.4, shape_order=O, field_order=fo, relax_tol=1e-14, relax_max_iter=200)
+    if split:
+        species = _split_species(species, n, O)
+        ref_species = [dict(s, u=s["u64"]) for s in species]
+    else:
+        ref_species = species
+    ref = _orc_run(orc, orc.make_params(current_scheme=1, gauss_passes=passes, **kw), ref_species, E, B)
+    prec = ppm.PP_PREC_FP32_SPLIT if split else ppm.PP_PREC_FP64
+    run = ppm.Run(ppm.make_params(precision=prec, current_scheme=ppm.PP_CURRENT_DIRECT, gauss_filter_passes=passes,
+                                  **kw), species, E=E, B=B)
+    for step in range(3):
+        ref.step()
+        run.step()
+        Eg, Bg, Jg = run.fields()
+        if split:
+            assert rel_l2(Jg, ref.J) < 1e-5, step
+            assert rel_l2(Eg - E, ref.E - E) < 1e-5 and rel_l2(Bg - B, ref.B - B) < 1e-5, step
+        else:
+            assert rel_inf(Jg, ref.J) < 1e-12, step
+            assert rel_inf(Eg, ref.E) < 1e-12 and rel_inf(Bg, ref.B) < 1e-12, step
+        for s, sp in enumerate(ref.species):
+            g = _by_id(run.particles(s))
+            if split:
+                X = I.from_split(g["cell"], g["pos"], n)
+                assert np.max(np.abs(periodic_diff(X, sp["pos"], n))) < 1e-5, (step, s)
+            else:
+                assert np.max(np.abs(periodic_diff(g["pos"], sp["pos"], n))) < 1e-12, (step, s)
+    d = run.diagnostics(ppm.PP_DIAG_RHO)
+    assert d.flags == 0
+    if passes:
+        P = orc.make_params(**kw)
+        gauss_ref = np.max(np.abs(orc.div_down(P, ref.E) - ref.rho()))
+        assert d.gauss_max <= 1.01 * gauss_ref + 1e-6 * d.rho_ref
+    run.close()
+
+
+def test_scheme_and_filter_parameters_are_validated(ppm):
+    for kw in (dict(current_scheme=2), dict(gauss_filter_passes=-1), dict(gauss_filter_passes=65)):
+        with pytest.raises(ppm.PPError):
+            ppm.Run(ppm.make_params(n=(4, 4, 4), **kw), [])
+
+
 def test_radiative_cooling_parameter_is_validated(ppm):
     with pytest.raises(ppm.PPError):
         ppm.Run(ppm.make_params(n=(4, 4, 4), rad_tau=-1.0), [])
