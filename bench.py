@@ -426,6 +426,49 @@ def mmi_bench(args, torch, pp):
     return 0
 
 
+def kh_tile_unevenness(run, torch, pp, n, t=(8, 8)):
+    """Largest over mean particle count of the 8x8x1 tiles (all species), from the device
+    arrays of the current positions."""
+    nt0 = (n[0] + t[0] - 1) // t[0]
+    ntiles = nt0 * ((n[1] + t[1] - 1) // t[1])
+    counts = torch.zeros(ntiles, dtype=torch.int64, device=run.E.device)
+    for s in range(len(run.species)):
+        P = pp.pp_get_particles(run.handle, s)
+        cell = run._wrap_ptr(P.cell, P.n, None).to(torch.int64)
+        i, j = cell % n[0], (cell // n[0]) % n[1]
+        counts += torch.bincount((i // t[0]) + nt0 * (j // t[1]), minlength=ntiles)
+    return float(counts.max()) / float(counts.double().mean())
+
+
+def kh_long_run(run, torch, pp, n, npart, steps, window=50):
+    """The shear-flow run over ``steps`` steps: whole-step rate over windows at the start, the
+    middle and the end, tile unevenness, normalised Gauss residual and field energies there."""
+    out = []
+    marks = (0, steps // 2, steps - window)
+    done = 0
+    for m in marks:
+        while done < m:
+            run.step()
+            done += 1
+            if done % 500 == 0:
+                torch.cuda.synchronize()
+                log(f"[kh] step {done}/{steps}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(window):
+            run.step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        done += window
+        d = run.diagnostics(pp.PP_DIAG_RHO | pp.PP_DIAG_FIELDS)
+        rec = dict(steps=[m, m + window], updates_per_s=npart * window / wall, ms_per_step=1e3 * wall / window,
+                   tile_max_over_mean=kh_tile_unevenness(run, torch, pp, n), gauss_rel=d.gauss_max / d.rho_ref,
+                   field_E=d.field_E, field_B=d.field_B, flags=d.flags)
+        log(f"[kh] {rec}")
+        out.append(rec)
+    return out
+
+
 def kh_bench(args, torch, pp):
     """Kelvin-Helmholtz shear layers: 1024x512x1 cells, electrons and ions (mass ratio 25),
     64 particles per cell each (67,108,864 particles), bulk flows +-0.2c, u_th = 0.02c,
@@ -454,10 +497,12 @@ def kh_bench(args, torch, pp):
                            relax_tol=1e-8 if split else 1e-14, relax_max_iter=100)
         run = pp.Run(P, species, with_id=False)
         del cells, offs, us
+        key = "fp32_split" if split else "fp64_plain"
+        if split and args.kh_steps > 0:
+            res["long_run"] = kh_long_run(run, torch, pp, n, 2 * npart, args.kh_steps)
         steps = args.steps if split else max(1, args.fp64_steps)
         wall, gpd_ms = time_steps(run, torch, steps, args.warmup if split else 1)
         d = run.diagnostics(pp.PP_DIAG_MOMENTS | pp.PP_DIAG_FIELDS)
-        key = "fp32_split" if split else "fp64_plain"
         res[key] = dict(updates_per_s=2 * npart * steps / wall, ms_per_step=1e3 * wall / steps,
                         gpd_updates_per_s=2 * npart / (gpd_ms * 1e-3), flags=d.flags)
         log(f"[kh] {key}: {res[key]}")
@@ -568,6 +613,8 @@ def main(argv=None):
     ap.add_argument("--mmi-tp", type=float, default=0.01,
                     help="mmi: background temperature (m_e c^2); the default reads the paper's 0.1 as u_th")
     ap.add_argument("--grid-x", type=int, default=128, help="two-stream: cells along the beams")
+    ap.add_argument("--kh-steps", type=int, default=0,
+                    help="kh: also run this many steps, timing windows at the start, middle and end")
     ap.add_argument("--ts-steps", type=int, default=2000, help="two-stream: steps")
     ap.add_argument("--save-history", default="", help="two-stream: save the E_x energy history to PATH_<form>.npz")
     ap.add_argument("--requests", type=int, default=256)
