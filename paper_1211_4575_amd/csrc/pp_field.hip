@@ -226,6 +226,83 @@ __global__ void __launch_bounds__(FIELD_BS) k_field_batch(const FieldDesc* __res
     field_phase(T[r], b - prefix[r], phase, k);
 }
 
+// Relaxation sweep, tiled (single-run path).  A block owns a 32 x 8 column of cells in x-y
+// and marches over up to RX_ZC planes in z.  Each thread keeps the 2R+1 values of its own
+// column around the current plane in registers (the z taps of the Laplacian) and the block
+// stages the current plane of the tile plus an R-wide x-y ring in LDS (the x and y taps), so
+// each value of the input comes from memory about once per plane instead of once per tap.
+// The arithmetic and the order of the sums are those of relax_body, so both give the same
+// bits (the batched path keeps relax_body).
+constexpr int RX_TX = 32, RX_TY = 8, RX_ZC = 32;
+
+template <int R>
+__global__ void __launch_bounds__(256) k_relax_tiled(FieldDesc D, int k) {
+    constexpr int W = RX_TX + 2 * R, H = RX_TY + 2 * R;
+    __shared__ double pl[W * H];
+    const FieldGeom& G = D.G;
+    const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
+    const int nbx = (n0 + RX_TX - 1) / RX_TX, nby = (n1 + RX_TY - 1) / RX_TY;
+    int b = blockIdx.x;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nby;
+    const int bz = b / nby;
+    const int i0 = bx * RX_TX, j0 = by * RX_TY, z0 = bz * RX_ZC;
+    const int z1 = z0 + RX_ZC < n2 ? z0 + RX_ZC : n2;
+    const int tx = threadIdx.x % RX_TX, ty = threadIdx.x / RX_TX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool valid = i < n0 && j < n1;
+    const int iw = nbw(i0, tx, n0, 1), jw = nbw(j0, ty, n1, 1);  // loads of idle threads wrap
+    const int m = D.sweeps;
+    double* out = ((m - k) % 2 == 0) ? D.B : D.Bw;
+    const double* in = k == 1 ? D.Bn : (((m - k + 1) % 2 == 0) ? D.B : D.Bw);
+    const double* prev = k <= 2 ? D.Bn : out;
+    const double w = D.omega[k];
+    const int nc = (int)G.nc;
+    for (int c = 0; c < 3; ++c) {
+        const double* x = in + c * G.nc;
+        double q[2 * R + 1];
+#pragma unroll
+        for (int t = 0; t <= 2 * R; ++t) q[t] = x[lin(G, iw, jw, nbw(z0, t - R, n2, G.small))];
+        for (int kz = z0; kz < z1; ++kz) {
+            __syncthreads();  // the previous plane's LDS reads are done
+            pl[(ty + R) * W + tx + R] = q[R];
+            for (int h = threadIdx.x; h < W * H; h += 256) {
+                const int a = h % W, bb = h / W;
+                if (a >= R && a < R + RX_TX && bb >= R && bb < R + RX_TY) continue;  // interior
+                pl[h] = x[lin(G, nbw(i0, a - R, n0, 1), nbw(j0, bb - R, n1, 1), kz)];
+            }
+            __syncthreads();
+            if (valid) {
+                const int qq = lin(G, i, j, kz);
+                double sl = 0.0;
+#pragma unroll
+                for (int o = -R; o <= R; ++o) {
+                    sl += G.L[0][o + R] * pl[(ty + R) * W + tx + R + o];
+                    sl += G.L[1][o + R] * pl[(ty + R + o) * W + tx + R];
+                    sl += G.L[2][o + R] * q[R + o];
+                }
+                const double xq = q[R];
+                const double Ax = xq - D.al2s * sl;
+                const double y = xq + (D.R[c * nc + qq] - Ax) * D.gdiag;
+                const double p = prev[c * nc + qq];
+                out[c * nc + qq] = p + w * (y - p);
+            }
+            if (kz + 1 < z1) {
+#pragma unroll
+                for (int t = 0; t < 2 * R; ++t) q[t] = q[t + 1];
+                q[2 * R] = x[lin(G, iw, jw, nbw(kz + 1, R, n2, G.small))];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+static int64_t relax_tiled_blocks(const FieldGeom& G) {
+    return (int64_t)((G.n[0] + RX_TX - 1) / RX_TX) * ((G.n[1] + RX_TY - 1) / RX_TY) *
+           ((G.n[2] + RX_ZC - 1) / RX_ZC);
+}
+
 static void fd_coeffs(int order, double a[3]) {
     a[0] = a[1] = a[2] = 0.0;
     if (order == 2) {
@@ -401,7 +478,15 @@ hipError_t launch_field_step(pp_run* r) {
     const dim3 grid((unsigned)blocks_of(D.G));
     hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_COPY, 0);
     hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_RHS, 0);
-    for (int k = 1; k <= D.sweeps; ++k) hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_JACOBI, k);
+    const dim3 rgrid((unsigned)relax_tiled_blocks(D.G));
+    for (int k = 1; k <= D.sweeps; ++k) {
+        if (D.G.R == 5)
+            hipLaunchKernelGGL(k_relax_tiled<5>, rgrid, dim3(256), 0, r->stream, D, k);
+        else if (D.G.R == 3)
+            hipLaunchKernelGGL(k_relax_tiled<3>, rgrid, dim3(256), 0, r->stream, D, k);
+        else
+            hipLaunchKernelGGL(k_relax_tiled<1>, rgrid, dim3(256), 0, r->stream, D, k);
+    }
     hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_UPDATE_E, 0);
     return hipGetLastError();
 }
