@@ -40,6 +40,8 @@ typedef struct {
     int32_t current_scheme; /* 0 = charge-conserving (Esirkepov), 1 = direct     */
                           /* (eq. "jj2" at the time-centred position)            */
     int32_t gauss_passes; /* passes of the Gauss-law filter after the field step */
+    int32_t time_order;   /* 2: leapfrog; 4: Forest-Ruth composition (whole-run  */
+                          /* driver, orc.py); the kernels here take one substep */
 } orc_params;
 
 /* ------------------------------------------------------------------ */
@@ -327,8 +329,18 @@ void orc_deposit_direct(const orc_params* P, double q, double w, const double X[
 /* pos and u are SoA: pos[d*n + p].  Returns a bit set: 1 = a particle   */
 /* moved one cell or more along some axis, 2 = non-finite state.         */
 /* ------------------------------------------------------------------ */
+int orc_step_species_kd(const orc_params* P, double kick, double q, double m, double w, int64_t n, double* pos,
+                        double* u, const double* E, const double* B, double* J);
+
 int orc_step_species(const orc_params* P, double q, double m, double w, int64_t n, double* pos, double* u,
                      const double* E, const double* B, double* J) {
+    return orc_step_species_kd(P, P->dt, q, m, w, n, pos, u, E, B, J);
+}
+
+/* The same with a momentum update (kick) over `kick` and the drift, current and position
+ * update over P->dt: one substep of a composition scheme. */
+int orc_step_species_kd(const orc_params* P, double kick, double q, double m, double w, int64_t n, double* pos,
+                        double* u, const double* E, const double* B, double* J) {
     int flags = 0;
     const double c = P->c;
     for (int64_t p = 0; p < n; ++p) {
@@ -338,7 +350,7 @@ int orc_step_species(const orc_params* P, double q, double m, double w, int64_t 
             up[d] = u[d * n + p];
         }
         orc_gather(P, E, B, X0, Ep, Bp);
-        orc_push_rad(P->pusher, q, m, P->dt, c, P->rad_tau, Ep, Bp, up);
+        orc_push_rad(P->pusher, q, m, kick, c, P->rad_tau, Ep, Bp, up);
         double g = sqrt(1.0 + dot3(up, up) / (c * c));
         for (int d = 0; d < 3; ++d) {
             X1[d] = X0[d] + P->dt * up[d] / (g * P->d[d]);

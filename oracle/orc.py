@@ -46,12 +46,13 @@ class Params(ctypes.Structure):
         ("rad_tau", ctypes.c_double),
         ("current_scheme", ctypes.c_int32),
         ("gauss_passes", ctypes.c_int32),
+        ("time_order", ctypes.c_int32),
     ]
 
 
 def make_params(n=(16, 16, 16), d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shape_order=2,
                 field_order=2, alpha=0.55, pusher=0, relax_tol=1e-14, relax_max_iter=200,
-                rho_background=0.0, rad_tau=0.0, current_scheme=0, gauss_passes=0) -> Params:
+                rho_background=0.0, rad_tau=0.0, current_scheme=0, gauss_passes=0, time_order=2) -> Params:
     p = Params()
     p.n[:] = [int(v) for v in n]
     p.d[:] = [float(v) for v in d]
@@ -62,7 +63,27 @@ def make_params(n=(16, 16, 16), d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shap
     p.rho_background = float(rho_background)
     p.rad_tau = float(rad_tau)
     p.current_scheme, p.gauss_passes = int(current_scheme), int(gauss_passes)
+    p.time_order = int(time_order)
     return p
+
+
+# Fourth-order composition (Forest & Ruth 1990; Candy & Rozmus 1991; Yoshida 1990): with
+# theta = 1/(2 - 2^(1/3)) the position form D(th/2) K(th) D((1-th)/2) K(1-2th) D((1-th)/2)
+# K(th) D(th/2) keeps every position at the middle of the momentum interval of its kick.
+# Merging the trailing and leading half drifts of consecutive steps gives three leapfrog
+# substeps per step, (kick, drift) = (th, (1-th)/2), (1-2th, (1-th)/2), (th, th) times dt,
+# with the positions and fields of the state a drift of th dt/2 ahead of the momenta.
+FR_THETA = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+FR_SUBSTEPS = ((FR_THETA, 0.5 * (1.0 - FR_THETA)), (1.0 - 2.0 * FR_THETA, 0.5 * (1.0 - FR_THETA)),
+               (FR_THETA, FR_THETA))
+
+
+def substep_params(P: Params, drift: float) -> Params:
+    """A copy of P whose time step is the drift of a substep."""
+    Q = Params()
+    ctypes.pointer(Q)[0] = P
+    Q.dt = drift
+    return Q
 
 
 _lib = None
@@ -88,6 +109,9 @@ def lib():
         L.orc_gauss_kappa.restype = ctypes.c_double
         L.orc_gauss_kappa.argtypes = [_P]
         L.orc_gauss_filter.argtypes = [_P, _D, _D, ctypes.c_int]
+        L.orc_step_species_kd.restype = ctypes.c_int
+        L.orc_step_species_kd.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_int64, _D, _D, _D, _D, _D]
         L.orc_step_species.restype = ctypes.c_int
         L.orc_step_species.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_int64, _D, _D, _D, _D, _D]
@@ -183,6 +207,13 @@ def deposit_current(P: Params, q: float, w: float, X0, X1, J: np.ndarray | None 
 
 
 # -- whole-array steps -----------------------------------------------------------------------
+def step_species_kd(P: Params, kick, q, m, w, pos: np.ndarray, u: np.ndarray, E, B, J) -> int:
+    """Steps 1-3 with the momentum update over ``kick`` and the drift over P.dt."""
+    n = pos.shape[1]
+    return lib().orc_step_species_kd(ctypes.byref(P), kick, q, m, w, n, _ptr(pos), _ptr(u), _ptr(E), _ptr(B),
+                                     _ptr(J))
+
+
 def step_species(P: Params, q, m, w, pos: np.ndarray, u: np.ndarray, E, B, J) -> int:
     """Steps 1-3 for one species, in place on pos/u, accumulating into J."""
     n = pos.shape[1]
@@ -278,22 +309,31 @@ class Run:
         self.flags = 0
         self.relax = (0, 0.0)
 
-    def particles_step(self):
+    def particles_step(self, P=None, kick=None):
+        P = self.P if P is None else P
+        kick = P.dt if kick is None else kick
         self.J[:] = 0.0
         for s in self.species:
-            self.flags |= step_species(self.P, s["q"], s["m"], s["w"], s["pos"], s["u"], self.E, self.B, self.J)
-        if self.P.current_scheme == 0:  # the line solve belongs to the charge-conserving current
-            current_high_order(self.P, self.J)
+            self.flags |= step_species_kd(P, kick, s["q"], s["m"], s["w"], s["pos"], s["u"], self.E, self.B, self.J)
+        if P.current_scheme == 0:  # the line solve belongs to the charge-conserving current
+            current_high_order(P, self.J)
 
-    def fields_step(self):
-        self.relax = field_step(self.P, self.E, self.B, self.J)
-        if self.P.gauss_passes > 0:  # Gauss-law filter with the charge density of x^{n+1}
-            r = np.zeros(_scal(self.P))
+    def fields_step(self, P=None):
+        P = self.P if P is None else P
+        self.relax = field_step(P, self.E, self.B, self.J)
+        if P.gauss_passes > 0:  # Gauss-law filter with the charge density of x^{n+1}
+            r = np.zeros(_scal(P))
             for s in self.species:
-                deposit_rho(self.P, s["q"], s["w"], s["pos"], r)
-            gauss_filter(self.P, self.E, r, self.P.gauss_passes)
+                deposit_rho(P, s["q"], s["w"], s["pos"], r)
+            gauss_filter(P, self.E, r, P.gauss_passes)
 
     def step(self):
+        if self.P.time_order == 4:  # three leapfrog substeps (FR_SUBSTEPS)
+            for kick, drift in FR_SUBSTEPS:
+                Q = substep_params(self.P, drift * self.P.dt)
+                self.particles_step(Q, kick * self.P.dt)
+                self.fields_step(Q)
+            return
         self.particles_step()
         self.fields_step()
 

@@ -134,3 +134,57 @@ def test_synchrotron_cooling_in_a_uniform_field(orc, pusher):
         assert abs(u[2]) < 1e-14  # stays in the plane
         errs.append(abs(np.linalg.norm(u) / exact - 1))
     assert errs[1] < 2e-3 and errs[0] / errs[1] > 1.8
+
+
+# ---- fourth-order time integration (Sec. III.A, symmetric composition) ------------------------
+def _gyro(t, B0=1.0, um=1.0, x0=8.0, y0=8.0, z0=8.0, phi0=0.3):
+    # electron (q = -1, m = 1) in B0 z: u turns at w = B0/gamma, radius |u|/B0
+    g = math.sqrt(1 + um * um)
+    w = B0 / g
+    ph = phi0 + w * t
+    u = np.array([um * math.cos(ph), um * math.sin(ph), 0.0])
+    r = um / B0
+    x = np.array([x0 + r * math.sin(ph), y0 - r * math.cos(ph), z0])
+    return x, u
+
+
+def _gyro_error(orc, h, order, T=4.0):
+    # leapfrog: x at t, u at t - h/2.  Composition: the state's positions are a drift of
+    # theta h / 2 (at the momentum's velocity) ahead of the momenta, x + (theta h/2) v
+    th = orc.FR_THETA
+    if order == 4:
+        x, u = _gyro(0.0)
+        x = x + 0.5 * th * h * u / math.sqrt(1 + u @ u)
+    else:
+        x, _ = _gyro(0.0)
+        _, u = _gyro(-h / 2)
+    n = (16, 16, 16)
+    P = orc.make_params(n=n, dt=h, shape_order=3, field_order=2, time_order=order, relax_tol=1e-15,
+                        relax_max_iter=400)
+    B = np.zeros((3, 16, 16, 16))
+    B[2] = 1.0
+    run = orc.Run(P, [dict(q=-1.0, m=1.0, w=1e-15, pos=x.reshape(3, 1), u=u.reshape(3, 1))], B=B)
+    steps = int(round(T / h))
+    for _ in range(steps):
+        run.step()
+    xg, ug = run.species[0]["pos"][:, 0], run.species[0]["u"][:, 0]
+    if order == 4:
+        xg = xg - 0.5 * th * h * ug / math.sqrt(1 + ug @ ug)
+        xe, ue = _gyro(T)
+    else:
+        xe, _ = _gyro(T)
+        _, ue = _gyro(T - h / 2)
+    return max(np.max(np.abs(xg - xe)), np.max(np.abs(ug - ue)))
+
+
+def test_fourth_order_composition_converges_at_fourth_order(orc):
+    # a test particle gyrating in a uniform B through whole runs (fields advanced every
+    # substep): the leapfrog error falls 4x per halving of the step, the composition's 16x
+    th = orc.FR_THETA
+    assert abs(sum(k for k, _ in orc.FR_SUBSTEPS) - 1) < 1e-15 and abs(sum(d for _, d in orc.FR_SUBSTEPS) - 1) < 1e-15
+    assert abs(2 * th ** 3 + (1 - 2 * th) ** 3) < 1e-14  # the third-order condition of the triple jump
+    e2 = [_gyro_error(orc, h, 2) for h in (0.2, 0.1)]
+    e4 = [_gyro_error(orc, h, 4) for h in (0.2, 0.1)]
+    assert 3.5 < e2[0] / e2[1] < 4.5, e2
+    assert 14 < e4[0] / e4[1] < 18, e4
+    assert e4[1] < e2[1] / 50
