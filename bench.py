@@ -34,7 +34,7 @@ def log(*a):
 
 
 def make_pair_mj_run(pp, ind, torch, n, ppc, theta, split, with_id=False, rad_tau=0.0, current_scheme=0,
-                     gauss_passes=0):
+                     gauss_passes=0, time_order=2):
     """Build a pp.Run for the pair-plasma workload with particles generated on the device.
     Returns the run and the number of particles per species."""
     npart = n[0] * n[1] * n[2] * ppc
@@ -55,7 +55,7 @@ def make_pair_mj_run(pp, ind, torch, n, ppc, theta, split, with_id=False, rad_ta
     params = pp.make_params(n, shape_order=3, field_order=6, dt=0.4, alpha=0.55,
                             precision=pp.PP_PREC_FP32_SPLIT if split else pp.PP_PREC_FP64,
                             relax_tol=1e-8 if split else 1e-14, relax_max_iter=100, rad_tau=rad_tau,
-                            current_scheme=current_scheme, gauss_filter_passes=gauss_passes)
+                            current_scheme=current_scheme, gauss_filter_passes=gauss_passes, time_order=time_order)
     species = []
     for s, q in enumerate((-1.0, 1.0)):
         sp = dict(q=q, m=1.0, w=1.0 / ppc, u=us[s])
@@ -601,6 +601,8 @@ def main(argv=None):
     ap.add_argument("--current", choices=("cc", "direct"), default="cc",
                     help="current scheme: charge-conserving (default) or direct")
     ap.add_argument("--gauss-passes", type=int, default=0, help="Gauss-law filter passes per step")
+    ap.add_argument("--time-order", type=int, choices=(2, 4), default=2,
+                    help="2: leapfrog; 4: fourth-order composition (three substeps per step)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--workload", choices=("pair_mj", "serving", "two_stream", "kh", "mmi"), default="pair_mj")
@@ -657,7 +659,7 @@ def main(argv=None):
     log(f"[bench] FP32 split: generating {n} x {args.ppc} ppc x 2 species on the device")
     scheme = pp.PP_CURRENT_DIRECT if args.current == "direct" else pp.PP_CURRENT_CC
     run, npart = make_pair_mj_run(pp, ind, torch, n, args.ppc, 1.0, split=True, rad_tau=args.rad_tau,
-                                  current_scheme=scheme, gauss_passes=args.gauss_passes)
+                                  current_scheme=scheme, gauss_passes=args.gauss_passes, time_order=args.time_order)
     npart *= 2  # electrons and positrons
     log(f"[bench] FP32 split: {npart} particles; warmup {args.warmup}, timing {args.steps} steps")
     wall, gpd_ms = time_steps(run, torch, args.steps, args.warmup)
@@ -683,7 +685,7 @@ def main(argv=None):
     if not args.no_fp64:
         log(f"[bench] FP64 plain: generating")
         run, _ = make_pair_mj_run(pp, ind, torch, n, args.ppc, 1.0, split=False, rad_tau=args.rad_tau,
-                                  current_scheme=scheme, gauss_passes=args.gauss_passes)
+                                  current_scheme=scheme, gauss_passes=args.gauss_passes, time_order=args.time_order)
         log(f"[bench] FP64 plain: warmup 1, timing {args.fp64_steps} steps")
         wall64, gpd64_ms = time_steps(run, torch, args.fp64_steps, 1)
         fp64 = dict(value=npart * args.fp64_steps / wall64, ms_per_step=1e3 * wall64 / args.fp64_steps,
@@ -732,7 +734,7 @@ def main(argv=None):
         "config": {"workload": f"pair plasma {n[0]}x{n[1]}x{n[2]}, {args.ppc} ppc/species, Maxwell-Juttner kT=mc^2, "
                                f"cubic weights, 6th-order fields, FP32 split positions",
                    "particles": npart, "step": "gather/push/deposit + line solve + sort + field step", "rad_tau": args.rad_tau,
-                   "current": args.current, "gauss_passes": args.gauss_passes,
+                   "current": args.current, "gauss_passes": args.gauss_passes, "time_order": args.time_order,
                    "gpd_updates_per_s": gpd_rate, "fp64_plain": fp64,
                    "fp32_over_fp64": (value / fp64["value"]) if fp64 else None, "diagnostics": diag32},
         "roofline": roofline,

@@ -113,6 +113,15 @@ typedef struct pp_params {
                             * 1 / max |K|^2 over the grid's wave numbers (K the symbol of
                             * the field-order first derivative).  Runs with passes > 0 are
                             * not accepted by pp_batch_add.                           */
+    int32_t time_order;    /* 2 (leapfrog, default) or 4: pp_step composes three
+                            * leapfrog substeps (Sec. III.A, symmetric fourth-order
+                            * integrator; the Forest-Ruth position form with theta =
+                            * 1/(2 - 2^(1/3)): (kick, drift) = (theta, (1-theta)/2),
+                            * (1-2 theta, (1-theta)/2), (theta, theta) times dt, fields
+                            * advanced with the drifts).  The state's positions and fields
+                            * are then a drift of theta dt/2 ahead of the momenta (load
+                            * x + theta dt/2 v for synchronised x, u).  Order 4 needs
+                            * theta c dt < min(d) and is not accepted by pp_batch_add.   */
 } pp_params;
 
 /* Caller-owned FP64 mesh (device pointers, 3*ncell doubles each). */
@@ -129,7 +138,8 @@ typedef struct pp_mesh {
  *                      lo = -1/2 for shape_order 2, 0 for shape_order 3.  A loader
  *                      gives i = floor(X - lo) mod n0 (offset in [lo, lo + 1): the
  *                      nearest node for quadratic, the node below for cubic weights).
- *                      The push keeps a particle whose last displacement, repeated, would
+ *                      The push keeps a particle whose last displacement, repeated (times
+ *                      the ratio of the next drift to this one in a composed step), would
  *                      cross the lower face of its cell in the cell below (offset in
  *                      [lo + 1, lo + 2)), so that the stencils of the next step line up.
  *  u[d]: proper velocity (double for FP64, float for FP32_SPLIT).
@@ -202,6 +212,15 @@ pp_status pp_field_step(pp_run* run);
  * particle arrays are sorted by cell between steps 3 and 4).  The order inside a
  * cell is unspecified.  The current and alternate buffers swap roles. */
 pp_status pp_sort_particles(pp_run* run, int32_t s);
+
+/* One whole time step in the run's time order (Sec. III step list): for time_order 2,
+ * pp_gather_push_deposit, pp_sort_particles(run, -1) and pp_field_step; for time_order 4,
+ * the three substeps of the composition (pp_params.time_order), each a particle update
+ * with its own kick and drift, a sort and a field step over its drift.  The three calls
+ * above, used one by one, always take one leapfrog step of dt.  After a composed step
+ * the continuity residual of pp_diagnostics is not defined (NaN): J is that of the last
+ * substep.  Errors as the three calls. */
+pp_status pp_step(pp_run* run);
 
 /* FP64 diagnostics selected by `what` (PP_DIAG_* bits) written to *out (host
  * memory).  Also reports and clears the device flag word.  Synchronises the

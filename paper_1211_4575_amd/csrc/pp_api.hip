@@ -41,6 +41,7 @@ static pp_status validate(const pp_params* p) {
     if (p->rad_tau < 0.0) return PP_E_ARG;
     if (p->current_scheme != PP_CURRENT_CC && p->current_scheme != PP_CURRENT_DIRECT) return PP_E_ARG;
     if (p->gauss_filter_passes < 0 || p->gauss_filter_passes > PP_MAX_GAUSS_PASSES) return PP_E_ARG;
+    if (p->time_order != 2 && p->time_order != 4) return PP_E_ARG;
     if (!finite_pos(p->dt) || !finite_pos(p->c) || !finite_pos(p->eps0)) return PP_E_ARG;
     if (p->shape_order != 2 && p->shape_order != 3) return PP_E_ARG;
     if (p->field_order != 2 && p->field_order != 4 && p->field_order != 6) return PP_E_ARG;
@@ -51,6 +52,7 @@ static pp_status validate(const pp_params* p) {
     double dmin = p->d[0];
     for (int d = 1; d < 3; ++d) dmin = p->d[d] < dmin ? p->d[d] : dmin;
     if (!(p->c * p->dt < dmin)) return PP_E_CFL;
+    if (p->time_order == 4 && !(FR_THETA * p->c * p->dt < dmin)) return PP_E_CFL;  // the longest drift
     return PP_OK;
 }
 
@@ -94,7 +96,7 @@ static void release(pp_run* r) {
     f(r->Jq);
     f(r->tile_max);
     f(r->qscale);
-    f(r->omega);
+    for (auto& S : r->rs) f(S.omega);
     f(r->rounds);
     for (int s = 0; s < PP_MAX_SPECIES; ++s) {
         f(r->sp[s].cell_cnt);
@@ -150,7 +152,7 @@ static size_t internal_bytes(const pp_params* p, const Geom& g, int64_t nmax, in
     b += 2 * nc * sizeof(double);                                          // rho, rho_prev
     b += nb * sizeof(int32_t) + (size_t)scan_tmp_size(g.nbins + 1) * sizeof(int32_t);
     b += sizeof(int32_t) + ((size_t)diag_acc_count() + 8) * sizeof(double);
-    b += ((size_t)p->relax_max_iter + 2) * sizeof(double);  // relaxation weights
+    b += (p->time_order == 4 ? 3 : 1) * ((size_t)p->relax_max_iter + 2) * sizeof(double);  // relaxation weights
     if (p->precision == PP_PREC_FP32_SPLIT) {
         b += n3 * sizeof(long long) + PP_MAX_SPECIES * sizeof(int32_t) + sizeof(double);
         b += 2 * (size_t)nmax * sizeof(int32_t);                           // sort scratch
@@ -211,7 +213,8 @@ pp_status pp_create(const pp_params* params, const pp_mesh* mesh, void* hip_stre
     okk = okk && dmalloc(&r->rho, (size_t)g.ncell) && dmalloc(&r->rho_prev, (size_t)g.ncell);
     okk = okk && dmalloc(&r->sort_cursor, (size_t)g.nbins) && dmalloc(&r->scan_tmp, (size_t)scan_tmp_size(g.nbins + 1));
     okk = okk && dmalloc(&r->flags, 1) && dmalloc(&r->dacc, (size_t)diag_acc_count() + 8);
-    okk = okk && dmalloc(&r->omega, (size_t)params->relax_max_iter + 2);
+    r->nrs = params->time_order == 4 ? 3 : 1;
+    for (int k = 0; k < r->nrs; ++k) okk = okk && dmalloc(&r->rs[k].omega, (size_t)params->relax_max_iter + 2);
     if (params->precision == PP_PREC_FP32_SPLIT) {
         okk = okk && dmalloc(&r->rounds, (size_t)g.ntiles * SORT_RCAP);
         okk = okk && dmalloc(&r->Jq, n3) && dmalloc(&r->tile_max, PP_MAX_SPECIES) && dmalloc(&r->qscale, 1) &&
@@ -364,6 +367,31 @@ pp_status pp_field_step(pp_run* r) {
         if (!ok(e, "gauss_filter")) return PP_E_HIP;
     }
     return PP_OK;
+}
+
+pp_status pp_step(pp_run* r) {
+    if (!r) return PP_E_ARG;
+    if (r->p.time_order != 4) {
+        pp_status st = pp_gather_push_deposit(r);
+        if (st == PP_OK) st = pp_sort_particles(r, -1);
+        if (st == PP_OK) st = pp_field_step(r);
+        return st;
+    }
+    pp_status st = PP_OK;
+    for (int k = 0; k < 3 && st == PP_OK; ++k) {
+        use_relax_set(r, k < 2 ? 1 : 2);  // sets 1 and 2 hold the drifts (1-theta)/2 dt and theta dt
+        r->dt_kick = FR_KICK[k] * r->p.dt;
+        r->drift_ratio = FR_DRIFT[(k + 1) % 3] / FR_DRIFT[k];
+        st = pp_gather_push_deposit(r);
+        if (st == PP_OK) st = pp_sort_particles(r, -1);
+        if (st == PP_OK) st = pp_field_step(r);
+    }
+    use_relax_set(r, 0);
+    r->dt_kick = r->p.dt;
+    r->drift_ratio = 1.0;
+    r->step -= 2;             // one step, three particle substeps
+    r->rho_prev_step = -1;    // J is the last substep's: no continuity check across the step
+    return st;
 }
 
 pp_status pp_sort_particles(pp_run* r, int32_t s) {

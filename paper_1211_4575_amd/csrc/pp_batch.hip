@@ -93,6 +93,7 @@ pp_status pp_batch_add(pp_batch* b, pp_run* r) {
     if (r->p.precision != PP_PREC_FP32_SPLIT || !gpd32_batchable(r)) return PP_E_ARG;
     if (r->stream != b->stream) return PP_E_ARG;
     if (r->p.gauss_filter_passes > 0) return PP_E_ARG;  // the filter has no batched form
+    if (r->p.time_order != 2) return PP_E_ARG;          // the batch steps leapfrog steps
     if (!b->runs.empty() && b->runs[0]->p.shape_order != r->p.shape_order) return PP_E_ARG;
     for (int s = 0; s < PP_MAX_SPECIES; ++s)
         if (r->sp[s].active && !r->sp[s].sorted) return PP_E_STATE;

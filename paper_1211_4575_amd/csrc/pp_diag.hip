@@ -537,7 +537,7 @@ hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out) {
         if (g > 4096) g = 4096;
         hipLaunchKernelGGL(k_residuals, dim3((unsigned)g), dim3(bs), 0, r->stream, G, (const double*)r->mesh.E,
                            (const double*)r->mesh.J, (const double*)r->mesh.B, (const double*)r->rho,
-                           (const double*)r->rho_prev, r->p.rho_background, 1.0 / r->p.eps0, r->p.dt, want_rho ? 1 : 0,
+                           (const double*)r->rho_prev, r->p.rho_background, 1.0 / r->p.eps0, r->dt_drift, want_rho ? 1 : 0,
                            have_prev ? 1 : 0, want_divb ? 1 : 0, r->dacc + ACC_GAUSS);
     }
     e = hipGetLastError();

@@ -362,6 +362,8 @@ int64_t field_blocks(const pp_run* r) { return blocks_of(make_geom(r)); }
 // r = (g1 - g0) / (2 - g0 - g1), and accelerated by Chebyshev semi-iteration (Golub and
 // Varga 1961): after m sweeps the error is multiplied by at most 1 / T_m(1/r) (T_m the
 // Chebyshev polynomial), and m is the smallest count for which that is <= relax_tol.
+static hipError_t relax_setup(pp_run* r, double dt, pp_run::RelaxSet& S);
+
 hipError_t field_setup(pp_run* r) {
     double a[3];
     fd_coeffs(r->p.field_order, a);
@@ -380,39 +382,6 @@ hipError_t field_setup(pp_run* r) {
                 r->lap[d][(-m - mp + 1) + R] += cf;
             }
     }
-    const double s = r->p.c * r->p.c * r->p.dt * r->p.dt;
-    const double al2s = r->p.alpha * r->p.alpha * s;
-    double diag = 1.0, amax = 1.0;
-    for (int d = 0; d < 3; ++d) {
-        const int N = r->p.n[d];
-        double fold0 = 0.0;
-        for (int o = -R; o <= R; ++o)
-            if (((o % N) + N) % N == 0) fold0 += r->lap[d][o + R];
-        diag -= al2s * fold0;
-        double mn = 0.0;
-        for (int mm = 0; mm < N; ++mm) {
-            double k = 2.0 * M_PI * mm / N, sym = 0.0;
-            for (int o = -R; o <= R; ++o) sym += r->lap[d][o + R] * cos(o * k);
-            if (sym < mn) mn = sym;
-        }
-        amax -= al2s * mn;
-    }
-    r->diagA = diag;
-    const double g0 = 1.0 - amax / diag, g1 = 1.0 - 1.0 / diag;
-    r->jac_rho = fmax(fabs(g0), fabs(g1));
-    r->relax_gamma = 2.0 / (2.0 - g0 - g1);
-    const double rr = (g1 - g0) / (2.0 - g0 - g1);
-    r->relax_r = rr;
-    int sweeps = 1;
-    double bound = 0.0;
-    if (rr > 1e-300) {
-        const double ac = acosh(1.0 / rr);
-        for (sweeps = 1; sweeps < r->p.relax_max_iter; ++sweeps)
-            if (1.0 / cosh(sweeps * ac) <= r->p.relax_tol) break;
-        bound = 1.0 / cosh(sweeps * ac);
-    }
-    r->jac_sweeps = sweeps;
-    r->jac_bound = bound;
     // Gauss-law filter damping: 1 / max over the grid's wave numbers of sum_d K_d^2, K_d the
     // symbol (2/d) sum_m a_m sin((m - 1/2) k) of the field-order first derivative
     double kmax2 = 0.0;
@@ -429,6 +398,54 @@ hipError_t field_setup(pp_run* r) {
         kmax2 += best;
     }
     r->gauss_kappa = kmax2 > 0.0 ? 1.0 / kmax2 : 0.0;
+    // relaxation constants for each drift size the run steps with
+    const double drifts[3] = {r->p.dt, FR_DRIFT[0] * r->p.dt, FR_DRIFT[2] * r->p.dt};
+    for (int k = 0; k < r->nrs; ++k) {
+        hipError_t e = relax_setup(r, drifts[k], r->rs[k]);
+        if (e != hipSuccess) return e;
+    }
+    use_relax_set(r, 0);
+    r->dt_kick = r->dt_drift = r->p.dt;
+    return hipSuccess;
+}
+
+// Relaxation constants of one drift size dt (the operator depends on dt^2 only).
+static hipError_t relax_setup(pp_run* r, double dt, pp_run::RelaxSet& S) {
+    const int R = r->lap_r;
+    const double s = r->p.c * r->p.c * dt * dt;
+    const double al2s = r->p.alpha * r->p.alpha * s;
+    double diag = 1.0, amax = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        const int N = r->p.n[d];
+        double fold0 = 0.0;
+        for (int o = -R; o <= R; ++o)
+            if (((o % N) + N) % N == 0) fold0 += r->lap[d][o + R];
+        diag -= al2s * fold0;
+        double mn = 0.0;
+        for (int mm = 0; mm < N; ++mm) {
+            double k = 2.0 * M_PI * mm / N, sym = 0.0;
+            for (int o = -R; o <= R; ++o) sym += r->lap[d][o + R] * cos(o * k);
+            if (sym < mn) mn = sym;
+        }
+        amax -= al2s * mn;
+    }
+    S.drift = dt;
+    S.diagA = diag;
+    const double g0 = 1.0 - amax / diag, g1 = 1.0 - 1.0 / diag;
+    S.jac_rho = fmax(fabs(g0), fabs(g1));
+    S.gamma = 2.0 / (2.0 - g0 - g1);
+    const double rr = (g1 - g0) / (2.0 - g0 - g1);
+    S.r = rr;
+    int sweeps = 1;
+    double bound = 0.0;
+    if (rr > 1e-300) {
+        const double ac = acosh(1.0 / rr);
+        for (sweeps = 1; sweeps < r->p.relax_max_iter; ++sweeps)
+            if (1.0 / cosh(sweeps * ac) <= r->p.relax_tol) break;
+        bound = 1.0 / cosh(sweeps * ac);
+    }
+    S.sweeps = sweeps;
+    S.bound = bound;
     // omega_1 = 1, omega_2 = 1 / (1 - r^2/2), omega_{k+1} = 1 / (1 - r^2 omega_k / 4)
     const int n_om = r->p.relax_max_iter + 2;
     double* om = new (std::nothrow) double[n_om];
@@ -436,14 +453,26 @@ hipError_t field_setup(pp_run* r) {
     om[0] = 0.0;
     om[1] = 1.0;
     for (int k = 2; k < n_om; ++k) om[k] = k == 2 ? 1.0 / (1.0 - 0.5 * rr * rr) : 1.0 / (1.0 - 0.25 * rr * rr * om[k - 1]);
-    hipError_t e = hipMemcpy(r->omega, om, n_om * sizeof(double), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(S.omega, om, n_om * sizeof(double), hipMemcpyHostToDevice);
     delete[] om;
     return e;
 }
 
+void use_relax_set(pp_run* r, int k) {
+    const pp_run::RelaxSet& S = r->rs[k];
+    r->diagA = S.diagA;
+    r->jac_rho = S.jac_rho;
+    r->relax_gamma = S.gamma;
+    r->relax_r = S.r;
+    r->jac_sweeps = S.sweeps;
+    r->jac_bound = S.bound;
+    r->omega = S.omega;
+    r->dt_drift = S.drift;
+}
+
 void field_desc(const pp_run* r, FieldDesc* D) {
     D->G = make_geom(r);
-    const double c2 = r->p.c * r->p.c, dt = r->p.dt, s = c2 * dt * dt;
+    const double c2 = r->p.c * r->p.c, dt = r->dt_drift, s = c2 * dt * dt;
     const double al = r->p.alpha, be = 1.0 - al;
     const double mu0 = 1.0 / (r->p.eps0 * c2);
     D->E = r->mesh.E;

@@ -3,8 +3,9 @@
 // storage, Sec. V.B).  The offset is measured from the nearest node (lo = -1/2) for quadratic
 // weights and from the node below (lo = 0) for cubic weights and lies in [lo, lo + 1), so
 // that the centred support starts one node below the cell; a particle whose last
-// displacement, repeated, would take it across the lower face of its cell is kept in the
-// cell below with its offset in [lo + 1, lo + 2).  Then the current window of the next step
+// displacement, repeated (scaled by the ratio of the next drift to this one inside a
+// composed step), would take it across the lower face of its cell is kept in the cell
+// below with its offset in [lo + 1, lo + 2).  Then the current window of the next step
 // (old and new support) starts 2 nodes below the cell for almost every particle.
 // Particles are stored per tile in round-major order (see pp_sort.hip): 64 consecutive
 // particles sit in 64 different cells of the tile, so the 64 lanes of a wavefront touch 64
@@ -58,7 +59,9 @@ struct Gpd32Args {
     int64_t nc;
     int fe[3], ce[3];  // LDS extents (runtime-shape kernel)
     int flo[3], clo[3];
-    float dt;
+    float dt;   // drift: positions and current
+    float dtk;  // kick: momentum update (radiative cooling included)
+    float pred; // next drift / this drift: the next displacement expected from this one
     float inv_d[3];
     float ic;
     int pusher;
@@ -364,7 +367,7 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
                 push_boris<float>(S.h, A.ic, E, B, u);
             else
                 push_vay<float>(S.h, A.ic, E, B, u);
-            if (S.krad != 0.0f) rad_cool<float>(S.krad, A.dt, A.ic, um, u);
+            if (S.krad != 0.0f) rad_cool<float>(S.krad, A.dtk, A.ic, um, u);
 
             const float ig = rsqrtf(1.0f + dot(u, u) * A.ic * A.ic);
             const float uu[3] = {u.x, u.y, u.z};
@@ -488,7 +491,8 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
             }
 
             // renormalise: new cell and offset in [lo, lo + 1), or in [lo + 1, lo + 2) in the
-            // cell below when the same displacement again would cross the lower face
+            // cell below when the next displacement (this one times the ratio of the next drift
+            // to this one) would cross the lower face
             int nc3[3], shv[3];
             float fn[3];
             const int gc[3] = {org[0] + li, org[1] + lj, org[2] + lk};
@@ -506,7 +510,7 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
                     sh += 1.0f;
                 }
                 const float up = o + 1.0f;
-                if (o + dxs[d] < lo && up < lo + 2.0f) {
+                if (o + dxs[d] * A.pred < lo && up < lo + 2.0f) {
                     o = up;
                     sh -= 1.0f;
                 }
@@ -684,7 +688,7 @@ int gpd32_scale_e0(const pp_run* r) {
         const Species& S = r->sp[s];
         if (!S.active) continue;
         for (int d = 0; d < 3; ++d) {
-            const double f = fabs(S.q * S.w * r->p.d[d] / r->p.dt);
+            const double f = fabs(S.q * S.w * r->p.d[d] / r->dt_drift);
             fmax = f > fmax ? f : fmax;
         }
     }
@@ -714,7 +718,9 @@ void gpd32_fill_args(const pp_run* r, Gpd32Args* Ap) {
     }
     A.ntiles = r->g.ntiles;
     A.nc = r->g.ncell;
-    A.dt = (float)r->p.dt;
+    A.dt = (float)r->dt_drift;
+    A.dtk = (float)r->dt_kick;
+    A.pred = (float)r->drift_ratio;
     A.ic = (float)(1.0 / r->p.c);
     A.pusher = r->p.pusher;
     A.nsp = 0;
@@ -729,9 +735,9 @@ void gpd32_fill_args(const pp_run* r, Gpd32Args* Ap) {
         for (int d = 0; d < 3; ++d) {
             D.pos[d] = (float*)S.cur.pos[d];
             D.u[d] = (float*)S.cur.u[d];
-            D.fac[d] = -S.q * S.w * r->p.d[d] / r->p.dt;
+            D.fac[d] = -S.q * S.w * r->p.d[d] / r->dt_drift;
         }
-        D.h = (float)(S.q * r->p.dt / S.m);
+        D.h = (float)(S.q * r->dt_kick / S.m);
         D.krad = (float)(r->p.rad_tau * S.q * S.q / S.m);
         D.qw = S.q * S.w;
     }

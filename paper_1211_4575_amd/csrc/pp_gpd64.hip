@@ -10,7 +10,8 @@ namespace pp {
 struct Gpd64Args {
     int n[3];
     double d[3];      // cell size
-    double dt, ic;    // time step, 1/c
+    double dt, ic;    // drift time step (positions, current), 1/c
+    double dtk;       // kick time step (momentum update)
     double h;         // q dt / m
     double krad;      // radiative cooling constant rad_tau q^2 / m (0: off)
     double fac[3];    // -q w d_c / dt, current prefactor per component
@@ -86,7 +87,7 @@ __global__ void __launch_bounds__(256) k_gpd64(Gpd64Args A) {
         push_boris<double>(A.h, A.ic, E, B, u);
     else
         push_vay<double>(A.h, A.ic, E, B, u);
-    if (A.krad != 0.0) rad_cool<double>(A.krad, A.dt, A.ic, um, u);
+    if (A.krad != 0.0) rad_cool<double>(A.krad, A.dtk, A.ic, um, u);
 
     const double g = sqrt(1.0 + dot(u, u) * A.ic * A.ic);
     const double uu[3] = {u.x, u.y, u.z};
@@ -217,11 +218,12 @@ hipError_t launch_gpd64(pp_run* r, int s, double* J) {
         A.d[d] = r->p.d[d];
         A.pos[d] = (double*)S.cur.pos[d];
         A.u[d] = (double*)S.cur.u[d];
-        A.fac[d] = -S.q * S.w * r->p.d[d] / r->p.dt;
+        A.fac[d] = -S.q * S.w * r->p.d[d] / r->dt_drift;
     }
-    A.dt = r->p.dt;
+    A.dt = r->dt_drift;
+    A.dtk = r->dt_kick;
     A.ic = 1.0 / r->p.c;
-    A.h = S.q * r->p.dt / S.m;
+    A.h = S.q * r->dt_kick / S.m;
     A.krad = r->p.rad_tau * S.q * S.q / S.m;
     A.np = S.n;
     A.E = r->mesh.E;

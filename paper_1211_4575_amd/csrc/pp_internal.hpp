@@ -105,6 +105,18 @@ struct pp_run {
     double jac_bound = 0.0;  // error reduction bound after jac_sweeps sweeps
     double* omega = nullptr; // Chebyshev weights (device, relax_max_iter + 2)
     double gauss_kappa = 0.0; // damping of the Gauss-law filter: 1 / max |K|^2
+    // time step of the particle and field kernels: kick (momentum update) and drift
+    // (positions, current, fields); both dt except inside a composed step
+    double dt_kick = 0.0, dt_drift = 0.0;
+    double drift_ratio = 1.0;  // next drift / this drift (where the split form stores a particle)
+    // relaxation constants per drift size: [0] for dt, [1] and [2] for the two drifts of
+    // the fourth-order composition; the fields above hold the active set
+    struct RelaxSet {
+        double drift = 0.0, diagA = 1.0, jac_rho = 0.0, gamma = 1.0, r = 0.0, bound = 0.0;
+        int sweeps = 0;
+        double* omega = nullptr;
+    } rs[3];
+    int nrs = 1;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timing = false;
@@ -122,6 +134,13 @@ namespace pp {
 inline bool uses_line_solve(const pp_run* r) {
     return r->p.field_order > 2 && r->p.current_scheme == PP_CURRENT_CC;
 }
+
+// Fourth-order composition (Forest and Ruth 1990, position form): theta = 1/(2 - 2^(1/3));
+// substep (kick, drift) factors of dt after merging the half drifts of consecutive steps
+constexpr double FR_THETA = 1.3512071919596578;
+constexpr double FR_KICK[3] = {FR_THETA, 1.0 - 2.0 * FR_THETA, FR_THETA};
+constexpr double FR_DRIFT[3] = {0.5 * (1.0 - FR_THETA), 0.5 * (1.0 - FR_THETA), FR_THETA};
+void use_relax_set(pp_run* r, int k);  // make relaxation set k active
 
 void set_hip_error(hipError_t e, const char* where);
 inline bool ok(hipError_t e, const char* where) {

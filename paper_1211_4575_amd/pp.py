@@ -23,6 +23,7 @@ PP_FLAG_CFL, PP_FLAG_NONFINITE, PP_FLAG_OUT_OF_TILE = 1, 2, 4
 PP_DIAG_MOMENTS, PP_DIAG_FIELDS, PP_DIAG_RHO, PP_DIAG_DIVB, PP_DIAG_ALL = 1, 2, 4, 8, 15
 
 EXPORTED = ("pp_workspace_size", "pp_create", "pp_init_species", "pp_gather_push_deposit", "pp_field_step", "pp_sort_particles",
+            "pp_step",
             "pp_diagnostics", "pp_get_particles", "pp_timing_enable", "pp_timing_read", "pp_destroy",
             "pp_status_str", "pp_last_hip_error", "pp_batch_create", "pp_batch_add", "pp_batch_remove",
             "pp_batch_size", "pp_batch_step", "pp_batch_destroy")
@@ -46,6 +47,7 @@ class pp_params(ctypes.Structure):
         ("rad_tau", ctypes.c_double),
         ("current_scheme", ctypes.c_int32),
         ("gauss_filter_passes", ctypes.c_int32),
+        ("time_order", ctypes.c_int32),
     ]
 
 
@@ -113,6 +115,7 @@ def lib():
         L.pp_gather_push_deposit.argtypes = [vp]
         L.pp_field_step.argtypes = [vp]
         L.pp_sort_particles.argtypes = [vp, ctypes.c_int32]
+        L.pp_step.argtypes = [vp]
         L.pp_diagnostics.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(pp_diag)]
         L.pp_get_particles.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(pp_particles)]
         L.pp_timing_enable.argtypes = [vp, ctypes.c_int32]
@@ -169,6 +172,10 @@ def pp_field_step(run):
 
 def pp_sort_particles(run, s=-1):
     _check("pp_sort_particles", lib().pp_sort_particles(run, s))
+
+
+def pp_step(run):
+    _check("pp_step", lib().pp_step(run))
 
 
 def pp_diagnostics(run, what=PP_DIAG_ALL) -> pp_diag:
@@ -229,7 +236,7 @@ def pp_batch_destroy(batch):
 # ---- convenience owner of the torch tensors ---------------------------------------------
 def make_params(n, d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shape_order=2, field_order=2, alpha=0.55,
                 pusher=0, precision=PP_PREC_FP64, relax_tol=1e-14, relax_max_iter=200, rho_background=0.0,
-                rad_tau=0.0, current_scheme=0, gauss_filter_passes=0):
+                rad_tau=0.0, current_scheme=0, gauss_filter_passes=0, time_order=2):
     p = pp_params()
     p.n[:] = [int(v) for v in n]
     p.d[:] = [float(v) for v in d]
@@ -240,6 +247,7 @@ def make_params(n, d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shape_order=2, fi
     p.rho_background = float(rho_background)
     p.rad_tau = float(rad_tau)
     p.current_scheme, p.gauss_filter_passes = int(current_scheme), int(gauss_filter_passes)
+    p.time_order = int(time_order)
     return p
 
 
@@ -325,6 +333,9 @@ class Run:
         pp_field_step(self.handle)
 
     def step(self, sort=True):
+        if self.params.time_order == 4:  # the composed step (three substeps) in the library
+            pp_step(self.handle)
+            return
         self.gather_push_deposit()
         if sort or self.split:
             self.sort()

@@ -146,6 +146,13 @@ def test_batch_rejects_what_it_cannot_batch(ppm, orc):
         rg = ppm.Run(Pg, _split_species(species, (8, 8, 8), 3), E=E, B=B)
         with pytest.raises(ppm.PPError):
             ppm.pp_batch_add(batch, rg.handle)
+        # a run with the fourth-order composition
+        species, E, B = random_state(orc, (8, 8, 8), 2, seed=7)
+        P4 = ppm.make_params(n=(8, 8, 8), shape_order=3, field_order=2, precision=ppm.PP_PREC_FP32_SPLIT,
+                             time_order=4, dt=0.3)
+        r4 = ppm.Run(P4, _split_species(species, (8, 8, 8), 3), E=E, B=B)
+        with pytest.raises(ppm.PPError):
+            ppm.pp_batch_add(batch, r4.handle)
         # capacity, duplicates, other weight order
         ra, rb = _make(ppm, orc, 0), _make(ppm, orc, 1)
         ppm.pp_batch_add(batch, ra.handle)

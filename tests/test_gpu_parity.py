@@ -276,6 +276,53 @@ def test_scheme_and_filter_parameters_are_validated(ppm):
             ppm.Run(ppm.make_params(n=(4, 4, 4), **kw), [])
 
 
+@pytest.mark.parametrize("split", [False, True], ids=["fp64", "fp32_split"])
+def test_fourth_order_steps_match_oracle(ppm, orc, split):
+    # time_order 4: three substeps per step with kicks and drifts of their own (negative
+    # ones included), the fields advanced with each drift; two steps against the oracle
+    n, O, fo = (8, 8, 6), 3, 6
+    _say("fourth order", "split" if split else "fp64")
+    species, E, B = random_state(orc, n, 3, seed=91, uth=0.3)
+    kw = dict(n=n, dt=0.3, shape_order=O, field_order=fo, relax_tol=1e-14, relax_max_iter=300)
+    if split:
+        species = _split_species(species, n, O)
+        ref_species = [dict(s, u=s["u64"]) for s in species]
+    else:
+        ref_species = species
+    ref = _orc_run(orc, orc.make_params(time_order=4, **kw), ref_species, E, B)
+    prec = ppm.PP_PREC_FP32_SPLIT if split else ppm.PP_PREC_FP64
+    run = ppm.Run(ppm.make_params(precision=prec, time_order=4, **kw), species, E=E, B=B)
+    for step in range(2):
+        ref.step()
+        run.step()
+        Eg, Bg, Jg = run.fields()
+        if split:
+            assert rel_l2(Eg - E, ref.E - E) < 1e-5 and rel_l2(Bg - B, ref.B - B) < 1e-5, step
+        else:
+            assert rel_inf(Jg, ref.J) < 1e-12, step
+            assert rel_inf(Eg, ref.E) < 1e-12 and rel_inf(Bg, ref.B) < 1e-12, step
+        for s, sp in enumerate(ref.species):
+            g = _by_id(run.particles(s))
+            if split:
+                X = I.from_split(g["cell"], g["pos"], n)
+                assert np.max(np.abs(periodic_diff(X, sp["pos"], n))) < 1e-5, (step, s)
+                assert rel_inf(g["u"].astype(np.float64), sp["u"]) < 2e-5, (step, s)
+            else:
+                assert np.max(np.abs(periodic_diff(g["pos"], sp["pos"], n))) < 1e-12, (step, s)
+                assert rel_inf(g["u"], sp["u"]) < 1e-12, (step, s)
+    d = run.diagnostics()
+    assert d.flags == 0 and d.step == 2 and np.isnan(d.cc_max)
+    run.close()
+
+
+def test_time_order_is_validated(ppm):
+    with pytest.raises(ppm.PPError):
+        ppm.Run(ppm.make_params(n=(4, 4, 4), time_order=3), [])
+    with pytest.raises(ppm.PPError):  # theta c dt >= d: the longest drift breaks the particle CFL
+        ppm.Run(ppm.make_params(n=(4, 4, 4), dt=0.8, time_order=4), [])
+    ppm.Run(ppm.make_params(n=(4, 4, 4), dt=0.8), []).close()
+
+
 def test_radiative_cooling_parameter_is_validated(ppm):
     with pytest.raises(ppm.PPError):
         ppm.Run(ppm.make_params(n=(4, 4, 4), rad_tau=-1.0), [])
