@@ -101,6 +101,7 @@ static void release(pp_run* r) {
     for (int s = 0; s < PP_MAX_SPECIES; ++s) {
         f(r->sp[s].cell_cnt);
         f(r->sp[s].rank);
+        f(r->sp[s].perm);
         f(r->sp[s].offsets_next);
     }
     for (int d = 0; d < 3; ++d) f(r->line[d].coef);
@@ -157,8 +158,9 @@ static size_t internal_bytes(const pp_params* p, const Geom& g, int64_t nmax, in
         b += n3 * sizeof(long long) + PP_MAX_SPECIES * sizeof(int32_t) + sizeof(double);
         b += 2 * (size_t)nmax * sizeof(int32_t);                           // sort scratch
         b += (size_t)g.ntiles * SORT_RCAP * sizeof(RoundEntry);            // round tables
-        // per species: cell counts, particle ranks, next tile starts
-        b += (size_t)nsp * (nc * sizeof(int32_t) + (size_t)nmax * sizeof(int32_t) + ((size_t)g.ntiles + 1) * sizeof(int32_t));
+        // per species: cell counts, particle ranks and sort permutation, next tile starts
+        b += (size_t)nsp * (nc * sizeof(int32_t) + 2 * (size_t)nmax * sizeof(int32_t) +
+                            ((size_t)g.ntiles + 1) * sizeof(int32_t));
     }
     if (p->field_order > 2)  // line-solve coefficients: at most min(N, 127) per axis
         for (int d = 0; d < 3; ++d) b += (size_t)(p->n[d] < 127 ? p->n[d] : 127) * sizeof(double);
@@ -291,7 +293,11 @@ pp_status pp_init_species(pp_run* r, int32_t s, double q, double m, double w, co
         if (S.rank) (void)hipFree(S.rank);
         S.rank = nullptr;
         if (!dmalloc(&S.rank, (size_t)parts->n)) return PP_E_HIP;
+        if (S.perm) (void)hipFree(S.perm);
+        S.perm = nullptr;
+        if (!dmalloc(&S.perm, (size_t)parts->n)) return PP_E_HIP;
     }
+    S.pending = false;
     if (split && parts->n > r->sort_scratch_n) {
         if (r->sort_scratch) (void)hipFree(r->sort_scratch);
         r->sort_scratch = nullptr;
@@ -334,6 +340,12 @@ pp_status pp_gather_push_deposit(pp_run* r) {
     if (split) {
         e = launch_gpd32(r, target);
         if (!ok(e, "gather_push_deposit")) return PP_E_HIP;
+        for (int s = 0; s < PP_MAX_SPECIES; ++s) {  // the kernel wrote the pending order
+            Species& S = r->sp[s];
+            if (!S.active || !S.pending) continue;
+            swap_buffers(S.cur);
+            S.pending = false;
+        }
     } else {
         for (int s = 0; s < PP_MAX_SPECIES; ++s) {
             if (!r->sp[s].active) continue;
@@ -449,6 +461,7 @@ pp_status pp_diagnostics(pp_run* r, uint32_t what, pp_diag* out) {
 pp_status pp_get_particles(pp_run* r, int32_t s, pp_particles* out) {
     if (!r || !out || s < 0 || s >= PP_MAX_SPECIES) return PP_E_ARG;
     if (!r->sp[s].active) return PP_E_STATE;
+    if (!ok(materialize(r, s), "materialize")) return PP_E_HIP;  // the buffers in sort order
     *out = r->sp[s].cur;
     return PP_OK;
 }

@@ -97,6 +97,7 @@ pp_status pp_batch_add(pp_batch* b, pp_run* r) {
     if (!b->runs.empty() && b->runs[0]->p.shape_order != r->p.shape_order) return PP_E_ARG;
     for (int s = 0; s < PP_MAX_SPECIES; ++s)
         if (r->sp[s].active && !r->sp[s].sorted) return PP_E_STATE;
+    if (!ok(materialize(r, -1), "materialize")) return PP_E_HIP;  // batched kernels move in place
     b->runs.push_back(r);
     return PP_OK;
 }

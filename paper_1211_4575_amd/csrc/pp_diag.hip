@@ -418,7 +418,8 @@ static hipError_t launch_rho32(pp_run* r, unsigned mask) {
         if (!(mask & (1u << s))) continue;
         const Species& S = r->sp[s];
         Rho32Sp& D = A.sp[A.nsp++];
-        D.start = S.offsets;
+        // with a sort order pending, the buffers still follow the previous tile starts
+        D.start = S.pending ? S.offsets_next : S.offsets;
         D.cell = (const int32_t*)S.cur.cell;
         for (int d = 0; d < 3; ++d) D.pos[d] = (const float*)S.cur.pos[d];
         D.qw = S.q * S.w;
@@ -487,7 +488,9 @@ hipError_t deposit_rho_all(pp_run* r) {
 hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out) {
     const int bs = 256;
     const int64_t nc = r->g.ncell;
-    hipError_t e = launch_fill(r->dacc, ACC_COUNT, 0.0, r->stream);
+    hipError_t e = materialize(r, -1);  // a pending sort order: move the particles first
+    if (e != hipSuccess) return e;
+    e = launch_fill(r->dacc, ACC_COUNT, 0.0, r->stream);
     if (e != hipSuccess) return e;
     const bool split = r->p.precision == PP_PREC_FP32_SPLIT;
     const double V = r->p.d[0] * r->p.d[1] * r->p.d[2];

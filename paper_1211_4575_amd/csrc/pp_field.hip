@@ -234,6 +234,7 @@ __global__ void __launch_bounds__(FIELD_BS) k_field_batch(const FieldDesc* __res
 // The arithmetic and the order of the sums are those of relax_body, so both give the same
 // bits (the batched path keeps relax_body).
 constexpr int RX_TX = 32, RX_TY = 8, RX_ZC = 32;
+constexpr int64_t RX_MIN_BLOCKS = 1024;  // 4 columns per CU
 
 template <int R>
 __global__ void __launch_bounds__(256) k_relax_tiled(FieldDesc D, int k) {
@@ -507,9 +508,14 @@ hipError_t launch_field_step(pp_run* r) {
     const dim3 grid((unsigned)blocks_of(D.G));
     hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_COPY, 0);
     hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_RHS, 0);
-    const dim3 rgrid((unsigned)relax_tiled_blocks(D.G));
+    // the tiled sweep needs enough columns to fill the GPU; small boxes use the per-cell one
+    // (the same bits either way)
+    const int64_t tb = relax_tiled_blocks(D.G);
+    const dim3 rgrid((unsigned)tb);
     for (int k = 1; k <= D.sweeps; ++k) {
-        if (D.G.R == 5)
+        if (tb < RX_MIN_BLOCKS)
+            hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_JACOBI, k);
+        else if (D.G.R == 5)
             hipLaunchKernelGGL(k_relax_tiled<5>, rgrid, dim3(256), 0, r->stream, D, k);
         else if (D.G.R == 3)
             hipLaunchKernelGGL(k_relax_tiled<3>, rgrid, dim3(256), 0, r->stream, D, k);

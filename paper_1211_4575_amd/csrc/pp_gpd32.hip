@@ -42,9 +42,18 @@ struct Sp32 {
     const int32_t* start;  // tile starts (ntiles + 1)
     int32_t* cnt;          // particles per cell of the new positions (for the next sort)
     int32_t* rank;         // rank of each particle in its new cell (for the next sort)
-    int32_t* cell;
-    float* pos[3];
-    float* u[3];
+    // A sort leaves the new order as a permutation: slot q of the tile order holds the
+    // particle at index perm[q] of the input arrays, and the kernel writes slot q of the
+    // output arrays (it moves the particles as it updates them).  perm == nullptr: in place.
+    const int32_t* perm;
+    const int32_t* cell;
+    const float* pos[3];
+    const float* u[3];
+    int32_t* cell_o;
+    float* pos_o[3];
+    float* u_o[3];
+    const int64_t* id;  // tags moved with the permutation (nullptr: none or in place)
+    int64_t* id_o;
     float h;        // q dt / m
     float krad;     // radiative cooling constant rad_tau q^2 / m (0: off)
     double fac[3];  // -q w d_c / dt
@@ -307,10 +316,27 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
         const int32_t end = S.start[tile + 1];
         const double facq[3] = {S.fac[0] * qs, S.fac[1] * qs, S.fac[2] * qs};
         const double qwq = S.qw * qs;
-        for (int32_t p = start + threadIdx.x; p < end; p += GPD32_BS) {
+        for (int32_t q = start + threadIdx.x; q < end; q += GPD32_BS) {
+            const int32_t p = S.perm ? S.perm[q] : q;
+            if (p < 0) {  // an empty slot (counts made inconsistent by flagged particles)
+                S.rank[q] = -1;
+                continue;
+            }
             const int32_t cell = S.cell[p];
             float f[3] = {S.pos[0][p], S.pos[1][p], S.pos[2][p]};
             V3<float> u{S.u[0][p], S.u[1][p], S.u[2][p]};
+            if (S.id) S.id_o[q] = S.id[p];
+            // a particle left as it is still moves to its slot when the kernel reorders
+            auto keep = [&](const V3<float>& uk) {
+                if (!S.perm) return;
+                S.cell_o[q] = cell;
+                S.pos_o[0][q] = f[0];
+                S.pos_o[1][q] = f[1];
+                S.pos_o[2][q] = f[2];
+                S.u_o[0][q] = uk.x;
+                S.u_o[1][q] = uk.y;
+                S.u_o[2][q] = uk.z;
+            };
             // position inside the tile: rel = li + n0 lj + n0 n1 lk with l < t, found by
             // comparisons (no division)
             int64_t rel = (int64_t)cell - base_cell;
@@ -332,12 +358,14 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
                                     (int64_t)cell;
             if (!inside) {  // not this tile's particle: left out of the next sort
                 bad_all |= PP_FLAG_OUT_OF_TILE;
-                S.rank[p] = -1;
+                keep(u);
+                S.rank[q] = -1;
                 continue;
             }
-            if (!offset_ok<O>(f[0]) || !offset_ok<O>(f[1]) || !offset_ok<O>(f[2])) {  // left in place
+            if (!offset_ok<O>(f[0]) || !offset_ok<O>(f[1]) || !offset_ok<O>(f[2])) {  // left as it is
                 bad_all |= PP_FLAG_OUT_OF_TILE;
-                S.rank[p] = dest_rank(A, S, slots, loc, cell);
+                keep(u);
+                S.rank[q] = dest_rank(A, S, slots, loc, cell);
                 continue;
             }
 
@@ -381,9 +409,10 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
                 x1[d] = f[d] + dd;  // new position relative to the old cell's node
                 dxs[d] = dd;
             }
-            if (bad) {  // left in place
+            if (bad) {  // left as it was before the push
                 bad_all |= bad;
-                S.rank[p] = dest_rank(A, S, slots, loc, cell);
+                keep(um);
+                S.rank[q] = dest_rank(A, S, slots, loc, cell);
                 continue;
             }
 
@@ -519,15 +548,15 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
                 nc3[d] = wrap(gc[d] + (int)sh, A.n[d]);
             }
             const int32_t newcell = nc3[0] + n0 * (nc3[1] + n1 * nc3[2]);
-            S.cell[p] = newcell;
-            S.pos[0][p] = fn[0];
-            S.pos[1][p] = fn[1];
-            S.pos[2][p] = fn[2];
-            S.u[0][p] = u.x;
-            S.u[1][p] = u.y;
-            S.u[2][p] = u.z;
+            S.cell_o[q] = newcell;
+            S.pos_o[0][q] = fn[0];
+            S.pos_o[1][q] = fn[1];
+            S.pos_o[2][q] = fn[2];
+            S.u_o[0][q] = u.x;
+            S.u_o[1][q] = u.y;
+            S.u_o[2][q] = u.z;
             const int dst[3] = {li + shv[0], lj + shv[1], lk + shv[2]};
-            S.rank[p] = dest_rank(A, S, slots, dst, newcell);
+            S.rank[q] = dest_rank(A, S, slots, dst, newcell);
         }
         // reserve the tile's range in each destination cell's count, then complete the ranks
         __syncthreads();
@@ -731,10 +760,16 @@ void gpd32_fill_args(const pp_run* r, Gpd32Args* Ap) {
         D.start = S.offsets;
         D.cnt = S.cell_cnt;
         D.rank = S.rank;
+        D.perm = S.pending ? S.perm : nullptr;
         D.cell = S.cur.cell;
+        D.cell_o = S.pending ? S.cur.cell_alt : S.cur.cell;
+        D.id = S.pending ? S.cur.id : nullptr;
+        D.id_o = S.pending ? S.cur.id_alt : nullptr;
         for (int d = 0; d < 3; ++d) {
-            D.pos[d] = (float*)S.cur.pos[d];
-            D.u[d] = (float*)S.cur.u[d];
+            D.pos[d] = (const float*)S.cur.pos[d];
+            D.u[d] = (const float*)S.cur.u[d];
+            D.pos_o[d] = (float*)(S.pending ? S.cur.pos_alt[d] : S.cur.pos[d]);
+            D.u_o[d] = (float*)(S.pending ? S.cur.u_alt[d] : S.cur.u[d]);
             D.fac[d] = -S.q * S.w * r->p.d[d] / r->dt_drift;
         }
         D.h = (float)(S.q * r->dt_kick / S.m);

@@ -48,6 +48,11 @@ struct Species {
     int32_t* rank = nullptr;
     int32_t* offsets_next = nullptr;
     bool ranked = false;  // cell_cnt / rank describe the current positions
+    // split form: the last sort left its order as a permutation (slot q of the new order is
+    // particle perm[q] of the current buffers); the next particle kernel, or materialize,
+    // moves the particles
+    int32_t* perm = nullptr;
+    bool pending = false;
 };
 
 // Round table of a tile (split-form sort): in round r, the cells holding more than r
@@ -163,6 +168,8 @@ int64_t field_blocks(const pp_run* r);  // blocks of one field launch of this ru
 hipError_t launch_sort(pp_run* r, int s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 void sort_done(pp_run* r, int s);  // host bookkeeping after a ranked sort was enqueued
+// move the particles of species s (or of every species, s = -1) to a pending sort order
+hipError_t materialize(pp_run* r, int s);
 hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out);
 hipError_t deposit_rho_all(pp_run* r);  // rho of the current positions into r->rho
 hipError_t launch_gauss_filter(pp_run* r);  // the run's Gauss-law filter passes on E

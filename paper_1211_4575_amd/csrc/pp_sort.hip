@@ -10,7 +10,10 @@
 // ascending inside a round, so that 64 consecutive particles sit in 64 different cells.
 // After a push the particle kernel has already counted the particles of every new cell and
 // ranked each particle inside it, so the sort is a per-tile round table, a scan over tiles
-// and one scatter straight to the final positions (ranked sort).  The first sort of a
+// and the destination slot of every particle, kept as a permutation (ranked sort): the next
+// particle kernel moves the particles while it updates them, and reading them (or any other
+// use of the order) applies the permutation first.  In a batch the ranked sort moves the
+// particles itself (a tile's particles staged in LDS and written out).  The first sort of a
 // species (arbitrary order) buckets by tile -- a count per tile, a scan, and a scatter whose
 // positions come from block-aggregated atomics -- and then rebuilds the round-major order
 // tile by tile.
@@ -534,10 +537,6 @@ __device__ __forceinline__ void ranked_move_tile(const RankedArgs& A, int64_t T,
     }
 }
 
-__global__ void __launch_bounds__(MOVE_BS) k_ranked_move(RankedArgs A, int cap) {
-    extern __shared__ __align__(16) unsigned char lds_move[];
-    ranked_move_tile(A, blockIdx.x, cap, lds_move);
-}
 
 // LDS image capacity for a species: room for tiles somewhat above the mean population
 int move_capacity(const pp_run* r, int s) {
@@ -693,9 +692,7 @@ __global__ void __launch_bounds__(MOVE_BS) k_move_batch(const SortDesc* __restri
 static hipError_t allow_large_lds() {
     static bool done = false;
     if (done) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void*)k_ranked_move, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_move_batch, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    hipError_t e = hipFuncSetAttribute((const void*)k_move_batch, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     done = e == hipSuccess;
     return e;
 }
@@ -788,21 +785,93 @@ void sort_done(pp_run* r, int s) {
     S.sorted = true;
 }
 
+// Destination slot of every particle, as a permutation: perm[slot] = particle (slots no
+// particle goes to keep -1).  The particle kernel then reads through it and writes the
+// new order, so the particles move once per step, together with their update.
+__global__ void __launch_bounds__(256) k_ranked_perm(RankedArgs A, int32_t* perm) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.n) return;
+    const int32_t pos = ranked_pos(A, (int32_t)p);
+    if (pos >= 0) perm[pos] = (int32_t)p;
+}
+
+// out[q] = in[perm[q]] for every attribute (the move a pending permutation stands for)
+struct ApplyArgs {
+    int64_t n;
+    const int32_t* perm;
+    const int32_t* cell;
+    const float* pos[3];
+    const float* u[3];
+    const int64_t* id;
+    int32_t* cell_o;
+    float* pos_o[3];
+    float* u_o[3];
+    int64_t* id_o;
+};
+
+__global__ void __launch_bounds__(256) k_apply_perm(ApplyArgs A) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= A.n) return;
+    const int32_t p = A.perm[q];
+    if (p < 0) return;
+    A.cell_o[q] = A.cell[p];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        A.pos_o[d][q] = A.pos[d][p];
+        A.u_o[d][q] = A.u[d][p];
+    }
+    if (A.id) A.id_o[q] = A.id[p];
+}
+
+hipError_t materialize(pp_run* r, int s) {
+    for (int k = 0; k < PP_MAX_SPECIES; ++k) {
+        if (s >= 0 && k != s) continue;
+        Species& S = r->sp[k];
+        if (!S.active || !S.pending) continue;
+        if (S.n > 0) {
+            ApplyArgs A;
+            A.n = S.n;
+            A.perm = S.perm;
+            A.cell = S.cur.cell;
+            A.cell_o = S.cur.cell_alt;
+            A.id = S.cur.id;
+            A.id_o = S.cur.id ? S.cur.id_alt : nullptr;
+            for (int d = 0; d < 3; ++d) {
+                A.pos[d] = (const float*)S.cur.pos[d];
+                A.u[d] = (const float*)S.cur.u[d];
+                A.pos_o[d] = (float*)S.cur.pos_alt[d];
+                A.u_o[d] = (float*)S.cur.u_alt[d];
+            }
+            hipLaunchKernelGGL(k_apply_perm, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, r->stream, A);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            swap_buffers(S.cur);
+        }
+        S.pending = false;
+    }
+    return hipSuccess;
+}
+
 static hipError_t sort_ranked(pp_run* r, int s) {
     RankedArgs A;
     ranked_args(r, s, &A);
+    Species& S = r->sp[s];
     const int64_t nt = r->g.ntiles;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, r->stream, r->tile_max + s, (int64_t)1, 0);
     hipLaunchKernelGGL(k_round_tables, dim3((unsigned)((nt + 3) / 4)), dim3(256), 0, r->stream, A);
     scan_inplace(A.tot, nt + 1, r->scan_tmp, r->stream);
-    if (r->sp[s].n > 0) {
-        hipError_t e0 = allow_large_lds();
-        if (e0 != hipSuccess) return e0;
-        const int cap = move_capacity(r, s);
-        hipLaunchKernelGGL(k_ranked_move, dim3((unsigned)nt), dim3(MOVE_BS), move_lds_bytes(cap), r->stream, A, cap);
+    if (S.n > 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(S.n, 256)), dim3(256), 0, r->stream, S.perm, S.n, -1);
+        hipLaunchKernelGGL(k_ranked_perm, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, r->stream, A, S.perm);
     }
     hipError_t e = hipGetLastError();
-    sort_done(r, s);
+    // the new tile starts become current; the particles stay where they are until moved
+    int32_t* t = S.offsets;
+    S.offsets = S.offsets_next;
+    S.offsets_next = t;
+    S.ranked = false;
+    S.sorted = true;
+    S.pending = S.n > 0;
     return e;
 }
 
@@ -881,7 +950,11 @@ static hipError_t sort_species(pp_run* r, int s) {
 }
 
 hipError_t launch_sort(pp_run* r, int s) {
-    if (r->p.precision == PP_PREC_FP32_SPLIT) return r->sp[s].ranked ? sort_ranked(r, s) : sort_species<float>(r, s);
+    if (r->p.precision == PP_PREC_FP32_SPLIT) {
+        hipError_t e = materialize(r, s);  // a sort of a sort: apply the pending order first
+        if (e != hipSuccess) return e;
+        return r->sp[s].ranked ? sort_ranked(r, s) : sort_species<float>(r, s);
+    }
     return sort_species<double>(r, s);
 }
 

@@ -194,9 +194,9 @@ def test_workspace_size_is_host_only_and_validates():
                        precision=pp.PP_PREC_FP32_SPLIT)
     b0 = pp.pp_workspace_size(P, 0, 2)
     b1 = pp.pp_workspace_size(P, 1000, 2)
-    # two int32 of sort scratch per particle of the largest species, one int32 rank per particle
-    # of each species
-    assert b1 - b0 == 2 * 1000 * 4 + 2 * 1000 * 4
+    # two int32 of sort scratch per particle of the largest species, one int32 rank and one
+    # int32 sort permutation entry per particle of each species
+    assert b1 - b0 == 2 * 1000 * 4 + 2 * (2 * 1000 * 4)
     nc = 32 ** 3
     assert b0 >= (3 + 3 + 2 + 3) * 3 * nc * 8 // 3  # relaxation buffers, J2, rho pair, fixed-point J
     P64 = pp.make_params((32, 32, 32), shape_order=3, field_order=2)
