@@ -97,7 +97,6 @@ pp_status pp_batch_add(pp_batch* b, pp_run* r) {
     if (!b->runs.empty() && b->runs[0]->p.shape_order != r->p.shape_order) return PP_E_ARG;
     for (int s = 0; s < PP_MAX_SPECIES; ++s)
         if (r->sp[s].active && !r->sp[s].sorted) return PP_E_STATE;
-    if (!ok(materialize(r, -1), "materialize")) return PP_E_HIP;  // batched kernels move in place
     b->runs.push_back(r);
     return PP_OK;
 }
@@ -168,6 +167,12 @@ pp_status pp_batch_step(pp_batch* b) {
         pp_run* r = b->runs[i];
         double* target = uses_line_solve(r) ? r->J2 : r->mesh.J;
         gpd32_fill_args(r, (Gpd32Args*)(H + o_gpd + i * gpd32_args_size()));
+        for (int s = 0; s < PP_MAX_SPECIES; ++s) {  // the kernel writes the pending order
+            Species& S = r->sp[s];
+            if (!S.active || !S.pending) continue;
+            swap_buffers(S.cur);
+            S.pending = false;
+        }
         gpd32_fixed_desc(r, target, (FixedDesc*)(H + o_fix + i * gpd32_fixed_desc_size()));
         field_desc(r, (FieldDesc*)(H + o_field + i * field_desc_size()));
         tpre[i + 1] = tpre[i] + r->g.ntiles;
@@ -217,22 +222,17 @@ pp_status pp_batch_step(pp_batch* b) {
         if (ns == 0) continue;
         const int64_t* pre[SORT_BATCH_PHASES];
         for (int ph = 0; ph < SORT_BATCH_PHASES; ++ph) pre[ph] = (const int64_t*)(D + o_spre[s][ph]);
-        int maxcap = 0;
-        for (int j = 0; j < ns; ++j) {
-            const int c = move_capacity(b->runs[slot_segs[s][j]], s);
-            maxcap = c > maxcap ? c : maxcap;
-        }
-        e = launch_sort_batch(D + o_sort[s], pre, stot[s], ns, maxcap, b->stream);
+        e = launch_sort_batch(D + o_sort[s], pre, stot[s], ns, b->stream);
         if (!ok(e, "batch sort")) return PP_E_HIP;
     }
     e = launch_field_step_batch(D + o_field, (const int64_t*)(D + o_cpre), n, cpre[n], max_sweeps, b->stream);
     if (!ok(e, "batch field_step")) return PP_E_HIP;
 
-    // ---- host bookkeeping (buffer roles after the sort) ----------------------------------
+    // ---- host bookkeeping (tile starts and pending orders after the sort) ------------------
     for (int i = 0; i < n; ++i) {
         pp_run* r = b->runs[i];
         for (int s = 0; s < PP_MAX_SPECIES; ++s)
-            if (r->sp[s].active) sort_done(r, s);
+            if (r->sp[s].active) sort_enqueued(r, s);
         r->step += 1;
     }
     return PP_OK;

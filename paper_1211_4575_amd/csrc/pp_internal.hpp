@@ -167,7 +167,7 @@ int64_t field_blocks(const pp_run* r);  // blocks of one field launch of this ru
 // (first sort, arbitrary order) by bucketing and a per-tile rebuild.
 hipError_t launch_sort(pp_run* r, int s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
-void sort_done(pp_run* r, int s);  // host bookkeeping after a ranked sort was enqueued
+void sort_enqueued(pp_run* r, int s);  // host bookkeeping after a ranked sort was enqueued
 // move the particles of species s (or of every species, s = -1) to a pending sort order
 hipError_t materialize(pp_run* r, int s);
 hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out);
@@ -204,7 +204,6 @@ void sort_desc(const pp_run* r, int s, SortDesc* D);
 constexpr int SORT_BATCH_PHASES = 4;
 void sort_desc_blocks(const pp_run* r, int s, int64_t blocks[SORT_BATCH_PHASES]);
 hipError_t launch_sort_batch(const void* table, const int64_t* const prefixes[SORT_BATCH_PHASES],
-                             const int64_t totals[SORT_BATCH_PHASES], int nseg, int maxcap, hipStream_t st);
-int move_capacity(const pp_run* r, int s);
+                             const int64_t totals[SORT_BATCH_PHASES], int nseg, hipStream_t st);
 
 }  // namespace pp

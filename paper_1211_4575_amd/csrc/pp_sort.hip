@@ -443,107 +443,38 @@ __global__ void __launch_bounds__(256) k_round_tables(RankedArgs A) {
     round_table_tile(A, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
-// Destination slot of particle p of the current order (-1: not placed, a flagged particle);
-// tot holds the next tile starts.
-__device__ __forceinline__ int32_t ranked_pos(const RankedArgs& A, int32_t p) {
-    const int32_t r = A.rank[p];
+// Destination slot of particle p of the current order (-1: not placed, a flagged particle, or
+// valid false); tot holds the next tile starts.  Called by whole wavefronts: ranks past the
+// round table take their overflow slots with one atomic per wavefront and tile, lanes in lane
+// order (bunched plasmas put hundreds of particles in one cell).
+__device__ __forceinline__ int32_t ranked_pos(const RankedArgs& A, int32_t p, bool valid) {
+    const int32_t r = valid ? A.rank[p] : -1;
+    int32_t t = 0, pos = -1;
+    if (r >= 0) {
+        const int32_t key = key_cell(A.G, A.cell[p]);
+        t = key / TILE_CELLS;
+        if (r < SORT_RCAP) {
+            const int lc = key % TILE_CELLS;
+            const RoundEntry e = A.rounds[(int64_t)t * SORT_RCAP + r];
+            pos = A.tot[t] + e.before + (int32_t)__popcll(lc == 0 ? 0ull : (e.mask & ((1ull << lc) - 1ull)));
+        }
+    }
+    const bool over = r >= SORT_RCAP;
+    const int lane = threadIdx.x & 63;
+    uint64_t todo = __ballot(over);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int32_t lt = __shfl(t, leader, 64);
+        const uint64_t grp = __ballot(over && t == lt) & todo;
+        int32_t base = 0;
+        if (lane == leader) base = atomicAdd(&A.ovf[lt], (int32_t)__popcll(grp));
+        base = __shfl(base, leader, 64);
+        if (over && t == lt)
+            pos = A.tot[t] + A.rtot[t] + base + (int32_t)__popcll(grp & ((1ull << lane) - 1ull));
+        todo &= ~grp;
+    }
     if (r < 0) return -1;
-    const int32_t key = key_cell(A.G, A.cell[p]);
-    const int32_t t = key / TILE_CELLS;
-    const int lc = key % TILE_CELLS;
-    int32_t pos;
-    if (r < SORT_RCAP) {
-        const RoundEntry e = A.rounds[(int64_t)t * SORT_RCAP + r];
-        pos = A.tot[t] + e.before + (int32_t)__popcll(lc == 0 ? 0ull : (e.mask & ((1ull << lc) - 1ull)));
-    } else {
-        pos = A.tot[t] + A.rtot[t] + atomicAdd(&A.ovf[t], 1);
-    }
     return pos < A.tot[t + 1] ? pos : -1;  // inconsistent counts (flagged state): never past the tile
-}
-
-// One workgroup per source tile T moves T's particles to their places.  Most of them stay in
-// tile T: the workgroup loads every attribute of its particles at once (coalesced, source
-// order), keeps the ones bound for tile T in an LDS image of T's destination range and
-// writes the image out coalesced (slots filled from neighbouring tiles are skipped: their
-// workgroups store those directly).  Tiles larger than the image scatter directly.
-constexpr int MOVE_BS = 1024;
-constexpr int MOVE_WORDS = 7;  // cell, pos[3], u[3]
-
-// image words plus one "filled" byte per slot; at 32 ppc per species (mean tile 2048, cap
-// 2816) two workgroups fit in a CU's 160 KiB
-size_t move_lds_bytes(int cap) { return (size_t)cap * (sizeof(int32_t) * MOVE_WORDS + 1); }
-
-__device__ __forceinline__ void move_one(const RankedArgs& A, int32_t p, int32_t pos) {
-    A.cell_o[pos] = A.cell[p];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        A.pos_o[d][pos] = A.pos[d][p];
-        A.u_o[d][pos] = A.u[d][p];
-    }
-    if (A.id) A.id_o[pos] = A.id[p];
-}
-
-__device__ __forceinline__ void ranked_move_tile(const RankedArgs& A, int64_t T, int cap, unsigned char* lds) {
-    if (T >= A.ntiles) return;
-    const int32_t ss = A.start[T], se = A.start[T + 1];
-    const int32_t d0 = A.tot[T], d1 = A.tot[T + 1];
-    if (se - ss > cap || d1 - d0 > cap) {  // a crowded tile
-        for (int32_t p = ss + threadIdx.x; p < se; p += blockDim.x) {
-            const int32_t pos = ranked_pos(A, p);
-            if (pos >= 0) move_one(A, p, pos);
-        }
-        return;
-    }
-    uint32_t* img = (uint32_t*)lds;                       // MOVE_WORDS * cap
-    uint8_t* filled = (uint8_t*)(img + MOVE_WORDS * cap);  // cap
-    const int32_t nd = d1 - d0;
-    for (int32_t q = threadIdx.x; q < nd; q += blockDim.x) filled[q] = 0;
-    __syncthreads();
-    for (int32_t p = ss + threadIdx.x; p < se; p += blockDim.x) {
-        uint32_t v[MOVE_WORDS];
-        v[0] = (uint32_t)A.cell[p];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            v[1 + d] = __float_as_uint(A.pos[d][p]);
-            v[4 + d] = __float_as_uint(A.u[d][p]);
-        }
-        const int32_t pos = ranked_pos(A, p);
-        if (pos < 0) continue;
-        if (A.id) A.id_o[pos] = A.id[p];
-        const int32_t q = pos - d0;
-        if (q >= 0 && q < nd) {
-#pragma unroll
-            for (int w = 0; w < MOVE_WORDS; ++w) img[w * cap + q] = v[w];
-            filled[q] = 1;
-        } else {
-            A.cell_o[pos] = (int32_t)v[0];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                A.pos_o[d][pos] = __uint_as_float(v[1 + d]);
-                A.u_o[d][pos] = __uint_as_float(v[4 + d]);
-            }
-        }
-    }
-    __syncthreads();
-    for (int32_t q = threadIdx.x; q < nd; q += blockDim.x) {
-        if (!filled[q]) continue;
-        const int32_t j = d0 + q;
-        A.cell_o[j] = (int32_t)img[q];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            A.pos_o[d][j] = __uint_as_float(img[(1 + d) * cap + q]);
-            A.u_o[d][j] = __uint_as_float(img[(4 + d) * cap + q]);
-        }
-    }
-}
-
-
-// LDS image capacity for a species: room for tiles somewhat above the mean population
-int move_capacity(const pp_run* r, int s) {
-    const double mean = (double)r->sp[s].n / (double)(r->g.ntiles > 0 ? r->g.ntiles : 1);
-    int cap = (int)(1.25 * mean) + 256;
-    const int cmax = (int)((150 * 1024) / move_lds_bytes(1));
-    return cap < 256 ? 256 : (cap > cmax ? cmax : cap);
 }
 
 // ---- exclusive scan of int32, in place ------------------------------------------------
@@ -628,10 +559,12 @@ static KeyGeom key_geom(const pp_run* r) {
 // ---- batched ranked sort of one species slot over several runs -----------------------------
 struct SortDesc {
     RankedArgs A;
-    int cap;  // LDS image capacity of the move
+    int32_t* perm;  // n slots: the destination order, perm[slot] = particle
 };
 
-enum SortPhase { SP_RESET = 0, SP_TABLES = 1, SP_SCAN = 2, SP_MOVE = 3 };
+// reset: tile maximum and perm = -1; tables: round tables; scan: next tile starts;
+// perm: every particle's slot
+enum SortPhase { SP_RESET = 0, SP_TABLES = 1, SP_SCAN = 2, SP_PERM = 3 };
 
 // whole-segment exclusive scan by one workgroup (segments are short: one entry per tile)
 __device__ __forceinline__ void scan_segment(int32_t* data, int64_t n) {
@@ -665,9 +598,11 @@ __global__ void __launch_bounds__(256) k_sort_batch(const SortDesc* __restrict__
     if (r < 0) return;
     const RankedArgs& A = T[r].A;
     const int64_t blk = b - prefix[r];
+    const int64_t p = blk * 256 + threadIdx.x;
     switch (phase) {
     case SP_RESET:
-        if (threadIdx.x == 0) *A.tile_max = 0;
+        if (p == 0) *A.tile_max = 0;
+        if (p < A.n) T[r].perm[p] = -1;
         break;
     case SP_TABLES:
         round_table_tile(A, blk * 4 + (threadIdx.x >> 6));
@@ -675,28 +610,15 @@ __global__ void __launch_bounds__(256) k_sort_batch(const SortDesc* __restrict__
     case SP_SCAN:
         scan_segment(A.tot, A.ntiles + 1);
         break;
+    case SP_PERM: {
+        const int32_t pos = ranked_pos(A, (int32_t)p, p < A.n);
+        if (pos >= 0) T[r].perm[pos] = (int32_t)p;
+        break;
+    }
     default:
         break;
     }
 }
-
-__global__ void __launch_bounds__(MOVE_BS) k_move_batch(const SortDesc* __restrict__ T, const int64_t* __restrict__ prefix,
-                                                        int nseg) {
-    extern __shared__ __align__(16) unsigned char lds_move[];
-    const int64_t b = blockIdx.x;
-    const int r = find_segment(prefix, nseg, b);
-    if (r < 0) return;
-    ranked_move_tile(T[r].A, b - prefix[r], T[r].cap, lds_move);
-}
-
-static hipError_t allow_large_lds() {
-    static bool done = false;
-    if (done) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void*)k_move_batch, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-    done = e == hipSuccess;
-    return e;
-}
-
 
 static void ranked_args(const pp_run* r, int s, RankedArgs* A) {
     const Species& S = r->sp[s];
@@ -726,7 +648,7 @@ static void ranked_args(const pp_run* r, int s, RankedArgs* A) {
 
 void sort_desc(const pp_run* r, int s, SortDesc* D) {
     ranked_args(r, s, &D->A);
-    D->cap = move_capacity(r, s);
+    D->perm = r->sp[s].perm;
 }
 
 size_t sort_desc_size() { return sizeof(SortDesc); }
@@ -734,26 +656,21 @@ size_t sort_desc_size() { return sizeof(SortDesc); }
 // Blocks each phase needs for one descriptor.
 void sort_desc_blocks(const pp_run* r, int s, int64_t blocks[SORT_BATCH_PHASES]) {
     const int64_t nt = r->g.ntiles;
-    blocks[SP_RESET] = 1;
+    const int64_t pb = (r->sp[s].n + 255) / 256;
+    blocks[SP_RESET] = pb > 0 ? pb : 1;
     blocks[SP_TABLES] = (nt + 3) / 4;
     blocks[SP_SCAN] = 1;
-    blocks[SP_MOVE] = r->sp[s].n > 0 ? nt : 0;
+    blocks[SP_PERM] = pb;
 }
 
 // prefixes: one array of nseg + 1 block prefixes (device) per phase, totals: blocks per phase
 hipError_t launch_sort_batch(const void* table, const int64_t* const prefixes[SORT_BATCH_PHASES],
-                             const int64_t totals[SORT_BATCH_PHASES], int nseg, int maxcap, hipStream_t st) {
+                             const int64_t totals[SORT_BATCH_PHASES], int nseg, hipStream_t st) {
     if (nseg == 0) return hipSuccess;
     const SortDesc* T = (const SortDesc*)table;
-    for (int ph = 0; ph < SP_MOVE; ++ph) {
+    for (int ph = 0; ph < SORT_BATCH_PHASES; ++ph) {
         if (totals[ph] == 0) continue;
         hipLaunchKernelGGL(k_sort_batch, dim3((unsigned)totals[ph]), dim3(256), 0, st, T, prefixes[ph], nseg, ph);
-    }
-    if (totals[SP_MOVE] > 0) {
-        hipError_t e = allow_large_lds();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_move_batch, dim3((unsigned)totals[SP_MOVE]), dim3(MOVE_BS), move_lds_bytes(maxcap), st, T,
-                           prefixes[SP_MOVE], nseg);
     }
     return hipGetLastError();
 }
@@ -775,14 +692,16 @@ void swap_buffers(pp_particles& c) {
     }
 }
 
-void sort_done(pp_run* r, int s) {
+// Host bookkeeping once a ranked sort is enqueued: the new tile starts become current and the
+// particles stay where they are until the next particle kernel (or materialize) moves them.
+void sort_enqueued(pp_run* r, int s) {
     Species& S = r->sp[s];
-    if (S.n > 0) swap_buffers(S.cur);
     int32_t* t = S.offsets;
     S.offsets = S.offsets_next;
     S.offsets_next = t;
     S.ranked = false;
     S.sorted = true;
+    S.pending = S.n > 0;
 }
 
 // Destination slot of every particle, as a permutation: perm[slot] = particle (slots no
@@ -790,8 +709,7 @@ void sort_done(pp_run* r, int s) {
 // new order, so the particles move once per step, together with their update.
 __global__ void __launch_bounds__(256) k_ranked_perm(RankedArgs A, int32_t* perm) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= A.n) return;
-    const int32_t pos = ranked_pos(A, (int32_t)p);
+    const int32_t pos = ranked_pos(A, (int32_t)p, p < A.n);
     if (pos >= 0) perm[pos] = (int32_t)p;
 }
 
@@ -865,13 +783,7 @@ static hipError_t sort_ranked(pp_run* r, int s) {
         hipLaunchKernelGGL(k_ranked_perm, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, r->stream, A, S.perm);
     }
     hipError_t e = hipGetLastError();
-    // the new tile starts become current; the particles stay where they are until moved
-    int32_t* t = S.offsets;
-    S.offsets = S.offsets_next;
-    S.offsets_next = t;
-    S.ranked = false;
-    S.sorted = true;
-    S.pending = S.n > 0;
+    sort_enqueued(r, s);
     return e;
 }
 

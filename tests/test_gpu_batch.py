@@ -48,11 +48,18 @@ def _split_species(species, n, O):
 
 
 DIRECT_RUNS = (1,)  # runs with the direct current (no line solve) in the batch
+CROWDED_RUNS = (3,)  # runs with one cell holding more ranks than the sort's round table
 
 
 def _make(ppm, orc, k):
     n, ppc, fo, pusher, d, dt, _, _ = RUNS[k]
     species, E, B = random_state(orc, n, ppc, seed=700 + k, d=d)
+    if k in CROWDED_RUNS:
+        rng = np.random.default_rng(800 + k)
+        for sp in species:
+            more = rng.uniform(0, 1, (3, 400)) * 0.9 + np.array([[3.05], [2.05], [1.05]])
+            sp["pos"] = np.ascontiguousarray(np.concatenate([sp["pos"], more], axis=1))
+            sp["u"] = np.ascontiguousarray(np.concatenate([sp["u"], rng.normal(0, 0.2, (3, 400))], axis=1))
     P = ppm.make_params(n=n, d=d, dt=dt, shape_order=3, field_order=fo, pusher=pusher,
                         precision=ppm.PP_PREC_FP32_SPLIT, relax_tol=1e-14, relax_max_iter=200,
                         current_scheme=ppm.PP_CURRENT_DIRECT if k in DIRECT_RUNS else ppm.PP_CURRENT_CC)
