@@ -84,16 +84,19 @@ __global__ void __launch_bounds__(256) k_hist_f64(KeyGeom G, const double* __res
 // consecutive particles; each wavefront groups its lanes by destination tile (ballot loop),
 // the group leader reserves slots in a small LDS table keyed by tile, and after a barrier
 // one global atomic per distinct tile of the block reserves the block's run in that tile.
-// A block's particles come from one or two source tiles, so its destinations are a few
-// tiles of their neighbourhood.
+// When a block's particles come from one or two source tiles, its destinations are a few
+// tiles of their neighbourhood; in arbitrary order (a fresh load) nearly every particle of a
+// block has its own tile, the table fills at once and the probe limit sends the rest straight
+// to the global counters.
 constexpr int AGG_SLOTS = 128;
+constexpr int AGG_PROBES = 8;
 constexpr int AGG_PER_THREAD = 4;
 constexpr int AGG_BLOCK = 256 * AGG_PER_THREAD;
 
-// LDS slot of a key (open addressing); -1 when the table is full
+// LDS slot of a key (open addressing, at most AGG_PROBES probes); -1 when none is free
 __device__ __forceinline__ int agg_slot(int32_t* keys, int32_t key) {
     const unsigned h = ((unsigned)key * 2654435761u) >> 25;  // 7 bits
-    for (int probe = 0; probe < AGG_SLOTS; ++probe) {
+    for (int probe = 0; probe < AGG_PROBES; ++probe) {
         const int sl = (int)((h + (unsigned)probe) & (AGG_SLOTS - 1));
         const int32_t prev = atomicCAS(&keys[sl], -1, key);
         if (prev == -1 || prev == key) return sl;

@@ -432,6 +432,27 @@ def test_sort_is_a_permutation_by_cell(ppm, orc):
     run.close()
 
 
+def test_first_sort_of_an_arbitrary_order_many_tiles(ppm, orc):
+    # 768 tiles and particles in random order: a block of the bucketing sort meets far more
+    # destination tiles than its aggregation table holds, so most go to the global counters
+    n = (48, 32, 32)
+    _say("first sort", n)
+    species, E, B = random_state(orc, n, 3, seed=12, e_amp=0.0, b_amp=0.0)
+    sp32 = _split_species(species, n, 3)
+    run = ppm.Run(ppm.make_params(n=n, shape_order=3, field_order=2, precision=ppm.PP_PREC_FP32_SPLIT), sp32, E=E,
+                  B=B)
+    for step in range(2):
+        for s in range(2):
+            g = run.particles(s)
+            assert np.array_equal(np.sort(g["id"]), np.arange(len(g["id"])))
+            if step == 0:  # the loaded particles, only reordered
+                assert np.array_equal(g["cell"][np.argsort(g["id"])], sp32[s]["cell"])
+            _assert_round_major(g["cell"], n, (4, 4, 4))
+        run.step()
+    assert run.diagnostics().flags == 0
+    run.close()
+
+
 def _assert_round_major(cells, n, t):
     """Tiles in order; inside a tile round r holds one particle of every cell with more than r
     particles, local cells ascending (ranks beyond the round table may come last in any order)."""
