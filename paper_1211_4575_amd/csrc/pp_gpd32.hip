@@ -458,6 +458,7 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
             // Esirkepov current on the common window of O+2 centred nodes per axis
             float S0[3][O + 2], DS[3][O + 2];
             int wb[3];
+            bool moved[3];  // old and new supports differ along the axis
             {
                 const int clo[3] = {L.clox, L.cloy, L.cloz};
 #pragma unroll
@@ -479,6 +480,7 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
                         DS[d][kk] = s1 - s0;
                     }
                     wb[d] = loc[d] + clo[d] + bmin;
+                    moved[d] = lo1 || hi1;
                 }
             }
             const int cst[3] = {L.csx, L.csy, L.csz};
@@ -497,18 +499,24 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
                     acc += DS[comp][a];
                     Pq[a] = (double)acc * facq[comp];
                 }
+                // Along an axis where the supports coincide the window's last node carries no
+                // weight (its transverse factors are exactly zero) and the last prefix sum is
+                // the rounding residue of a vanishing sum: those additions are left out.
 #pragma unroll
                 for (int bq = 0; bq < O + 2; ++bq) {
+                    if (bq == O + 1 && !moved[d1]) continue;
                     // F = S0_1 (S0_2 + DS_2/2) + DS_1 (S0_2/2 + DS_2/3)
                     const float g1 = S0[d1][bq], h1 = DS[d1][bq];
 #pragma unroll
                     for (int e = 0; e < O + 2; ++e) {
+                        if (e == O + 1 && !moved[d2]) continue;
                         const float Fq = g1 * (S0[d2][e] + 0.5f * DS[d2][e]) +
                                          h1 * (0.5f * S0[d2][e] + (1.0f / 3.0f) * DS[d2][e]);
                         const double Fd = (double)Fq;
                         const int rowo = off0 + bq * cst[d1] + e * cst[d2];
 #pragma unroll
                         for (int a = 0; a <= O; ++a) {
+                            if (a == O && !moved[comp]) continue;
                             // bits of (1.5*2^52 + round(P_a F fac 2^e)): see the header
                             const double dq = fma(Pq[a], Fd, ROUND_MAGIC);
                             atomicAdd(Jc + rowo + a * cst[comp], (unsigned long long)__double_as_longlong(dq));

@@ -446,38 +446,63 @@ __global__ void __launch_bounds__(256) k_round_tables(RankedArgs A) {
     round_table_tile(A, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
-// Destination slot of particle p of the current order (-1: not placed, a flagged particle, or
-// valid false); tot holds the next tile starts.  Called by whole wavefronts: ranks past the
-// round table take their overflow slots with one atomic per wavefront and tile, lanes in lane
-// order (bunched plasmas put hundreds of particles in one cell).
-__device__ __forceinline__ int32_t ranked_pos(const RankedArgs& A, int32_t p, bool valid) {
-    const int32_t r = valid ? A.rank[p] : -1;
-    int32_t t = 0, pos = -1;
-    if (r >= 0) {
-        const int32_t key = key_cell(A.G, A.cell[p]);
-        t = key / TILE_CELLS;
-        if (r < SORT_RCAP) {
+// Destination slots of PERM_PER particles per thread (block blk of 256 threads covers
+// particles blk * PERM_BLOCK onwards, coalesced), recorded as perm[slot] = particle: the
+// table position of rank r in cell c's tile (tot holds the next tile starts); -1 for a
+// flagged particle (negative rank).  Every load of every particle is issued before the
+// first store, so the dependent loads of several particles are in flight together.  Ranks
+// past the round table take slots at the end of their tile with one atomic per wavefront
+// and tile, lanes in lane order (bunched plasmas put hundreds of particles in one cell).
+constexpr int PERM_PER = 4;
+constexpr int PERM_BLOCK = 256 * PERM_PER;
+
+__device__ __forceinline__ void ranked_perm_block(const RankedArgs& A, int32_t* perm, int64_t blk) {
+    const int64_t p0 = blk * PERM_BLOCK + threadIdx.x;
+    int32_t r[PERM_PER], c[PERM_PER], t[PERM_PER], pos[PERM_PER], lim[PERM_PER];
+#pragma unroll
+    for (int k = 0; k < PERM_PER; ++k) {
+        const int64_t p = p0 + k * 256;
+        const bool v = p < A.n;
+        r[k] = v ? A.rank[p] : -1;
+        c[k] = v ? A.cell[p] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < PERM_PER; ++k) {
+        t[k] = 0;
+        pos[k] = -1;
+        lim[k] = 0;
+        if (r[k] < 0) continue;
+        const int32_t key = key_cell(A.G, c[k]);
+        t[k] = key / TILE_CELLS;
+        lim[k] = A.tot[t[k] + 1];
+        pos[k] = A.tot[t[k]];
+        if (r[k] < SORT_RCAP) {
             const int lc = key % TILE_CELLS;
-            const RoundEntry e = A.rounds[(int64_t)t * SORT_RCAP + r];
-            pos = A.tot[t] + e.before + (int32_t)__popcll(lc == 0 ? 0ull : (e.mask & ((1ull << lc) - 1ull)));
+            const RoundEntry e = A.rounds[(int64_t)t[k] * SORT_RCAP + r[k]];
+            pos[k] += e.before + (int32_t)__popcll(lc == 0 ? 0ull : (e.mask & ((1ull << lc) - 1ull)));
+        } else {
+            pos[k] += A.rtot[t[k]];
         }
     }
-    const bool over = r >= SORT_RCAP;
     const int lane = threadIdx.x & 63;
-    uint64_t todo = __ballot(over);
-    while (todo) {
-        const int leader = __ffsll((unsigned long long)todo) - 1;
-        const int32_t lt = __shfl(t, leader, 64);
-        const uint64_t grp = __ballot(over && t == lt) & todo;
-        int32_t base = 0;
-        if (lane == leader) base = atomicAdd(&A.ovf[lt], (int32_t)__popcll(grp));
-        base = __shfl(base, leader, 64);
-        if (over && t == lt)
-            pos = A.tot[t] + A.rtot[t] + base + (int32_t)__popcll(grp & ((1ull << lane) - 1ull));
-        todo &= ~grp;
+#pragma unroll
+    for (int k = 0; k < PERM_PER; ++k) {
+        const bool over = r[k] >= SORT_RCAP;
+        uint64_t todo = __ballot(over);
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const int32_t lt = __shfl(t[k], leader, 64);
+            const uint64_t grp = __ballot(over && t[k] == lt) & todo;
+            int32_t base = 0;
+            if (lane == leader) base = atomicAdd(&A.ovf[lt], (int32_t)__popcll(grp));
+            base = __shfl(base, leader, 64);
+            if (over && t[k] == lt) pos[k] += base + (int32_t)__popcll(grp & ((1ull << lane) - 1ull));
+            todo &= ~grp;
+        }
     }
-    if (r < 0) return -1;
-    return pos < A.tot[t + 1] ? pos : -1;  // inconsistent counts (flagged state): never past the tile
+#pragma unroll
+    for (int k = 0; k < PERM_PER; ++k)  // inconsistent counts (flagged state): never past the tile
+        if (r[k] >= 0 && pos[k] < lim[k]) perm[pos[k]] = (int32_t)(p0 + k * 256);
 }
 
 // ---- exclusive scan of int32, in place ------------------------------------------------
@@ -613,11 +638,9 @@ __global__ void __launch_bounds__(256) k_sort_batch(const SortDesc* __restrict__
     case SP_SCAN:
         scan_segment(A.tot, A.ntiles + 1);
         break;
-    case SP_PERM: {
-        const int32_t pos = ranked_pos(A, (int32_t)p, p < A.n);
-        if (pos >= 0) T[r].perm[pos] = (int32_t)p;
+    case SP_PERM:
+        ranked_perm_block(A, T[r].perm, blk);
         break;
-    }
     default:
         break;
     }
@@ -663,7 +686,7 @@ void sort_desc_blocks(const pp_run* r, int s, int64_t blocks[SORT_BATCH_PHASES])
     blocks[SP_RESET] = pb > 0 ? pb : 1;
     blocks[SP_TABLES] = (nt + 3) / 4;
     blocks[SP_SCAN] = 1;
-    blocks[SP_PERM] = pb;
+    blocks[SP_PERM] = (r->sp[s].n + PERM_BLOCK - 1) / PERM_BLOCK;
 }
 
 // prefixes: one array of nseg + 1 block prefixes (device) per phase, totals: blocks per phase
@@ -711,9 +734,7 @@ void sort_enqueued(pp_run* r, int s) {
 // particle goes to keep -1).  The particle kernel then reads through it and writes the
 // new order, so the particles move once per step, together with their update.
 __global__ void __launch_bounds__(256) k_ranked_perm(RankedArgs A, int32_t* perm) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t pos = ranked_pos(A, (int32_t)p, p < A.n);
-    if (pos >= 0) perm[pos] = (int32_t)p;
+    ranked_perm_block(A, perm, blockIdx.x);
 }
 
 // out[q] = in[perm[q]] for every attribute (the move a pending permutation stands for)
@@ -783,7 +804,8 @@ static hipError_t sort_ranked(pp_run* r, int s) {
     scan_inplace(A.tot, nt + 1, r->scan_tmp, r->stream);
     if (S.n > 0) {
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(S.n, 256)), dim3(256), 0, r->stream, S.perm, S.n, -1);
-        hipLaunchKernelGGL(k_ranked_perm, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, r->stream, A, S.perm);
+        hipLaunchKernelGGL(k_ranked_perm, dim3((unsigned)((S.n + PERM_BLOCK - 1) / PERM_BLOCK)), dim3(256), 0, r->stream,
+                           A, S.perm);
     }
     hipError_t e = hipGetLastError();
     sort_enqueued(r, s);
