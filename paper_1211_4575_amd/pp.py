@@ -374,6 +374,17 @@ class Run:
             out["id"] = self._wrap_ptr(P.id, n, None).cpu().numpy()
         return out
 
+    def particle_tensors(self, s):
+        """Current particle state of species s as device tensors: views of the run's own
+        buffers (no copy), valid until the next step or sort."""
+        P = pp_get_particles(self.handle, s)
+        n = P.n
+        out = dict(u=[self._wrap_ptr(P.u[d], n, None) for d in range(3)],
+                   pos=[self._wrap_ptr(P.pos[d], n, None) for d in range(3)])
+        out["cell"] = self._wrap_ptr(P.cell, n, None) if self.split else None
+        out["id"] = self._wrap_ptr(P.id, n, None) if P.id else None
+        return out
+
     def fields(self):
         self.torch.cuda.synchronize(self.dev)
         return self.E.cpu().numpy(), self.B.cpu().numpy(), self.J.cpu().numpy()
