@@ -239,6 +239,7 @@ constexpr int64_t RX_MIN_BLOCKS = 1024;  // 4 columns per CU
 template <int R>
 __global__ void __launch_bounds__(256) k_relax_tiled(FieldDesc D, int k) {
     constexpr int W = RX_TX + 2 * R, H = RX_TY + 2 * R;
+    constexpr int NH = (W * H + 255) / 256;  // ring entries a thread may stage per plane
     __shared__ double pl[W * H];
     const FieldGeom& G = D.G;
     const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
@@ -260,22 +261,52 @@ __global__ void __launch_bounds__(256) k_relax_tiled(FieldDesc D, int k) {
     const double* prev = k <= 2 ? D.Bn : out;
     const double w = D.omega[k];
     const int nc = (int)G.nc;
+    const int nxy = n0 * n1;
+    // this thread's entries of the x-y ring around the tile: LDS index (-1: none) and
+    // in-plane offset (periodic), the same for every plane
+    int hl[NH], hg[NH];
+#pragma unroll
+    for (int e = 0; e < NH; ++e) {
+        const int h = threadIdx.x + 256 * e;
+        const int a = h % W, bb = h / W;
+        const bool ring = h < W * H && !(a >= R && a < R + RX_TX && bb >= R && bb < R + RX_TY);
+        hl[e] = ring ? h : -1;
+        hg[e] = ring ? nbw(i0, a - R, n0, 1) + n0 * nbw(j0, bb - R, n1, 1) : 0;
+    }
+    const int own = valid ? lin(G, i, j, 0) : 0;
     for (int c = 0; c < 3; ++c) {
         const double* x = in + c * G.nc;
-        double q[2 * R + 1];
+        const double* rhs = D.R + c * G.nc;
+        const double* pv = prev + c * G.nc;
+        // the loads of a plane are issued one plane ahead, so they are in flight while the
+        // block works on the current one
+        double q[2 * R + 1], hv[NH];
 #pragma unroll
         for (int t = 0; t <= 2 * R; ++t) q[t] = x[lin(G, iw, jw, nbw(z0, t - R, n2, G.small))];
+#pragma unroll
+        for (int e = 0; e < NH; ++e) hv[e] = hl[e] >= 0 ? x[hg[e] + z0 * nxy] : 0.0;
+        double rq = valid ? rhs[own + z0 * nxy] : 0.0;
+        double pq = valid ? pv[own + z0 * nxy] : 0.0;
         for (int kz = z0; kz < z1; ++kz) {
             __syncthreads();  // the previous plane's LDS reads are done
             pl[(ty + R) * W + tx + R] = q[R];
-            for (int h = threadIdx.x; h < W * H; h += 256) {
-                const int a = h % W, bb = h / W;
-                if (a >= R && a < R + RX_TX && bb >= R && bb < R + RX_TY) continue;  // interior
-                pl[h] = x[lin(G, nbw(i0, a - R, n0, 1), nbw(j0, bb - R, n1, 1), kz)];
-            }
+#pragma unroll
+            for (int e = 0; e < NH; ++e)
+                if (hl[e] >= 0) pl[hl[e]] = hv[e];
             __syncthreads();
+            const bool more = kz + 1 < z1;
+            double qn = 0.0, rn = 0.0, pn = 0.0;
+            if (more) {
+                qn = x[lin(G, iw, jw, nbw(kz + 1, R, n2, G.small))];
+#pragma unroll
+                for (int e = 0; e < NH; ++e)
+                    if (hl[e] >= 0) hv[e] = x[hg[e] + (kz + 1) * nxy];
+                if (valid) {
+                    rn = rhs[own + (kz + 1) * nxy];
+                    pn = pv[own + (kz + 1) * nxy];
+                }
+            }
             if (valid) {
-                const int qq = lin(G, i, j, kz);
                 double sl = 0.0;
 #pragma unroll
                 for (int o = -R; o <= R; ++o) {
@@ -285,18 +316,261 @@ __global__ void __launch_bounds__(256) k_relax_tiled(FieldDesc D, int k) {
                 }
                 const double xq = q[R];
                 const double Ax = xq - D.al2s * sl;
-                const double y = xq + (D.R[c * nc + qq] - Ax) * D.gdiag;
-                const double p = prev[c * nc + qq];
-                out[c * nc + qq] = p + w * (y - p);
+                const double y = xq + (rq - Ax) * D.gdiag;
+                out[c * nc + own + kz * nxy] = pq + w * (y - pq);
             }
-            if (kz + 1 < z1) {
+            if (more) {
 #pragma unroll
                 for (int t = 0; t < 2 * R; ++t) q[t] = q[t + 1];
-                q[2 * R] = x[lin(G, iw, jw, nbw(kz + 1, R, n2, G.small))];
+                q[2 * R] = qn;
+                rq = rn;
+                pq = pn;
             }
         }
         __syncthreads();
     }
+}
+
+// Right-hand side and E update, tiled the same way (single-run path): per component, each
+// array the component's stencils read streams through the block one z plane at a time, its
+// x-y ring staged in LDS when a stencil runs along x or y and a register window of z offsets
+// kept when one runs along z; the next plane's loads are issued before the current plane is
+// computed.  Sums are taken in the order of rhs_body and update_E_body (same bits).
+struct TileCtx {
+    int z0, z1, tx, ty, col, own, nxy, n2, small;
+    bool valid;
+};
+
+template <int R>
+struct Ring {  // this thread's entries of the x-y ring of a plane: LDS index (-1: none), offset
+    static constexpr int W = RX_TX + 2 * R, H = RX_TY + 2 * R, NH = (W * H + 255) / 256;
+    int hl[NH], hg[NH];
+};
+
+template <int R>
+__device__ __forceinline__ void tile_ctx(const FieldGeom& G, TileCtx& X, Ring<R>& g) {
+    constexpr int W = Ring<R>::W, H = Ring<R>::H;
+    const int n0 = G.n[0], n1 = G.n[1];
+    const int nbx = (n0 + RX_TX - 1) / RX_TX, nby = (n1 + RX_TY - 1) / RX_TY;
+    int b = blockIdx.x;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nby;
+    const int bz = b / nby;
+    const int i0 = bx * RX_TX, j0 = by * RX_TY;
+    X.z0 = bz * RX_ZC;
+    X.z1 = X.z0 + RX_ZC < G.n[2] ? X.z0 + RX_ZC : G.n[2];
+    X.tx = threadIdx.x % RX_TX;
+    X.ty = threadIdx.x / RX_TX;
+    X.valid = i0 + X.tx < n0 && j0 + X.ty < n1;
+    X.col = nbw(i0, X.tx, n0, 1) + n0 * nbw(j0, X.ty, n1, 1);  // idle threads load wrapped columns
+    X.own = X.valid ? X.col : 0;
+    X.nxy = n0 * n1;
+    X.n2 = G.n[2];
+    X.small = G.small;
+#pragma unroll
+    for (int e = 0; e < Ring<R>::NH; ++e) {
+        const int h = threadIdx.x + 256 * e;
+        const int a = h % W, bb = h / W;
+        const bool ring = h < W * H && !(a >= R && a < R + RX_TX && bb >= R && bb < R + RX_TY);
+        g.hl[e] = ring ? h : -1;
+        g.hg[e] = ring ? nbw(i0, a - R, n0, 1) + n0 * nbw(j0, bb - R, n1, 1) : 0;
+    }
+}
+
+// One array streamed through the planes: values at z offsets WLO..WHI of the thread's column
+// around the current plane and, with PLANE, the current plane's ring for the LDS stage.
+template <int R, int WLO, int WHI, bool PLANE>
+struct ZStream {
+    static constexpr int NW = WHI - WLO + 1, NH = Ring<R>::NH;
+    const double* f;
+    double w[NW];
+    double hv[PLANE ? NH : 1];
+    double wn;
+    __device__ __forceinline__ void init(const double* src, const TileCtx& X, const Ring<R>& g) {
+        f = src;
+#pragma unroll
+        for (int t = 0; t < NW; ++t) w[t] = f[X.col + X.nxy * nbw(X.z0, WLO + t, X.n2, X.small)];
+        if constexpr (PLANE) {
+#pragma unroll
+            for (int e = 0; e < NH; ++e) hv[e] = g.hl[e] >= 0 ? f[g.hg[e] + X.z0 * X.nxy] : 0.0;
+        }
+    }
+    __device__ __forceinline__ void stage(double* pl, const TileCtx& X, const Ring<R>& g) const {
+        if constexpr (PLANE) {
+            pl[(X.ty + R) * Ring<R>::W + X.tx + R] = w[-WLO];
+#pragma unroll
+            for (int e = 0; e < NH; ++e)
+                if (g.hl[e] >= 0) pl[g.hl[e]] = hv[e];
+        }
+    }
+    __device__ __forceinline__ void prefetch(int kz1, const TileCtx& X, const Ring<R>& g) {
+        wn = f[X.col + X.nxy * nbw(kz1, WHI, X.n2, X.small)];
+        if constexpr (PLANE) {
+#pragma unroll
+            for (int e = 0; e < NH; ++e)
+                if (g.hl[e] >= 0) hv[e] = f[g.hg[e] + kz1 * X.nxy];
+        }
+    }
+    __device__ __forceinline__ void shift() {
+#pragma unroll
+        for (int t = 0; t < NW - 1; ++t) w[t] = w[t + 1];
+        w[NW - 1] = wn;
+    }
+    __device__ __forceinline__ double at(int o) const { return w[o - WLO]; }
+};
+
+// sum_m a_m (f[+m-1+UP] - f[-m+UP]) along axis AX (UP = 1: dup, UP = 0: ddn), from the staged
+// plane (x, y) or the z window
+template <int R, int M, int AX, int UP, class S>
+__device__ __forceinline__ double dtile(const S& st, const double* pl, int c0, const double* a) {
+    constexpr int step = AX == 0 ? 1 : Ring<R>::W;
+    double s = 0.0;
+#pragma unroll
+    for (int m = 1; m <= M; ++m) {
+        const int hi = m - 1 + UP, lo = -m + UP;
+        if constexpr (AX == 2)
+            s += a[m - 1] * (st.at(hi) - st.at(lo));
+        else
+            s += a[m - 1] * (pl[c0 + hi * step] - pl[c0 + lo * step]);
+    }
+    return s;
+}
+
+template <int M, int C>
+__device__ __forceinline__ void rhs_tiled_comp(const FieldDesc& D, const TileCtx& X, const Ring<2 * M - 1>& g,
+                                               double* lds) {
+    constexpr int R = 2 * M - 1, WH = Ring<R>::W * Ring<R>::H;
+    constexpr int d1 = (C + 1) % 3, d2 = (C + 2) % 3;
+    constexpr bool uz = d1 == 2, vz = d2 == 2;  // which curl term differentiates along z
+    const FieldGeom& G = D.G;
+    ZStream<R, -R, R, true> sB;
+    ZStream<R, uz ? -M + 1 : 0, uz ? M : 0, !uz> sEu, sJu;  // E_d2, J_d2 along d1
+    ZStream<R, vz ? -M + 1 : 0, vz ? M : 0, !vz> sEv, sJv;  // E_d1, J_d1 along d2
+    sB.init(D.Bn + C * G.nc, X, g);
+    sEu.init(D.E + d2 * G.nc, X, g);
+    sEv.init(D.E + d1 * G.nc, X, g);
+    sJu.init(D.J + d2 * G.nc, X, g);
+    sJv.init(D.J + d1 * G.nc, X, g);
+    double *pB = lds, *pEu = lds + WH, *pEv = lds + 2 * WH, *pJu = lds + 3 * WH, *pJv = lds + 4 * WH;
+    const int c0 = (X.ty + R) * Ring<R>::W + X.tx + R;
+    for (int kz = X.z0; kz < X.z1; ++kz) {
+        __syncthreads();  // the previous plane's LDS reads are done
+        sB.stage(pB, X, g);
+        sEu.stage(pEu, X, g);
+        sEv.stage(pEv, X, g);
+        sJu.stage(pJu, X, g);
+        sJv.stage(pJv, X, g);
+        __syncthreads();
+        const bool more = kz + 1 < X.z1;
+        if (more) {
+            sB.prefetch(kz + 1, X, g);
+            sEu.prefetch(kz + 1, X, g);
+            sEv.prefetch(kz + 1, X, g);
+            sJu.prefetch(kz + 1, X, g);
+            sJv.prefetch(kz + 1, X, g);
+        }
+        if (X.valid) {
+            double lp = 0.0;
+#pragma unroll
+            for (int o = -R; o <= R; ++o) {
+                lp += G.L[0][o + R] * pB[c0 + o];
+                lp += G.L[1][o + R] * pB[c0 + o * Ring<R>::W];
+                lp += G.L[2][o + R] * sB.at(o);
+            }
+            double curlE = dtile<R, M, d1, 1>(sEu, pEu, c0, G.a[d1]) - dtile<R, M, d2, 1>(sEv, pEv, c0, G.a[d2]);
+            double curlJ = dtile<R, M, d1, 1>(sJu, pJu, c0, G.a[d1]) - dtile<R, M, d2, 1>(sJv, pJv, c0, G.a[d2]);
+            D.R[C * G.nc + X.own + (int64_t)kz * X.nxy] = sB.at(0) + D.cab * lp - D.dt * curlE + D.cj * curlJ;
+        }
+        if (more) {
+            sB.shift();
+            sEu.shift();
+            sEv.shift();
+            sJu.shift();
+            sJv.shift();
+        }
+    }
+}
+
+template <int M, int C>
+__device__ __forceinline__ void update_E_tiled_comp(const FieldDesc& D, const TileCtx& X, const Ring<2 * M - 1>& g,
+                                                    double* lds) {
+    constexpr int R = 2 * M - 1, WH = Ring<R>::W * Ring<R>::H;
+    constexpr int d1 = (C + 1) % 3, d2 = (C + 2) % 3;
+    constexpr bool uz = d1 == 2, vz = d2 == 2;
+    const FieldGeom& G = D.G;
+    ZStream<R, uz ? -M : 0, uz ? M - 1 : 0, !uz> sBu, sNu;  // B_d2, Bn_d2 along d1
+    ZStream<R, vz ? -M : 0, vz ? M - 1 : 0, !vz> sBv, sNv;  // B_d1, Bn_d1 along d2
+    ZStream<R, 0, 0, false> sE, sJ;
+    sBu.init(D.B + d2 * G.nc, X, g);
+    sBv.init(D.B + d1 * G.nc, X, g);
+    sNu.init(D.Bn + d2 * G.nc, X, g);
+    sNv.init(D.Bn + d1 * G.nc, X, g);
+    sE.init(D.E + C * G.nc, X, g);
+    sJ.init(D.J + C * G.nc, X, g);
+    double *pBu = lds, *pBv = lds + WH, *pNu = lds + 2 * WH, *pNv = lds + 3 * WH;
+    const int c0 = (X.ty + R) * Ring<R>::W + X.tx + R;
+    for (int kz = X.z0; kz < X.z1; ++kz) {
+        __syncthreads();
+        sBu.stage(pBu, X, g);
+        sBv.stage(pBv, X, g);
+        sNu.stage(pNu, X, g);
+        sNv.stage(pNv, X, g);
+        __syncthreads();
+        const bool more = kz + 1 < X.z1;
+        if (more) {
+            sBu.prefetch(kz + 1, X, g);
+            sBv.prefetch(kz + 1, X, g);
+            sNu.prefetch(kz + 1, X, g);
+            sNv.prefetch(kz + 1, X, g);
+            sE.prefetch(kz + 1, X, g);
+            sJ.prefetch(kz + 1, X, g);
+        }
+        if (X.valid) {
+            double cn = dtile<R, M, d1, 0>(sBu, pBu, c0, G.a[d1]) - dtile<R, M, d2, 0>(sBv, pBv, c0, G.a[d2]);
+            double co = dtile<R, M, d1, 0>(sNu, pNu, c0, G.a[d1]) - dtile<R, M, d2, 0>(sNv, pNv, c0, G.a[d2]);
+            D.E[C * G.nc + X.own + (int64_t)kz * X.nxy] =
+                sE.at(0) + D.c2dt * (D.al * cn + D.be * co - D.mu0 * sJ.at(0));
+        }
+        if (more) {
+            sBu.shift();
+            sBv.shift();
+            sNu.shift();
+            sNv.shift();
+            sE.shift();
+            sJ.shift();
+        }
+    }
+}
+
+enum CurlKind { CK_RHS = 0, CK_UPDATE_E = 1 };
+
+template <int M, int KIND>
+__global__ void __launch_bounds__(256) k_curl_tiled(FieldDesc D) {
+    constexpr int R = 2 * M - 1;
+    __shared__ double lds[5 * Ring<R>::W * Ring<R>::H];
+    TileCtx X;
+    Ring<R> g;
+    tile_ctx<R>(D.G, X, g);
+    if constexpr (KIND == CK_RHS) {
+        rhs_tiled_comp<M, 0>(D, X, g, lds);
+        rhs_tiled_comp<M, 1>(D, X, g, lds);
+        rhs_tiled_comp<M, 2>(D, X, g, lds);
+    } else {
+        update_E_tiled_comp<M, 0>(D, X, g, lds);
+        update_E_tiled_comp<M, 1>(D, X, g, lds);
+        update_E_tiled_comp<M, 2>(D, X, g, lds);
+    }
+}
+
+template <int KIND>
+static void launch_curl_tiled(const FieldDesc& D, int64_t blocks, hipStream_t st) {
+    if (D.G.M == 3)
+        hipLaunchKernelGGL((k_curl_tiled<3, KIND>), dim3((unsigned)blocks), dim3(256), 0, st, D);
+    else if (D.G.M == 2)
+        hipLaunchKernelGGL((k_curl_tiled<2, KIND>), dim3((unsigned)blocks), dim3(256), 0, st, D);
+    else
+        hipLaunchKernelGGL((k_curl_tiled<1, KIND>), dim3((unsigned)blocks), dim3(256), 0, st, D);
 }
 
 static int64_t relax_tiled_blocks(const FieldGeom& G) {
@@ -506,12 +780,15 @@ hipError_t launch_field_step(pp_run* r) {
     field_desc(r, &D);
     const int bs = FIELD_BS;
     const dim3 grid((unsigned)blocks_of(D.G));
-    hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_COPY, 0);
-    hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_RHS, 0);
-    // the tiled sweep needs enough columns to fill the GPU; small boxes use the per-cell one
-    // (the same bits either way)
+    // the tiled kernels need enough columns to fill the GPU; small boxes use the per-cell
+    // ones (the same bits either way)
     const int64_t tb = relax_tiled_blocks(D.G);
     const dim3 rgrid((unsigned)tb);
+    hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_COPY, 0);
+    if (tb < RX_MIN_BLOCKS)
+        hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_RHS, 0);
+    else
+        launch_curl_tiled<CK_RHS>(D, tb, r->stream);
     for (int k = 1; k <= D.sweeps; ++k) {
         if (tb < RX_MIN_BLOCKS)
             hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_JACOBI, k);
@@ -522,7 +799,10 @@ hipError_t launch_field_step(pp_run* r) {
         else
             hipLaunchKernelGGL(k_relax_tiled<1>, rgrid, dim3(256), 0, r->stream, D, k);
     }
-    hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_UPDATE_E, 0);
+    if (tb < RX_MIN_BLOCKS)
+        hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_UPDATE_E, 0);
+    else
+        launch_curl_tiled<CK_UPDATE_E>(D, tb, r->stream);
     return hipGetLastError();
 }
 

@@ -12,8 +12,8 @@
 // ranked each particle inside it, so the sort is a per-tile round table, a scan over tiles
 // and the destination slot of every particle, kept as a permutation (ranked sort): the next
 // particle kernel moves the particles while it updates them, and reading them (or any other
-// use of the order) applies the permutation first.  In a batch the ranked sort moves the
-// particles itself (a tile's particles staged in LDS and written out).  The first sort of a
+// use of the order) applies the permutation first; batched runs do the same, with every
+// phase one launch over all members.  The first sort of a
 // species (arbitrary order) buckets by tile -- a count per tile, a scan, and a scatter whose
 // positions come from block-aggregated atomics -- and then rebuilds the round-major order
 // tile by tile.
