@@ -690,6 +690,11 @@ def main(argv=None):
         wall64, gpd64_ms = time_steps(run, torch, args.fp64_steps, 1)
         fp64 = dict(value=npart * args.fp64_steps / wall64, ms_per_step=1e3 * wall64 / args.fp64_steps,
                     gpd_updates_per_s=npart / (gpd64_ms * 1e-3), gpd_ms=gpd64_ms)
+        # per-step charge conservation and Gauss residual of the FP64 form, outside the timed region
+        run.diagnostics(pp.PP_DIAG_RHO)
+        run.step()
+        dg = run.diagnostics(pp.PP_DIAG_ALL)
+        fp64["diagnostics"] = dict(cc_rel=dg.cc_max / dg.rho_ref, gauss_rel=dg.gauss_max / dg.rho_ref, flags=dg.flags)
         log(f"[bench] FP64 plain {fp64}")
         run.close()
         del run
