@@ -885,7 +885,7 @@ __device__ __forceinline__ void line_body(const LineArgs& A, int64_t b) {
 // x lines are rows (stored line by line, j fastest); y and z lines are taken W consecutive
 // x at a time (stored with the W lines interleaved, x fastest), so loads and stores move
 // whole rows or W-wide row segments.
-constexpr int LINE_LDS_DOUBLES = 4096;  // 32 KiB
+constexpr int LINE_LDS_DOUBLES = 4608;  // 36 KiB: 16 lines of 256 cells plus the wrap-around
 
 __device__ __forceinline__ void line_lds_body(const LineArgs& A, int64_t b, double* e) {
     const FieldGeom& G = A.G;
