@@ -446,23 +446,22 @@ __global__ void __launch_bounds__(256) k_round_tables(RankedArgs A) {
     round_table_tile(A, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
-// Destination slots of PERM_PER particles per thread (block blk of 256 threads covers
-// particles blk * PERM_BLOCK onwards, coalesced), recorded as perm[slot] = particle: the
-// table position of rank r in cell c's tile (tot holds the next tile starts); -1 for a
-// flagged particle (negative rank).  Every load of every particle is issued before the
-// first store, so the dependent loads of several particles are in flight together.  Ranks
-// past the round table take slots at the end of their tile with one atomic per wavefront
-// and tile, lanes in lane order (bunched plasmas put hundreds of particles in one cell).
+// Destination slots of PERM_PER particles per thread, p = p0 + 256 k below pend: the table
+// position of rank r in the new cell's tile (tot holds the next tile starts), or -1 for a
+// flagged particle (negative rank) and for inconsistent counts (flagged state: never past the
+// tile).  Every load of every particle is issued before any result is used, so the
+// dependent loads of several particles are in flight together.  Ranks past the round table
+// take slots at the end of their tile with one atomic per wavefront and tile, lanes in lane
+// order (bunched plasmas put hundreds of particles in one cell).  Called by whole wavefronts.
 constexpr int PERM_PER = 4;
 constexpr int PERM_BLOCK = 256 * PERM_PER;
 
-__device__ __forceinline__ void ranked_perm_block(const RankedArgs& A, int32_t* perm, int64_t blk) {
-    const int64_t p0 = blk * PERM_BLOCK + threadIdx.x;
-    int32_t r[PERM_PER], c[PERM_PER], t[PERM_PER], pos[PERM_PER], lim[PERM_PER];
+__device__ __forceinline__ void ranked_slots(const RankedArgs& A, int64_t p0, int64_t pend, int32_t pos[PERM_PER]) {
+    int32_t r[PERM_PER], c[PERM_PER], t[PERM_PER], lim[PERM_PER];
 #pragma unroll
     for (int k = 0; k < PERM_PER; ++k) {
         const int64_t p = p0 + k * 256;
-        const bool v = p < A.n;
+        const bool v = p < pend;
         r[k] = v ? A.rank[p] : -1;
         c[k] = v ? A.cell[p] : 0;
     }
@@ -501,8 +500,46 @@ __device__ __forceinline__ void ranked_perm_block(const RankedArgs& A, int32_t* 
         }
     }
 #pragma unroll
-    for (int k = 0; k < PERM_PER; ++k)  // inconsistent counts (flagged state): never past the tile
-        if (r[k] >= 0 && pos[k] < lim[k]) perm[pos[k]] = (int32_t)(p0 + k * 256);
+    for (int k = 0; k < PERM_PER; ++k)
+        if (r[k] < 0 || pos[k] >= lim[k]) pos[k] = -1;
+}
+
+// perm[slot] = particle for the particles of source tile T (one workgroup per tile).  Most
+// of them stay in the tile: their entries are collected in an LDS image of T's destination
+// range and written out in order (entries that particles from neighbouring tiles fill are
+// written by those tiles' workgroups, directly); the rest, and every entry of a destination
+// range larger than the image, are written directly.
+constexpr int PERM_IMG = 4096;
+
+__device__ __forceinline__ void ranked_perm_tile(const RankedArgs& A, int32_t* perm, int64_t T, int32_t* img) {
+    if (T >= A.ntiles) return;
+    const int32_t ss = A.start[T], se = A.start[T + 1];
+    const int32_t d0 = A.tot[T];
+    const int32_t nd = A.tot[T + 1] - d0;
+    const bool staged = nd <= PERM_IMG;
+    if (staged)
+        for (int32_t q = threadIdx.x; q < nd; q += blockDim.x) img[q] = -1;
+    __syncthreads();
+    for (int64_t b = ss; b < se; b += PERM_BLOCK) {
+        int32_t pos[PERM_PER];
+        ranked_slots(A, b + threadIdx.x, se, pos);
+#pragma unroll
+        for (int k = 0; k < PERM_PER; ++k) {
+            if (pos[k] < 0) continue;
+            const int32_t p = (int32_t)(b + threadIdx.x + k * 256);
+            const int32_t q = pos[k] - d0;
+            if (staged && q >= 0 && q < nd)
+                img[q] = p;
+            else
+                perm[pos[k]] = p;
+        }
+    }
+    __syncthreads();
+    if (staged)
+        for (int32_t q = threadIdx.x; q < nd; q += blockDim.x) {
+            const int32_t v = img[q];
+            if (v >= 0) perm[d0 + q] = v;
+        }
 }
 
 // ---- exclusive scan of int32, in place ------------------------------------------------
@@ -638,9 +675,11 @@ __global__ void __launch_bounds__(256) k_sort_batch(const SortDesc* __restrict__
     case SP_SCAN:
         scan_segment(A.tot, A.ntiles + 1);
         break;
-    case SP_PERM:
-        ranked_perm_block(A, T[r].perm, blk);
+    case SP_PERM: {
+        __shared__ int32_t img[PERM_IMG];
+        ranked_perm_tile(A, T[r].perm, blk, img);
         break;
+    }
     default:
         break;
     }
@@ -686,7 +725,7 @@ void sort_desc_blocks(const pp_run* r, int s, int64_t blocks[SORT_BATCH_PHASES])
     blocks[SP_RESET] = pb > 0 ? pb : 1;
     blocks[SP_TABLES] = (nt + 3) / 4;
     blocks[SP_SCAN] = 1;
-    blocks[SP_PERM] = (r->sp[s].n + PERM_BLOCK - 1) / PERM_BLOCK;
+    blocks[SP_PERM] = r->sp[s].n > 0 ? nt : 0;
 }
 
 // prefixes: one array of nseg + 1 block prefixes (device) per phase, totals: blocks per phase
@@ -734,7 +773,8 @@ void sort_enqueued(pp_run* r, int s) {
 // particle goes to keep -1).  The particle kernel then reads through it and writes the
 // new order, so the particles move once per step, together with their update.
 __global__ void __launch_bounds__(256) k_ranked_perm(RankedArgs A, int32_t* perm) {
-    ranked_perm_block(A, perm, blockIdx.x);
+    __shared__ int32_t img[PERM_IMG];
+    ranked_perm_tile(A, perm, blockIdx.x, img);
 }
 
 // out[q] = in[perm[q]] for every attribute (the move a pending permutation stands for)
@@ -804,8 +844,7 @@ static hipError_t sort_ranked(pp_run* r, int s) {
     scan_inplace(A.tot, nt + 1, r->scan_tmp, r->stream);
     if (S.n > 0) {
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(S.n, 256)), dim3(256), 0, r->stream, S.perm, S.n, -1);
-        hipLaunchKernelGGL(k_ranked_perm, dim3((unsigned)((S.n + PERM_BLOCK - 1) / PERM_BLOCK)), dim3(256), 0, r->stream,
-                           A, S.perm);
+        hipLaunchKernelGGL(k_ranked_perm, dim3((unsigned)nt), dim3(256), 0, r->stream, A, S.perm);
     }
     hipError_t e = hipGetLastError();
     sort_enqueued(r, s);

@@ -366,6 +366,14 @@ class Run:
         P = pp_get_particles(self.handle, s)
         self.torch.cuda.synchronize(self.dev)
         n = P.n
+        if n == 0:  # an empty species may hold no buffers at all
+            rt = np.float32 if self.split else np.float64
+            out = dict(u=np.zeros((3, 0), rt), pos=np.zeros((3, 0), rt))
+            if self.split:
+                out["cell"] = np.zeros(0, np.int32)
+            if self.bufs[s]["id"] is not None:
+                out["id"] = np.zeros(0, np.int64)
+            return out
         out = dict(u=np.stack([self._wrap_ptr(P.u[d], n, None).cpu().numpy() for d in range(3)]))
         out["pos"] = np.stack([self._wrap_ptr(P.pos[d], n, None).cpu().numpy() for d in range(3)])
         if self.split:
@@ -379,6 +387,9 @@ class Run:
         buffers (no copy), valid until the next step or sort."""
         P = pp_get_particles(self.handle, s)
         n = P.n
+        if n == 0:
+            return {k: (v if k in ("cell", "id") else [v[d] for d in range(3)]) if v is not None else None
+                    for k, v in self.bufs[s].items() if k != "alt"}
         out = dict(u=[self._wrap_ptr(P.u[d], n, None) for d in range(3)],
                    pos=[self._wrap_ptr(P.pos[d], n, None) for d in range(3)])
         out["cell"] = self._wrap_ptr(P.cell, n, None) if self.split else None

@@ -528,3 +528,90 @@ def test_fp32_push_requires_sort(ppm, orc):
         run.gather_push_deposit()
     assert ei.value.status == ppm.PP_E_STATE
     run.close()
+
+
+@pytest.mark.parametrize("split", [False, True], ids=["fp64", "fp32_split"])
+def test_empty_species_and_vacuum_match_oracle(ppm, orc, split):
+    # degenerate inputs: a species without particles beside a populated one, then a box with
+    # no particles at all (the field step alone: vacuum Maxwell from a random divergence-free
+    # start); both against the oracle over three steps
+    n = (8, 8, 4)
+    _say("empty species", split)
+    species, E, B = random_state(orc, n, 2, seed=31, uth=0.2)
+    empty = dict(species[1], pos=np.zeros((3, 0)), u=np.zeros((3, 0)))
+    kw = dict(n=n, dt=0.4, shape_order=3, field_order=4, relax_tol=1e-14, relax_max_iter=200)
+    for case in ([species[0], empty], [dict(species[0], pos=np.zeros((3, 0)), u=np.zeros((3, 0))), empty]):
+        if split:
+            sp = _split_species(case, n, 3)
+            ref = _orc_run(orc, orc.make_params(**kw), [dict(s, u=s["u64"]) for s in sp], E, B)
+            run = ppm.Run(ppm.make_params(precision=ppm.PP_PREC_FP32_SPLIT, **kw), sp, E=E, B=B)
+            tol_f, tol_x, tol_u = 1e-5, 1e-6, 1e-5
+        else:
+            sp = case
+            ref = _orc_run(orc, orc.make_params(**kw), sp, E, B)
+            run = ppm.Run(ppm.make_params(precision=ppm.PP_PREC_FP64, **kw), sp, E=E, B=B)
+            tol_f, tol_x, tol_u = 1e-12, 1e-12, 1e-12
+        for _ in range(3):
+            ref.step()
+            run.step()
+        Eg, Bg, Jg = run.fields()
+        assert rel_l2(Eg - E, ref.E - E) < tol_f
+        assert rel_l2(Bg - B, ref.B - B) < tol_f
+        assert rel_l2(Jg, ref.J) < tol_f or (np.max(np.abs(ref.J)) == 0.0 and np.max(np.abs(Jg)) == 0.0)
+        for s, rs in enumerate(ref.species):
+            g = _by_id(run.particles(s))
+            assert g["u"].shape[1] == rs["u"].shape[1]
+            if rs["u"].shape[1] == 0:
+                continue
+            X = I.from_split(g["cell"], g["pos"], n) if split else g["pos"]
+            assert np.max(np.abs(periodic_diff(X, rs["pos"], n))) < tol_x
+            assert rel_inf(g["u"].astype(np.float64), rs["u"]) < tol_u
+        d = run.diagnostics()
+        assert d.flags == 0 and d.step == 3
+        run.close()
+
+
+def test_bad_particles_are_flagged_kept_and_left_out(ppm, orc):
+    # a non-finite momentum and an offset outside the split range: the step flags them
+    # (PP_FLAG_NONFINITE, PP_FLAG_OUT_OF_TILE), leaves both particles as they were, and keeps
+    # them out of the current, so every other particle and the fields follow the oracle run
+    # without them
+    n = (8, 8, 8)
+    _say("bad particles")
+    species, E, B = random_state(orc, n, 2, seed=41, uth=0.2)
+    sp32 = _split_species(species, n, 3)
+    bad_nan, bad_off = 5, 9
+    sp32[0]["u"] = sp32[0]["u"].copy()
+    sp32[0]["u"][1, bad_nan] = np.float32(np.nan)
+    sp32[1]["off"] = sp32[1]["off"].copy()
+    sp32[1]["off"][0, bad_off] = np.float32(3.5)
+    kw = dict(n=n, dt=0.4, shape_order=3, field_order=2, relax_tol=1e-14, relax_max_iter=200)
+    keep = [np.ones(sp32[0]["u"].shape[1], bool), np.ones(sp32[1]["u"].shape[1], bool)]
+    keep[0][bad_nan] = False
+    keep[1][bad_off] = False
+    good = [dict(s, pos=s["pos"][:, k], u64=s["u64"][:, k]) for s, k in zip(sp32, keep)]
+    ref = _orc_run(orc, orc.make_params(**kw), [dict(s, u=s["u64"]) for s in good], E, B)
+    ref.step()
+    run = ppm.Run(ppm.make_params(precision=ppm.PP_PREC_FP32_SPLIT, **kw), sp32, E=E, B=B)
+    run.step()
+    d = run.diagnostics()
+    assert d.flags & ppm.PP_FLAG_NONFINITE and d.flags & ppm.PP_FLAG_OUT_OF_TILE
+    Eg, Bg, Jg = run.fields()
+    assert rel_l2(Jg, ref.J) < 1e-5
+    assert rel_l2(Eg - E, ref.E - E) < 1e-5
+    assert rel_l2(Bg - B, ref.B - B) < 1e-5
+    for s, bad in ((0, bad_nan), (1, bad_off)):
+        g = _by_id(run.particles(s))
+        assert np.array_equal(np.sort(g["id"]), np.arange(len(g["id"])))
+        # the bad particle as it was loaded
+        assert g["cell"][bad] == sp32[s]["cell"][bad]
+        assert np.array_equal(g["pos"][:, bad], sp32[s]["off"][:, bad])
+        assert np.array_equal(g["u"][:, bad], sp32[s]["u"][:, bad], equal_nan=True)
+        # the others as the oracle moved them
+        k = keep[s]
+        X = I.from_split(g["cell"][k], g["pos"][:, k], n)
+        assert np.max(np.abs(periodic_diff(X, ref.species[s]["pos"], n))) < 1e-6
+        assert rel_inf(g["u"][:, k].astype(np.float64), ref.species[s]["u"]) < 1e-5
+    # flags are cleared once read
+    assert run.diagnostics().flags == 0
+    run.close()
