@@ -488,9 +488,9 @@ hipError_t deposit_rho_all(pp_run* r) {
 hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out) {
     const int bs = 256;
     const int64_t nc = r->g.ncell;
-    hipError_t e = materialize(r, -1);  // a pending sort order: move the particles first
-    if (e != hipSuccess) return e;
-    e = launch_fill(r->dacc, ACC_COUNT, 0.0, r->stream);
+    // a pending sort order needs no move here: the moments are sums over every particle and
+    // the charge deposit follows the tile starts of the buffers as they are
+    hipError_t e = launch_fill(r->dacc, ACC_COUNT, 0.0, r->stream);
     if (e != hipSuccess) return e;
     const bool split = r->p.precision == PP_PREC_FP32_SPLIT;
     const double V = r->p.d[0] * r->p.d[1] * r->p.d[2];
