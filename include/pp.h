@@ -205,7 +205,11 @@ pp_status pp_gather_push_deposit(pp_run* run);
 
 /* Steps 4-5 of Sec. III: B^{n+1} from the elliptic equation "EllipticB" (with
  * the J term's sign derived from "bnplus1"/"enplus1") by Jacobi relaxation from
- * B^n, then E^{n+1} from "enplus1".  E and B are updated in place. */
+ * B^n, then E^{n+1} from "enplus1".  E and B are updated in place.  The number of
+ * sweeps is the smallest whose error-reduction bound reaches relax_tol, at most
+ * relax_max_iter; when the cap is reached first the step is still completed with
+ * relax_max_iter sweeps and PP_E_NOCONV is returned (pp_diag.relax_resid gives the
+ * bound reached). */
 pp_status pp_field_step(pp_run* run);
 
 /* Counting sort of species s (-1 = all) by tile-major cell key (Sec. III: the
@@ -219,7 +223,7 @@ pp_status pp_sort_particles(pp_run* run, int32_t s);
  * with its own kick and drift, a sort and a field step over its drift.  The three calls
  * above, used one by one, always take one leapfrog step of dt.  After a composed step
  * the continuity residual of pp_diagnostics is not defined (NaN): J is that of the last
- * substep.  Errors as the three calls. */
+ * substep.  Errors as the three calls (PP_E_NOCONV once the whole step is done). */
 pp_status pp_step(pp_run* run);
 
 /* FP64 diagnostics selected by `what` (PP_DIAG_* bits) written to *out (host
@@ -264,7 +268,8 @@ pp_status pp_batch_remove(pp_batch* batch, pp_run* run);
 pp_status pp_batch_size(const pp_batch* batch, int32_t* n);
 
 /* One whole time step of every member (Sec. III order: particles, sort, fields), enqueued
- * on the batch's stream.  Each member's step counter advances by one. */
+ * on the batch's stream.  Each member's step counter advances by one.  PP_E_NOCONV (the
+ * step done) when a member's relaxation is capped by its relax_max_iter. */
 pp_status pp_batch_step(pp_batch* batch);
 
 /* Release the batch's own buffers (members are untouched). */

@@ -378,7 +378,8 @@ pp_status pp_field_step(pp_run* r) {
         e = launch_gauss_filter(r);
         if (!ok(e, "gauss_filter")) return PP_E_HIP;
     }
-    return PP_OK;
+    // the step is done either way; relax_max_iter sweeps could not reach relax_tol
+    return r->jac_converged ? PP_OK : PP_E_NOCONV;
 }
 
 pp_status pp_step(pp_run* r) {
@@ -390,6 +391,7 @@ pp_status pp_step(pp_run* r) {
         return st;
     }
     pp_status st = PP_OK;
+    bool noconv = false;  // a substep's relaxation capped: the step still completes
     for (int k = 0; k < 3 && st == PP_OK; ++k) {
         use_relax_set(r, k < 2 ? 1 : 2);  // sets 1 and 2 hold the drifts (1-theta)/2 dt and theta dt
         r->dt_kick = FR_KICK[k] * r->p.dt;
@@ -397,13 +399,17 @@ pp_status pp_step(pp_run* r) {
         st = pp_gather_push_deposit(r);
         if (st == PP_OK) st = pp_sort_particles(r, -1);
         if (st == PP_OK) st = pp_field_step(r);
+        if (st == PP_E_NOCONV) {
+            noconv = true;
+            st = PP_OK;
+        }
     }
     use_relax_set(r, 0);
     r->dt_kick = r->p.dt;
     r->drift_ratio = 1.0;
     r->step -= 2;             // one step, three particle substeps
     r->rho_prev_step = -1;    // J is the last substep's: no continuity check across the step
-    return st;
+    return st == PP_OK && noconv ? PP_E_NOCONV : st;
 }
 
 pp_status pp_sort_particles(pp_run* r, int32_t s) {

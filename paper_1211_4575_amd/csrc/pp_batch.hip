@@ -229,13 +229,16 @@ pp_status pp_batch_step(pp_batch* b) {
     if (!ok(e, "batch field_step")) return PP_E_HIP;
 
     // ---- host bookkeeping (tile starts and pending orders after the sort) ------------------
+    bool noconv = false;
     for (int i = 0; i < n; ++i) {
         pp_run* r = b->runs[i];
         for (int s = 0; s < PP_MAX_SPECIES; ++s)
             if (r->sp[s].active) sort_enqueued(r, s);
         r->step += 1;
+        noconv = noconv || !r->jac_converged;
     }
-    return PP_OK;
+    // every member stepped; a member's relaxation could not reach its tolerance
+    return noconv ? PP_E_NOCONV : PP_OK;
 }
 
 pp_status pp_batch_destroy(pp_batch* b) {

@@ -721,6 +721,7 @@ static hipError_t relax_setup(pp_run* r, double dt, pp_run::RelaxSet& S) {
     }
     S.sweeps = sweeps;
     S.bound = bound;
+    S.converged = bound <= r->p.relax_tol;
     // omega_1 = 1, omega_2 = 1 / (1 - r^2/2), omega_{k+1} = 1 / (1 - r^2 omega_k / 4)
     const int n_om = r->p.relax_max_iter + 2;
     double* om = new (std::nothrow) double[n_om];
@@ -741,6 +742,7 @@ void use_relax_set(pp_run* r, int k) {
     r->relax_r = S.r;
     r->jac_sweeps = S.sweeps;
     r->jac_bound = S.bound;
+    r->jac_converged = S.converged;
     r->omega = S.omega;
     r->dt_drift = S.drift;
 }

@@ -108,6 +108,7 @@ struct pp_run {
     double relax_r = 0.0;    // spectral radius of the extrapolated iteration
     int jac_sweeps = 0;      // relaxation sweeps per field step
     double jac_bound = 0.0;  // error reduction bound after jac_sweeps sweeps
+    bool jac_converged = true;  // jac_bound <= relax_tol (false: capped by relax_max_iter)
     double* omega = nullptr; // Chebyshev weights (device, relax_max_iter + 2)
     double gauss_kappa = 0.0; // damping of the Gauss-law filter: 1 / max |K|^2
     // time step of the particle and field kernels: kick (momentum update) and drift
@@ -119,6 +120,7 @@ struct pp_run {
     struct RelaxSet {
         double drift = 0.0, diagA = 1.0, jac_rho = 0.0, gamma = 1.0, r = 0.0, bound = 0.0;
         int sweeps = 0;
+        bool converged = true;
         double* omega = nullptr;
     } rs[3];
     int nrs = 1;

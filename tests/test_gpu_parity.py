@@ -615,3 +615,23 @@ def test_bad_particles_are_flagged_kept_and_left_out(ppm, orc):
     # flags are cleared once read
     assert run.diagnostics().flags == 0
     run.close()
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_capped_relaxation_reports_noconv_and_still_steps(ppm, orc, order):
+    # relax_max_iter too small for relax_tol: the field step is completed with the capped
+    # sweeps and reports PP_E_NOCONV; the diagnostics give the bound reached
+    n = (8, 8, 8)
+    species, E, B = random_state(orc, n, 2, seed=51, uth=0.2)
+    P = ppm.make_params(n=n, dt=0.4, shape_order=3, field_order=4, precision=ppm.PP_PREC_FP32_SPLIT,
+                        relax_tol=1e-14, relax_max_iter=2, time_order=order)
+    run = ppm.Run(P, _split_species(species, n, 3), E=E, B=B)
+    with pytest.raises(ppm.PPError) as ei:
+        run.step()
+    assert ei.value.status == ppm.PP_E_NOCONV
+    d = run.diagnostics(ppm.PP_DIAG_MOMENTS)
+    assert d.step == 1 and d.flags == 0
+    assert d.relax_iters == 2 and d.relax_resid > 1e-14
+    Eg, Bg, _ = run.fields()
+    assert np.max(np.abs(Eg - E)) > 0 and np.max(np.abs(Bg - B)) > 0  # the fields advanced
+    run.close()
