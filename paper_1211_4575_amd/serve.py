@@ -233,7 +233,12 @@ class DeviceBackend:
         return run
 
     def step(self):
-        self.pp.pp_batch_step(self.batch)
+        try:
+            self.pp.pp_batch_step(self.batch)
+        except self.pp.PPError as e:
+            # a member's relaxation capped by its relax_max_iter: the step was still taken
+            if e.status != self.pp.PP_E_NOCONV:
+                raise
         ev = self.torch.cuda.Event(enable_timing=True)
         ev.record(self.stream)
         return ev
