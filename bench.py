@@ -626,8 +626,8 @@ def main(argv=None):
     ap.add_argument("--ref-steps", type=int, default=3, help="serving: timed steps per class for the references")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
-              f"of this path is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): sharding the path over "
+              f"GPUs (sub-boxes of whole tiles with halo exchange) is not built.", file=sys.stderr)
         return 2
 
     import torch
