@@ -418,8 +418,7 @@ static hipError_t launch_rho32(pp_run* r, unsigned mask) {
         if (!(mask & (1u << s))) continue;
         const Species& S = r->sp[s];
         Rho32Sp& D = A.sp[A.nsp++];
-        // with a sort order pending, the buffers still follow the previous tile starts
-        D.start = S.pending ? S.offsets_next : S.offsets;
+        D.start = S.offsets;
         D.cell = (const int32_t*)S.cur.cell;
         for (int d = 0; d < 3; ++d) D.pos[d] = (const float*)S.cur.pos[d];
         D.qw = S.q * S.w;
@@ -465,6 +464,12 @@ static hipError_t launch_rho32(pp_run* r, unsigned mask) {
 hipError_t deposit_rho_all(pp_run* r) {
     const int64_t nc = r->g.ncell;
     const bool split = r->p.precision == PP_PREC_FP32_SPLIT;
+    if (split) {
+        // a pending sort order is applied first: in the order it replaces, the particles that
+        // changed tile would miss their workgroup's LDS block and take global atomics
+        hipError_t e = materialize(r, -1);
+        if (e != hipSuccess) return e;
+    }
     unsigned tiled = 0;
     if (split)
         for (int s = 0; s < PP_MAX_SPECIES; ++s) {
@@ -488,8 +493,8 @@ hipError_t deposit_rho_all(pp_run* r) {
 hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out) {
     const int bs = 256;
     const int64_t nc = r->g.ncell;
-    // a pending sort order needs no move here: the moments are sums over every particle and
-    // the charge deposit follows the tile starts of the buffers as they are
+    // the moments are sums over every particle: a pending sort order needs no move for them
+    // (the charge deposit applies it)
     hipError_t e = launch_fill(r->dacc, ACC_COUNT, 0.0, r->stream);
     if (e != hipSuccess) return e;
     const bool split = r->p.precision == PP_PREC_FP32_SPLIT;
