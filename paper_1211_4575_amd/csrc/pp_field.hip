@@ -234,12 +234,13 @@ __global__ void __launch_bounds__(FIELD_BS) k_field_batch(const FieldDesc* __res
 // The arithmetic and the order of the sums are those of relax_body, so both give the same
 // bits (the batched path keeps relax_body).
 constexpr int RX_TX = 32, RX_TY = 8, RX_ZC = 32;
-constexpr int64_t RX_MIN_BLOCKS = 1024;  // 4 columns per CU
+constexpr int RX_BS = RX_TX * RX_TY;  // one thread per column of the tile
+constexpr int64_t RX_MIN_BLOCKS = 1024 * 256 / RX_BS;  // 1024 threads' columns per CU
 
 template <int R>
-__global__ void __launch_bounds__(256) k_relax_tiled(FieldDesc D, int k) {
+__global__ void __launch_bounds__(RX_BS) k_relax_tiled(FieldDesc D, int k) {
     constexpr int W = RX_TX + 2 * R, H = RX_TY + 2 * R;
-    constexpr int NH = (W * H + 255) / 256;  // ring entries a thread may stage per plane
+    constexpr int NH = (W * H + RX_BS - 1) / RX_BS;  // ring entries a thread may stage per plane
     __shared__ double pl[W * H];
     const FieldGeom& G = D.G;
     const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
@@ -267,7 +268,7 @@ __global__ void __launch_bounds__(256) k_relax_tiled(FieldDesc D, int k) {
     int hl[NH], hg[NH];
 #pragma unroll
     for (int e = 0; e < NH; ++e) {
-        const int h = threadIdx.x + 256 * e;
+        const int h = threadIdx.x + RX_BS * e;
         const int a = h % W, bb = h / W;
         const bool ring = h < W * H && !(a >= R && a < R + RX_TX && bb >= R && bb < R + RX_TY);
         hl[e] = ring ? h : -1;
@@ -343,7 +344,7 @@ struct TileCtx {
 
 template <int R>
 struct Ring {  // this thread's entries of the x-y ring of a plane: LDS index (-1: none), offset
-    static constexpr int W = RX_TX + 2 * R, H = RX_TY + 2 * R, NH = (W * H + 255) / 256;
+    static constexpr int W = RX_TX + 2 * R, H = RX_TY + 2 * R, NH = (W * H + RX_BS - 1) / RX_BS;
     int hl[NH], hg[NH];
 };
 
@@ -370,7 +371,7 @@ __device__ __forceinline__ void tile_ctx(const FieldGeom& G, TileCtx& X, Ring<R>
     X.small = G.small;
 #pragma unroll
     for (int e = 0; e < Ring<R>::NH; ++e) {
-        const int h = threadIdx.x + 256 * e;
+        const int h = threadIdx.x + RX_BS * e;
         const int a = h % W, bb = h / W;
         const bool ring = h < W * H && !(a >= R && a < R + RX_TX && bb >= R && bb < R + RX_TY);
         g.hl[e] = ring ? h : -1;
@@ -546,7 +547,7 @@ __device__ __forceinline__ void update_E_tiled_comp(const FieldDesc& D, const Ti
 enum CurlKind { CK_RHS = 0, CK_UPDATE_E = 1 };
 
 template <int M, int KIND>
-__global__ void __launch_bounds__(256) k_curl_tiled(FieldDesc D) {
+__global__ void __launch_bounds__(RX_BS) k_curl_tiled(FieldDesc D) {
     constexpr int R = 2 * M - 1;
     __shared__ double lds[5 * Ring<R>::W * Ring<R>::H];
     TileCtx X;
@@ -566,11 +567,11 @@ __global__ void __launch_bounds__(256) k_curl_tiled(FieldDesc D) {
 template <int KIND>
 static void launch_curl_tiled(const FieldDesc& D, int64_t blocks, hipStream_t st) {
     if (D.G.M == 3)
-        hipLaunchKernelGGL((k_curl_tiled<3, KIND>), dim3((unsigned)blocks), dim3(256), 0, st, D);
+        hipLaunchKernelGGL((k_curl_tiled<3, KIND>), dim3((unsigned)blocks), dim3(RX_BS), 0, st, D);
     else if (D.G.M == 2)
-        hipLaunchKernelGGL((k_curl_tiled<2, KIND>), dim3((unsigned)blocks), dim3(256), 0, st, D);
+        hipLaunchKernelGGL((k_curl_tiled<2, KIND>), dim3((unsigned)blocks), dim3(RX_BS), 0, st, D);
     else
-        hipLaunchKernelGGL((k_curl_tiled<1, KIND>), dim3((unsigned)blocks), dim3(256), 0, st, D);
+        hipLaunchKernelGGL((k_curl_tiled<1, KIND>), dim3((unsigned)blocks), dim3(RX_BS), 0, st, D);
 }
 
 static int64_t relax_tiled_blocks(const FieldGeom& G) {
@@ -795,11 +796,11 @@ hipError_t launch_field_step(pp_run* r) {
         if (tb < RX_MIN_BLOCKS)
             hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_JACOBI, k);
         else if (D.G.R == 5)
-            hipLaunchKernelGGL(k_relax_tiled<5>, rgrid, dim3(256), 0, r->stream, D, k);
+            hipLaunchKernelGGL(k_relax_tiled<5>, rgrid, dim3(RX_BS), 0, r->stream, D, k);
         else if (D.G.R == 3)
-            hipLaunchKernelGGL(k_relax_tiled<3>, rgrid, dim3(256), 0, r->stream, D, k);
+            hipLaunchKernelGGL(k_relax_tiled<3>, rgrid, dim3(RX_BS), 0, r->stream, D, k);
         else
-            hipLaunchKernelGGL(k_relax_tiled<1>, rgrid, dim3(256), 0, r->stream, D, k);
+            hipLaunchKernelGGL(k_relax_tiled<1>, rgrid, dim3(RX_BS), 0, r->stream, D, k);
     }
     if (tb < RX_MIN_BLOCKS)
         hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_UPDATE_E, 0);

@@ -517,6 +517,22 @@ def test_host_validation_rejects_bad_params(ppm):
         with pytest.raises(ppm.PPError) as ei:
             ppm.pp_create(p, mesh, 0)
         assert ei.value.status == code, kw
+    # species arguments, checked before any pointer is used: counts past the int32 index
+    # range, negative counts, missing buffers, species slots and non-finite charges
+    for prec in (ppm.PP_PREC_FP64, ppm.PP_PREC_FP32_SPLIT):
+        h = ppm.pp_create(ppm.make_params((4, 4, 4), precision=prec), mesh, 0)
+        try:
+            cases = [(dict(n=2 ** 31), 0, 1.0, ppm.PP_E_CAPACITY), (dict(n=-1), 0, 1.0, ppm.PP_E_CAPACITY),
+                     (dict(n=8), 0, 1.0, ppm.PP_E_ARG), (dict(n=0), ppm.PP_MAX_SPECIES, 1.0, ppm.PP_E_ARG),
+                     (dict(n=0), 0, float("nan"), ppm.PP_E_NONFINITE)]
+            for fields, s, q, code in cases:
+                parts = ppm.pp_particles()
+                parts.n = fields["n"]
+                with pytest.raises(ppm.PPError) as ei:
+                    ppm.pp_init_species(h, s, q, 1.0, 1.0, parts)
+                assert ei.value.status == code, (prec, fields, s, q)
+        finally:
+            ppm.pp_destroy(h)
 
 
 def test_fp32_push_requires_sort(ppm, orc):
