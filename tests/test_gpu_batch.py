@@ -51,7 +51,7 @@ DIRECT_RUNS = (1,)  # runs with the direct current (no line solve) in the batch
 CROWDED_RUNS = (3,)  # runs with one cell holding more ranks than the sort's round table
 
 
-def _make(ppm, orc, k):
+def _make(ppm, orc, k, O=3):
     n, ppc, fo, pusher, d, dt, _, _ = RUNS[k]
     species, E, B = random_state(orc, n, ppc, seed=700 + k, d=d)
     if k in CROWDED_RUNS:
@@ -60,10 +60,10 @@ def _make(ppm, orc, k):
             more = rng.uniform(0, 1, (3, 400)) * 0.9 + np.array([[3.05], [2.05], [1.05]])
             sp["pos"] = np.ascontiguousarray(np.concatenate([sp["pos"], more], axis=1))
             sp["u"] = np.ascontiguousarray(np.concatenate([sp["u"], rng.normal(0, 0.2, (3, 400))], axis=1))
-    P = ppm.make_params(n=n, d=d, dt=dt, shape_order=3, field_order=fo, pusher=pusher,
+    P = ppm.make_params(n=n, d=d, dt=dt, shape_order=O, field_order=fo, pusher=pusher,
                         precision=ppm.PP_PREC_FP32_SPLIT, relax_tol=1e-14, relax_max_iter=200,
                         current_scheme=ppm.PP_CURRENT_DIRECT if k in DIRECT_RUNS else ppm.PP_CURRENT_CC)
-    return ppm.Run(P, _split_species(species, n, 3), E=E, B=B)
+    return ppm.Run(P, _split_species(species, n, O), E=E, B=B)
 
 
 def _state(run):
@@ -85,13 +85,14 @@ def _assert_same(a, b, what):
             assert np.array_equal(x[key], y[key]), f"{what}: species {s} {key} differs"
 
 
-def test_batch_equals_alone(ppm, orc):
+@pytest.mark.parametrize("O", [2, 3], ids=["quadratic", "cubic"])
+def test_batch_equals_alone(ppm, orc, O):
     import torch
     stream = torch.cuda.current_stream().cuda_stream
     alone = []
     for k, case in enumerate(RUNS):
-        _say("alone", k, case)
-        r = _make(ppm, orc, k)
+        _say("alone", k, case, O)
+        r = _make(ppm, orc, k, O)
         for _ in range(case[7]):
             r.step()
         d = r.diagnostics(ppm.PP_DIAG_MOMENTS)
@@ -99,7 +100,7 @@ def test_batch_equals_alone(ppm, orc):
         alone.append(_state(r))
         r.close()
 
-    runs = [_make(ppm, orc, k) for k in range(len(RUNS))]
+    runs = [_make(ppm, orc, k, O) for k in range(len(RUNS))]
     left = [case[7] for case in RUNS]
     batch = ppm.pp_batch_create(8, stream)
     try:
