@@ -93,6 +93,8 @@ FP32_CASES = [
     ((9, 7, 5), 3, 3, 4),
     ((64, 1, 1), 16, 3, 6),
     ((6, 2, 12), 3, 2, 4),
+    ((16, 8, 1), 4, 2, 6),  # flat 8x8x1 tiles, quadratic weights
+    ((24, 16, 1), 3, 3, 4),  # flat 8x8x1 tiles with a ragged tile row, cubic weights
 ]
 
 
