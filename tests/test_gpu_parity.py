@@ -98,14 +98,22 @@ FP32_CASES = [
 ]
 
 
-@pytest.mark.parametrize("ci", range(len(FP32_CASES)), ids=[str(c) for c in FP32_CASES])
+# cases with the Boris pusher and stronger fields (the FP32 cases above use Vay's)
+FP32_BORIS_CASES = [((9, 7, 5), 3, 3, 4), ((16, 8, 1), 4, 2, 2)]
+
+
+@pytest.mark.parametrize("ci", range(len(FP32_CASES) + len(FP32_BORIS_CASES)),
+                         ids=[str(c) for c in FP32_CASES] + ["boris" + str(c) for c in FP32_BORIS_CASES])
 def test_fp32_split_one_step_matches_oracle(ppm, orc, ci):
-    case = FP32_CASES[ci]
+    boris = ci >= len(FP32_CASES)
+    case = FP32_BORIS_CASES[ci - len(FP32_CASES)] if boris else FP32_CASES[ci]
     n, ppc, O, fo = case
-    _say("fp32 one step", case)
-    species, E, B = random_state(orc, n, ppc, seed=200 + ci, uth=0.2)
+    _say("fp32 one step", case, "boris" if boris else "vay")
+    species, E, B = random_state(orc, n, ppc, seed=200 + ci, uth=0.2, e_amp=0.2 if boris else 0.05,
+                                 b_amp=1.0 if boris else 0.3)
     sp32 = _split_species(species, n, O)
-    kw = dict(n=n, dt=0.4, shape_order=O, field_order=fo, relax_tol=1e-14, relax_max_iter=200)
+    kw = dict(n=n, dt=0.4, shape_order=O, field_order=fo, relax_tol=1e-14, relax_max_iter=200,
+              pusher=1 if boris else 0)
     P = orc.make_params(**kw)
     ref = _orc_run(orc, P, [dict(s, u=s["u64"]) for s in sp32], E, B)
     ref.step()
