@@ -49,6 +49,7 @@ def _split_species(species, n, O):
 
 DIRECT_RUNS = (1,)  # runs with the direct current (no line solve) in the batch
 CROWDED_RUNS = (3,)  # runs with one cell holding more ranks than the sort's round table
+RAD_RUNS = (2,)  # runs with radiative cooling in the push
 
 
 def _make(ppm, orc, k, O=3):
@@ -62,7 +63,8 @@ def _make(ppm, orc, k, O=3):
             sp["u"] = np.ascontiguousarray(np.concatenate([sp["u"], rng.normal(0, 0.2, (3, 400))], axis=1))
     P = ppm.make_params(n=n, d=d, dt=dt, shape_order=O, field_order=fo, pusher=pusher,
                         precision=ppm.PP_PREC_FP32_SPLIT, relax_tol=1e-14, relax_max_iter=200,
-                        current_scheme=ppm.PP_CURRENT_DIRECT if k in DIRECT_RUNS else ppm.PP_CURRENT_CC)
+                        current_scheme=ppm.PP_CURRENT_DIRECT if k in DIRECT_RUNS else ppm.PP_CURRENT_CC,
+                        rad_tau=0.05 if k in RAD_RUNS else 0.0)
     return ppm.Run(P, _split_species(species, n, O), E=E, B=B)
 
 
