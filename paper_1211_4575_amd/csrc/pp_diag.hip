@@ -175,10 +175,17 @@ struct Rho32Sp {
     double qw;
 };
 
+// A workgroup deposits the particles stored in its tile's range; under a pending sort
+// order that range holds the particles of the tile before their last push, which may have
+// moved up to RHO_HALO cells out of it, so the LDS block covers that many cells around the
+// tile (particles further away, only in flagged states, take global atomics).
+constexpr int RHO_HALO = 2;
+
 struct Rho32Args {
     int n[3], t[3], nt[3];
-    int ext[3];  // LDS block extent per axis: t + O + 1 (1 on a single-cell axis)
-    int lo[3];   // halo below the tile: 1 (0 on a single-cell axis)
+    int ext[3];   // LDS block extent per axis: t + 2 RHO_HALO + O + 1 (1 on a single-cell axis)
+    int lo[3];    // nodes below the tile: RHO_HALO + 1 (0 on a single-cell axis)
+    int halo[3];  // cells around the tile deposited in the block: RHO_HALO (0 on a single-cell axis)
     int64_t nc;
     int nsp;
     Rho32Sp sp[PP_MAX_SPECIES];
@@ -200,17 +207,19 @@ __device__ __forceinline__ unsigned long long rho_pattern(double a, double b) {
     return (unsigned long long)__double_as_longlong(fma(a, b, RHO_MAGIC));
 }
 
-// 2^e with e = e0 - ceil(log2(N)), N the sum of the largest tile populations of the
-// deposited species: a contribution is at most 2^(50 - ceil log2 N) and an LDS node sum at
-// most 2^50 in magnitude.
-__global__ void k_rho_scale(const int32_t* __restrict__ tile_max, unsigned mask, int e0, double* scale) {
+// 2^e with e = e0 - ceil(log2(N)) - margin, N the sum of the largest tile populations of
+// the deposited species: a contribution is at most 2^(50 - ceil log2 N) and an LDS node sum
+// at most 2^50 in magnitude.  margin = 1 under a pending sort order, whose tile ranges are
+// the previous step's (their populations differ from the new ones by the particles that
+// changed tile).
+__global__ void k_rho_scale(const int32_t* __restrict__ tile_max, unsigned mask, int e0, int margin, double* scale) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     long long nb = 0;
     for (int s = 0; s < PP_MAX_SPECIES; ++s)
         if (mask & (1u << s)) nb += tile_max[s];
     int lg = 0;
     while ((1ll << lg) < nb) ++lg;
-    *scale = ldexp(1.0, e0 - lg);
+    *scale = ldexp(1.0, e0 - lg - margin);
 }
 
 template <int O>
@@ -237,20 +246,27 @@ __global__ void __launch_bounds__(256) k_rho32(Rho32Args A) {
             const int g[3] = {cell % A.n[0], (cell / A.n[0]) % A.n[1], cell / nxy};
             const float f[3] = {S.pos[0][p], S.pos[1][p], S.pos[2][p]};
             bool finite = true, in_block = true;
+            int ll[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 finite = finite && fabsf(f[d]) <= 1048576.0f;  // false for NaN and Inf as well
-                const int l = g[d] - org[d];
-                in_block = in_block && l >= 0 && l < A.t[d] && f[d] >= flo && f[d] < flo + 2.0f;
+                int l = g[d] - org[d];  // cell relative to the tile, nearest periodic image
+                if (l >= A.t[d] + A.halo[d])
+                    l -= A.n[d];
+                else if (l < -A.halo[d])
+                    l += A.n[d];
+                ll[d] = l;
+                in_block = in_block && l >= -A.halo[d] && l < A.t[d] + A.halo[d] && f[d] >= flo && f[d] < flo + 2.0f;
             }
             if (!finite) continue;  // reported by the error flags
             double w[3][O + 1];
             int i0[3];
             if (in_block) {
-                // support inside the block: nodes g - 1 .. g + O, i.e. block indices 0 .. t + O
+                // support inside the block: nodes of cells -halo .. t + halo - 1 around the tile,
+                // i.e. block indices 0 .. t + 2 halo + O
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
-                    i0[d] = weights_abs<O>((double)(g[d] - org[d] + A.lo[d]) + (double)f[d], w[d]);
+                    i0[d] = weights_abs<O>((double)(ll[d] + A.lo[d]) + (double)f[d], w[d]);
 #pragma unroll
                 for (int c = 0; c <= O; ++c) {
                     const int zc = A.ext[2] == 1 ? 0 : i0[2] + c;
@@ -413,12 +429,15 @@ static hipError_t launch_rho32(pp_run* r, unsigned mask) {
     Rho32Args A;
     const int O = r->p.shape_order;
     double qwmax = 0.0;
+    bool pending = false;
     A.nsp = 0;
     for (int s = 0; s < PP_MAX_SPECIES; ++s) {
         if (!(mask & (1u << s))) continue;
         const Species& S = r->sp[s];
         Rho32Sp& D = A.sp[A.nsp++];
-        D.start = S.offsets;
+        // with a sort order pending, the buffers still follow the previous tile starts
+        D.start = S.pending ? S.offsets_next : S.offsets;
+        pending = pending || S.pending;
         D.cell = (const int32_t*)S.cur.cell;
         for (int d = 0; d < 3; ++d) D.pos[d] = (const float*)S.cur.pos[d];
         D.qw = S.q * S.w;
@@ -430,8 +449,9 @@ static hipError_t launch_rho32(pp_run* r, unsigned mask) {
         A.t[d] = r->g.t[d];
         A.nt[d] = r->g.nt[d];
         const bool single = r->p.n[d] == 1;
-        A.ext[d] = single ? 1 : r->g.t[d] + O + 1;
-        A.lo[d] = single ? 0 : 1;
+        A.ext[d] = single ? 1 : r->g.t[d] + 2 * RHO_HALO + O + 1;
+        A.lo[d] = single ? 0 : RHO_HALO + 1;
+        A.halo[d] = single ? 0 : RHO_HALO;
         vol *= A.ext[d];
     }
     A.nc = r->g.ncell;
@@ -441,7 +461,7 @@ static hipError_t launch_rho32(pp_run* r, unsigned mask) {
     int e0 = 50 - (int)ceil(log2(qwmax));
     if (e0 > 1000) e0 = 1000;
     hipLaunchKernelGGL(k_rho_scale, dim3(1), dim3(64), 0, r->stream, (const int32_t*)r->tile_max, mask, e0,
-                       r->dacc + ACC_RHO_SCALE);
+                       pending ? 1 : 0, r->dacc + ACC_RHO_SCALE);
     hipError_t e = launch_fill((double*)r->Jq, A.nc, 0.0, r->stream);  // all-zero bits
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)vol * sizeof(unsigned long long);
@@ -464,12 +484,6 @@ static hipError_t launch_rho32(pp_run* r, unsigned mask) {
 hipError_t deposit_rho_all(pp_run* r) {
     const int64_t nc = r->g.ncell;
     const bool split = r->p.precision == PP_PREC_FP32_SPLIT;
-    if (split) {
-        // a pending sort order is applied first: in the order it replaces, the particles that
-        // changed tile would miss their workgroup's LDS block and take global atomics
-        hipError_t e = materialize(r, -1);
-        if (e != hipSuccess) return e;
-    }
     unsigned tiled = 0;
     if (split)
         for (int s = 0; s < PP_MAX_SPECIES; ++s) {
@@ -493,8 +507,8 @@ hipError_t deposit_rho_all(pp_run* r) {
 hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out) {
     const int bs = 256;
     const int64_t nc = r->g.ncell;
-    // the moments are sums over every particle: a pending sort order needs no move for them
-    // (the charge deposit applies it)
+    // a pending sort order needs no move here: the moments are sums over every particle and
+    // the charge deposit follows the tile starts of the buffers as they are
     hipError_t e = launch_fill(r->dacc, ACC_COUNT, 0.0, r->stream);
     if (e != hipSuccess) return e;
     const bool split = r->p.precision == PP_PREC_FP32_SPLIT;
