@@ -365,20 +365,25 @@ def test_fp32_charge_density_matches_oracle(ppm, orc, ci):
     run = ppm.Run(ppm.make_params(n=n, shape_order=O, field_order=6, precision=ppm.PP_PREC_FP32_SPLIT,
                                   rho_background=-mean), sp32)
 
-    def check(tag):
+    def oracle_rho():
         rho = np.zeros((n[2], n[1], n[0]))
         for s, sp in enumerate(sp32):
             g = run.particles(s)
             orc.deposit_rho(P, sp["q"], sp["w"], np.ascontiguousarray(I.from_split(g["cell"], g["pos"], n)), rho)
+        return rho
+
+    def check(tag, rho):
         run.E.copy_(ppm_tensor(run, poisson_E(orc, P, rho)))
         d = run.diagnostics(ppm.PP_DIAG_RHO)
         assert d.gauss_max / d.rho_ref < 1e-10, (tag, d.gauss_max)
 
-    check("loaded")
+    check("loaded", oracle_rho())
     run.gather_push_deposit()
-    check("pushed")
-    run.sort()
-    check("sorted again")
+    rho = oracle_rho()
+    check("pushed", rho)
+    run.sort()  # the new order stays pending: the deposit reads the previous tile ranges
+    check("sorted again, order pending", rho)
+    check("sorted again, order applied", oracle_rho())
     run.close()
 
 
