@@ -39,3 +39,34 @@ def test_two_stream_rate_matches_the_cold_dispersion_relation():
     w = 1j * g
     assert abs(a * (1 / (w - k * v0) ** 2 + 1 / (w + k * v0) ** 2) - 1.0) < 1e-12
     assert abs(g - 0.342867) < 1e-6
+
+
+def test_lds_model_bound_from_its_instruction_counts():
+    # cubic weights: 300 64-bit atomics at 6.3 clk and 192 paired reads at 4 clk per 64
+    # particles, 256 CUs at 2.4 GHz
+    clk = (300 * 6.3 + 192 * 4.0) / 64.0
+    assert bench.lds_bound_updates_per_s(3) == 256 * 2.4e9 / clk
+    # quadratic weights: 3 * 3 * 4 * 4 atomics and 6 * 27 / 2 paired reads
+    clk2 = (144 * 6.3 + 81 * 4.0) / 64.0
+    assert bench.lds_bound_updates_per_s(2) == 256 * 2.4e9 / clk2
+
+
+def test_measured_traffic_is_used_only_for_the_kernel_sources_it_was_taken_on(monkeypatch):
+    import os
+    vals = {}
+    for line in open(os.path.join(bench.ROOT, "profiles", "k_gpd32_pair_mj_256_counters.md")):
+        line = line.strip()
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            vals[k] = v
+    n = int(vals["particles"])
+    per_byte_f = float(vals["copy_fetch_kib"]) * 1024.0 / float(vals["copy_bytes"])
+    per_byte_w = float(vals["copy_write_kib"]) * 1024.0 / float(vals["copy_bytes"])
+    want = (float(vals["fetch_kib_per_launch"]) * 1024.0 / per_byte_f
+            + float(vals["write_kib_per_launch"]) * 1024.0 / per_byte_w)
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: vals["kernel_source_digest"])
+    assert bench.measured_traffic(n) == want
+    assert 1.0 < want / (56.0 * n) < 10.0  # against the algorithmic 56 B per particle
+    assert bench.measured_traffic(n + 1) is None  # another workload
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0" * 16)
+    assert bench.measured_traffic(n) is None  # counters taken on other kernel sources
