@@ -214,7 +214,10 @@ pp_status pp_field_step(pp_run* run);
 
 /* Counting sort of species s (-1 = all) by tile-major cell key (Sec. III: the
  * particle arrays are sorted by cell between steps 3 and 4).  The order inside a
- * cell is unspecified.  The current and alternate buffers swap roles. */
+ * cell is unspecified.  The current and alternate buffers swap roles.  FP32_SPLIT:
+ * after a push the sort computes the new order only; the particles are moved into it
+ * by the next pp_gather_push_deposit (together with their update) or by
+ * pp_get_particles, whichever comes first. */
 pp_status pp_sort_particles(pp_run* run, int32_t s);
 
 /* One whole time step in the run's time order (Sec. III step list): for time_order 2,
@@ -231,7 +234,9 @@ pp_status pp_step(pp_run* run);
  * run's stream. */
 pp_status pp_diagnostics(pp_run* run, uint32_t what, pp_diag* out);
 
-/* Current buffer assignment of species s after sorts (host struct). */
+/* Current buffer assignment of species s after sorts (host struct), with the particles
+ * in sorted order: a new order left pending by pp_sort_particles is applied first
+ * (enqueued on the run's stream). */
 pp_status pp_get_particles(pp_run* run, int32_t s, pp_particles* out);
 
 /* Time of the gather/push/deposit kernels: when enabled, HIP events bracket every
