@@ -23,6 +23,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     int32_t n[3];         /* cells per dimension                              */
@@ -337,45 +340,76 @@ int orc_step_species(const orc_params* P, double q, double m, double w, int64_t 
     return orc_step_species_kd(P, P->dt, q, m, w, n, pos, u, E, B, J);
 }
 
+/* One particle of the loop below: returns its flags; a non-finite particle is left as it
+ * was and deposits nothing. */
+static int step_one(const orc_params* P, double kick, double q, double m, double w, int64_t n, int64_t p, double* pos,
+                    double* u, const double* E, const double* B, double* J) {
+    int flags = 0;
+    const double c = P->c;
+    double X0[3], X1[3], up[3], Ep[3], Bp[3];
+    for (int d = 0; d < 3; ++d) {
+        X0[d] = pos[d * n + p];
+        up[d] = u[d * n + p];
+    }
+    orc_gather(P, E, B, X0, Ep, Bp);
+    orc_push_rad(P->pusher, q, m, kick, c, P->rad_tau, Ep, Bp, up);
+    double g = sqrt(1.0 + dot3(up, up) / (c * c));
+    for (int d = 0; d < 3; ++d) {
+        X1[d] = X0[d] + P->dt * up[d] / (g * P->d[d]);
+        if (fabs(X1[d] - X0[d]) >= 1.0) flags |= 1;
+        if (!isfinite(X1[d]) || !isfinite(up[d])) flags |= 2;
+    }
+    if (flags & 2) return flags;
+    if (P->current_scheme == 1) {
+        double Xm[3], v[3];
+        for (int d = 0; d < 3; ++d) {
+            Xm[d] = 0.5 * (X0[d] + X1[d]);
+            v[d] = up[d] / g;
+        }
+        deposit_direct_one(P, q, w, Xm, v, J);
+    } else {
+        deposit_current_one(P, q, w, X0, X1, J);
+    }
+    for (int d = 0; d < 3; ++d) {
+        double x = fmod(X1[d], (double)P->n[d]);
+        if (x < 0) x += P->n[d];
+        if (x >= P->n[d]) x -= P->n[d];
+        pos[d * n + p] = x;
+        u[d * n + p] = up[d];
+    }
+    return flags;
+}
+
 /* The same with a momentum update (kick) over `kick` and the drift, current and position
- * update over P->dt: one substep of a composition scheme. */
+ * update over P->dt: one substep of a composition scheme.
+ * OpenMP mode (built with -fopenmp; the paper's shared-memory pattern, Sec. IX.B "OpenMP":
+ * one current buffer per thread): the particles are split statically among the threads, each
+ * thread deposits into its own zeroed copy of J, and the copies are added to J afterwards, for
+ * every node in thread order.  Only the summation order of J differs from the plain build. */
 int orc_step_species_kd(const orc_params* P, double kick, double q, double m, double w, int64_t n, double* pos,
                         double* u, const double* E, const double* B, double* J) {
     int flags = 0;
-    const double c = P->c;
-    for (int64_t p = 0; p < n; ++p) {
-        double X0[3], X1[3], up[3], Ep[3], Bp[3];
-        for (int d = 0; d < 3; ++d) {
-            X0[d] = pos[d * n + p];
-            up[d] = u[d * n + p];
-        }
-        orc_gather(P, E, B, X0, Ep, Bp);
-        orc_push_rad(P->pusher, q, m, kick, c, P->rad_tau, Ep, Bp, up);
-        double g = sqrt(1.0 + dot3(up, up) / (c * c));
-        for (int d = 0; d < 3; ++d) {
-            X1[d] = X0[d] + P->dt * up[d] / (g * P->d[d]);
-            if (fabs(X1[d] - X0[d]) >= 1.0) flags |= 1;
-            if (!isfinite(X1[d]) || !isfinite(up[d])) flags |= 2;
-        }
-        if (flags & 2) continue;
-        if (P->current_scheme == 1) {
-            double Xm[3], v[3];
-            for (int d = 0; d < 3; ++d) {
-                Xm[d] = 0.5 * (X0[d] + X1[d]);
-                v[d] = up[d] / g;
+#ifdef _OPENMP
+    const int nt = omp_get_max_threads();
+    if (nt > 1) {
+        const size_t n3 = 3 * ncell(P);
+        double* priv = (double*)calloc((size_t)nt * n3, sizeof(double));
+        if (priv) {
+#pragma omp parallel reduction(| : flags)
+            {
+                double* Jt = priv + (size_t)omp_get_thread_num() * n3;
+#pragma omp for schedule(static)
+                for (int64_t p = 0; p < n; ++p) flags |= step_one(P, kick, q, m, w, n, p, pos, u, E, B, Jt);
             }
-            deposit_direct_one(P, q, w, Xm, v, J);
-        } else {
-            deposit_current_one(P, q, w, X0, X1, J);
-        }
-        for (int d = 0; d < 3; ++d) {
-            double x = fmod(X1[d], (double)P->n[d]);
-            if (x < 0) x += P->n[d];
-            if (x >= P->n[d]) x -= P->n[d];
-            pos[d * n + p] = x;
-            u[d * n + p] = up[d];
+#pragma omp parallel for schedule(static)
+            for (size_t i = 0; i < n3; ++i)
+                for (int t = 0; t < nt; ++t) J[i] += priv[(size_t)t * n3 + i];
+            free(priv);
+            return flags;
         }
     }
+#endif
+    for (int64_t p = 0; p < n; ++p) flags |= step_one(P, kick, q, m, w, n, p, pos, u, E, B, J);
     return flags;
 }
 
@@ -388,24 +422,47 @@ void orc_deposit_current(const orc_params* P, double q, double w, const double X
 /* Charge density, eq. "rho2": rho(node) += q w W(X - node), same       */
 /* weights as the field gather.  Accumulates.                           */
 /* ------------------------------------------------------------------ */
-void orc_deposit_rho(const orc_params* P, double q, double w, int64_t n, const double* pos, double* rho) {
+static void rho_one(const orc_params* P, double q, double w, int64_t n, int64_t p, const double* pos, double* rho) {
     const int O = P->shape_order;
     const double r = support_radius(O);
-    for (int64_t p = 0; p < n; ++p) {
-        double X[3];
-        int lo[3], hi[3];
-        for (int d = 0; d < 3; ++d) {
-            X[d] = pos[d * n + p];
-            lo[d] = (int)floor(X[d] - r);
-            hi[d] = (int)ceil(X[d] + r);
-        }
-        for (int k = lo[2]; k <= hi[2]; ++k)
-            for (int j = lo[1]; j <= hi[1]; ++j)
-                for (int i = lo[0]; i <= hi[0]; ++i) {
-                    double wt = orc_W(O, i - X[0]) * orc_W(O, j - X[1]) * orc_W(O, k - X[2]);
-                    if (wt != 0.0) rho[idx3(P, i, j, k)] += q * w * wt;
-                }
+    double X[3];
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        X[d] = pos[d * n + p];
+        lo[d] = (int)floor(X[d] - r);
+        hi[d] = (int)ceil(X[d] + r);
     }
+    for (int k = lo[2]; k <= hi[2]; ++k)
+        for (int j = lo[1]; j <= hi[1]; ++j)
+            for (int i = lo[0]; i <= hi[0]; ++i) {
+                double wt = orc_W(O, i - X[0]) * orc_W(O, j - X[1]) * orc_W(O, k - X[2]);
+                if (wt != 0.0) rho[idx3(P, i, j, k)] += q * w * wt;
+            }
+}
+
+/* OpenMP mode: one rho buffer per thread, added in thread order (as the current above). */
+void orc_deposit_rho(const orc_params* P, double q, double w, int64_t n, const double* pos, double* rho) {
+#ifdef _OPENMP
+    const int nt = omp_get_max_threads();
+    if (nt > 1) {
+        const size_t nc = ncell(P);
+        double* priv = (double*)calloc((size_t)nt * nc, sizeof(double));
+        if (priv) {
+#pragma omp parallel
+            {
+                double* rt = priv + (size_t)omp_get_thread_num() * nc;
+#pragma omp for schedule(static)
+                for (int64_t p = 0; p < n; ++p) rho_one(P, q, w, n, p, pos, rt);
+            }
+#pragma omp parallel for schedule(static)
+            for (size_t i = 0; i < nc; ++i)
+                for (int t = 0; t < nt; ++t) rho[i] += priv[(size_t)t * nc + i];
+            free(priv);
+            return;
+        }
+    }
+#endif
+    for (int64_t p = 0; p < n; ++p) rho_one(P, q, w, n, p, pos, rho);
 }
 
 /* ------------------------------------------------------------------ */
@@ -442,6 +499,7 @@ static void deriv(const orc_params* P, const double* f, double* out, int dim, in
     double a[3];
     const int M = fd_coeffs(P->field_order, a);
     const double inv = 1.0 / P->d[dim];
+#pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < P->n[2]; ++k)
         for (int j = 0; j < P->n[1]; ++j)
             for (int i = 0; i < P->n[0]; ++i) {
@@ -473,6 +531,7 @@ void orc_curl_up(const orc_params* P, const double* F, double* out) {
         int d1 = (comp + 1) % 3, d2 = (comp + 2) % 3;
         deriv(P, F + d2 * nc, out + comp * nc, d1, 1);
         deriv(P, F + d1 * nc, t, d2, 1);
+#pragma omp parallel for schedule(static)
         for (size_t q = 0; q < nc; ++q) out[comp * nc + q] -= t[q];
     }
     free(t);
@@ -486,6 +545,7 @@ void orc_curl_down(const orc_params* P, const double* F, double* out) {
         int d1 = (comp + 1) % 3, d2 = (comp + 2) % 3;
         deriv(P, F + d2 * nc, out + comp * nc, d1, 0);
         deriv(P, F + d1 * nc, t, d2, 0);
+#pragma omp parallel for schedule(static)
         for (size_t q = 0; q < nc; ++q) out[comp * nc + q] -= t[q];
     }
     free(t);
@@ -498,6 +558,7 @@ void orc_div_down(const orc_params* P, const double* F, double* out) {
     memset(out, 0, nc * sizeof(double));
     for (int d = 0; d < 3; ++d) {
         deriv(P, F + d * nc, t, d, 0);
+#pragma omp parallel for schedule(static)
         for (size_t q = 0; q < nc; ++q) out[q] += t[q];
     }
     free(t);
@@ -539,9 +600,11 @@ void orc_gauss_filter(const orc_params* P, double* E, const double* rho, int pas
     double* t = (double*)malloc(nc * sizeof(double));
     for (int it = 0; it < passes; ++it) {
         orc_div_down(P, E, r);
+#pragma omp parallel for schedule(static)
         for (size_t q = 0; q < nc; ++q) r[q] -= (rho[q] + P->rho_background) / P->eps0;
         for (int d = 0; d < 3; ++d) {
             deriv(P, r, t, d, 1);
+#pragma omp parallel for schedule(static)
             for (size_t q = 0; q < nc; ++q) E[d * nc + q] += kappa * t[q];
         }
     }
@@ -556,6 +619,7 @@ void orc_div_up(const orc_params* P, const double* F, double* out) {
     memset(out, 0, nc * sizeof(double));
     for (int d = 0; d < 3; ++d) {
         deriv(P, F + d * nc, t, d, 1);
+#pragma omp parallel for schedule(static)
         for (size_t q = 0; q < nc; ++q) out[q] += t[q];
     }
     free(t);
@@ -579,6 +643,7 @@ static void laplacian_B_component(const orc_params* P, int comp, const double* f
             deriv(P, f, t1, d, 0);
             deriv(P, t1, t2, d, 1);
         }
+#pragma omp parallel for schedule(static)
         for (size_t q = 0; q < nc; ++q) out[q] += t2[q];
     }
     free(t1);
@@ -607,6 +672,7 @@ static void apply_A(const orc_params* P, const double* Bk, double* out, double* 
     const size_t n3 = 3 * ncell(P);
     const double s = P->c * P->c * P->dt * P->dt;
     orc_laplacian_B(P, Bk, tmp);
+#pragma omp parallel for schedule(static)
     for (size_t q = 0; q < n3; ++q) out[q] = Bk[q] - P->alpha * P->alpha * s * tmp[q];
 }
 
@@ -626,10 +692,13 @@ int orc_field_step(const orc_params* P, double* E, double* B, const double* J, d
     memcpy(Bn, B, n3 * sizeof(double));
     /* right-hand side */
     orc_laplacian_B(P, Bn, tmp);
+#pragma omp parallel for schedule(static)
     for (size_t q = 0; q < n3; ++q) rhs[q] = Bn[q] + al * be * s * tmp[q];
     orc_curl_up(P, E, tmp);
+#pragma omp parallel for schedule(static)
     for (size_t q = 0; q < n3; ++q) rhs[q] -= P->dt * tmp[q];
     orc_curl_up(P, J, tmp);
+#pragma omp parallel for schedule(static)
     for (size_t q = 0; q < n3; ++q) rhs[q] += al * c2 * mu0 * P->dt * P->dt * tmp[q];
 
     /* diagonal of A on this periodic grid: (A e0)_0 for a unit impulse e0 */
@@ -639,6 +708,7 @@ int orc_field_step(const orc_params* P, double* E, double* B, const double* J, d
     for (int comp = 0; comp < 3; ++comp) diag[comp] = AB[comp * nc];
 
     double rhsmax = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : rhsmax)
     for (size_t q = 0; q < n3; ++q)
         if (fabs(rhs[q]) > rhsmax) rhsmax = fabs(rhs[q]);
 
@@ -648,23 +718,23 @@ int orc_field_step(const orc_params* P, double* E, double* B, const double* J, d
     for (;;) {
         apply_A(P, Bk, AB, tmp);
         res = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : res)
         for (size_t q = 0; q < n3; ++q) {
             double rq = rhs[q] - AB[q];
             if (fabs(rq) > res) res = fabs(rq);
         }
         res = rhsmax > 0.0 ? res / rhsmax : res;
         if (res <= P->relax_tol || it >= P->relax_max_iter) break;
-        for (int comp = 0; comp < 3; ++comp)
-            for (size_t q = 0; q < nc; ++q) {
-                size_t g = comp * nc + q;
-                Bk[g] += (rhs[g] - AB[g]) / diag[comp];
-            }
+#pragma omp parallel for schedule(static)
+        for (size_t g = 0; g < n3; ++g) Bk[g] += (rhs[g] - AB[g]) / diag[g / nc];
         ++it;
     }
 
     /* explicit E update */
+#pragma omp parallel for schedule(static)
     for (size_t q = 0; q < n3; ++q) tmp2[q] = al * Bk[q] + be * Bn[q];
     orc_curl_down(P, tmp2, tmp);
+#pragma omp parallel for schedule(static)
     for (size_t q = 0; q < n3; ++q) E[q] += c2 * P->dt * (tmp[q] - mu0 * J[q]);
     memcpy(B, Bk, n3 * sizeof(double));
     if (resid_out) *resid_out = res;
@@ -743,44 +813,58 @@ void orc_current_high_order(const orc_params* P, double* J) {
         const int N = P->n[dim];
         double* A = (double*)calloc((size_t)N * N, sizeof(double));
         int* piv = (int*)calloc(N, sizeof(int));
-        double* line = (double*)calloc(N, sizeof(double));
-        double* dJ = (double*)calloc(N, sizeof(double));
         for (int i = 0; i < N; ++i)
             for (int l = -(M - 1); l <= M - 1; ++l) A[i * N + wrapi(i + l, N)] += T[l < 0 ? -l : l];
         lu_factor(N, A, piv);
         double* Jc = J + dim * nc;
         int o1 = (dim + 1) % 3, o2 = (dim + 2) % 3;
-        for (int e = 0; e < P->n[o2]; ++e)
-            for (int b = 0; b < P->n[o1]; ++b) {
-                int ijk[3];
-                ijk[o1] = b;
-                ijk[o2] = e;
-                double mean2 = 0.0;
-                for (int i = 0; i < N; ++i) {
-                    ijk[dim] = i;
-                    line[i] = Jc[idx3(P, ijk[0], ijk[1], ijk[2])];
-                    mean2 += line[i];
+        /* every line is independent (OpenMP mode: lines split among the threads) */
+#pragma omp parallel
+        {
+            double* line = (double*)calloc(N, sizeof(double));
+            double* dJ = (double*)calloc(N, sizeof(double));
+#pragma omp for collapse(2) schedule(static)
+            for (int e = 0; e < P->n[o2]; ++e)
+                for (int b = 0; b < P->n[o1]; ++b) {
+                    int ijk[3];
+                    ijk[o1] = b;
+                    ijk[o2] = e;
+                    double mean2 = 0.0;
+                    for (int i = 0; i < N; ++i) {
+                        ijk[dim] = i;
+                        line[i] = Jc[idx3(P, ijk[0], ijk[1], ijk[2])];
+                        mean2 += line[i];
+                    }
+                    mean2 /= N;
+                    for (int i = 0; i < N; ++i) dJ[i] = line[i] - line[wrapi(i - 1, N)];
+                    lu_solve(N, A, piv, dJ);
+                    double acc = 0.0, meanO = 0.0;
+                    for (int i = 0; i < N; ++i) {
+                        acc += dJ[i];
+                        line[i] = acc;
+                        meanO += acc;
+                    }
+                    meanO /= N;
+                    for (int i = 0; i < N; ++i) {
+                        ijk[dim] = i;
+                        Jc[idx3(P, ijk[0], ijk[1], ijk[2])] = line[i] + (mean2 - meanO);
+                    }
                 }
-                mean2 /= N;
-                for (int i = 0; i < N; ++i) dJ[i] = line[i] - line[wrapi(i - 1, N)];
-                lu_solve(N, A, piv, dJ);
-                double acc = 0.0, meanO = 0.0;
-                for (int i = 0; i < N; ++i) {
-                    acc += dJ[i];
-                    line[i] = acc;
-                    meanO += acc;
-                }
-                meanO /= N;
-                for (int i = 0; i < N; ++i) {
-                    ijk[dim] = i;
-                    Jc[idx3(P, ijk[0], ijk[1], ijk[2])] = line[i] + (mean2 - meanO);
-                }
-            }
+            free(line);
+            free(dJ);
+        }
         free(A);
         free(piv);
-        free(line);
-        free(dJ);
     }
+}
+
+/* Threads the OpenMP build uses (1 for the plain build). */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------ */

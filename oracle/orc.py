@@ -18,15 +18,25 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "orc.c")
 _LIB = os.path.join(_HERE, "liborc.so")
+_LIB_OMP = os.path.join(_HERE, "liborc_omp.so")
+
+
+def _compile(out: str, extra, force: bool) -> str:
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", *extra, "-o", tmp, _SRC, "-lm"],
+                              stderr=subprocess.DEVNULL)
+        os.replace(tmp, out)
+    return out
 
 
 def build(force: bool = False) -> str:
-    """Compile orc.c into liborc.so with gcc (plain -O2, single thread)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile orc.c twice with gcc: liborc.so (plain -O2, scalar, single thread: the checker)
+    and liborc_omp.so (the same source with -fopenmp: loops over particles use one current
+    buffer per thread, loops over cells and lines are split among the threads).  Returns the
+    path of the plain library."""
+    _compile(_LIB_OMP, ["-fopenmp"], force)
+    return _compile(_LIB, [], force)
 
 
 class Params(ctypes.Structure):
@@ -86,16 +96,40 @@ def substep_params(P: Params, drift: float) -> Params:
     return Q
 
 
-_lib = None
+_libs = {}
+_use_omp = False
 _D = ctypes.POINTER(ctypes.c_double)
 _P = ctypes.POINTER(Params)
 
 
+class openmp:
+    """Context manager: inside it every oracle call goes to the OpenMP build (threads from
+    OMP_NUM_THREADS), outside it to the plain scalar build."""
+
+    def __enter__(self):
+        global _use_omp
+        self._prev, _use_omp = _use_omp, True
+        return self
+
+    def __exit__(self, *exc):
+        global _use_omp
+        _use_omp = self._prev
+        return False
+
+
+def num_threads() -> int:
+    """Threads the active build uses (1 for the plain build)."""
+    return int(lib().orc_num_threads())
+
+
 def lib():
-    global _lib
-    if _lib is None:
-        _lib = ctypes.CDLL(build())
-        L = _lib
+    key = "omp" if _use_omp else "plain"
+    if key not in _libs:
+        build()
+        _libs[key] = ctypes.CDLL(_LIB_OMP if _use_omp else _LIB)
+        L = _libs[key]
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_num_threads.argtypes = []
         L.orc_W.restype = ctypes.c_double
         L.orc_W.argtypes = [ctypes.c_int, ctypes.c_double]
         L.orc_gather.argtypes = [_P, _D, _D, _D, _D, _D]
@@ -126,7 +160,7 @@ def lib():
         L.orc_current_high_order.argtypes = [_P, _D]
         L.orc_species_moments.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int64, _D, _D, _D]
         L.orc_field_energy.argtypes = [_P, _D, _D, _D]
-    return _lib
+    return _libs[key]
 
 
 def _ptr(a: np.ndarray):
