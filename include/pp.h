@@ -259,7 +259,9 @@ pp_status pp_destroy(pp_run* run);
  * Calls that overlap on one batch race; one host thread per batch. */
 typedef struct pp_batch pp_batch;
 
-/* Create an empty batch for at most max_runs members on a HIP stream. */
+/* Create an empty batch for at most max_runs members on a HIP stream.  Also allocates two
+ * pinned host staging buffers of PP_BATCH_NOALLOC_TABLE_BYTES and, the first time on a GPU,
+ * looks up the device address of that GPU's static table array (pp_batch_step_noalloc). */
 pp_status pp_batch_create(int32_t max_runs, void* hip_stream, pp_batch** out);
 
 /* Add a run (PP_E_ARG if it cannot be batched, PP_E_CAPACITY if full, PP_E_STATE if it is
@@ -279,6 +281,27 @@ pp_status pp_batch_step(pp_batch* batch);
 
 /* Release the batch's own buffers (members are untouched). */
 pp_status pp_batch_destroy(pp_batch* batch);
+
+/* ---- the batch step without allocation ------------------------------------------------
+ * For callers that cannot allocate memory inside their stepping loop (tight serving loops,
+ * harnesses that forbid hipMalloc while they run): the same step as pp_batch_step (same
+ * kernels, bitwise the same results), but the step's descriptor tables (per member: kernel
+ * arguments, block prefixes, sort and field descriptors) go to a fixed array of
+ * PP_BATCH_NOALLOC_TABLE_BYTES in device memory instead of the batch's own growable buffer,
+ * staged through the pinned host buffers that pp_batch_create allocates.  The call itself
+ * allocates nothing, on the device or the host.
+ *  - The array is static: each GPU the library runs on holds one copy, from the first
+ *    pp_batch_create on it until the process ends.  It is shared by every batch on that GPU
+ *    and keeps the last call's tables; every call writes the whole part it reads, so nothing
+ *    has to start at zero.  Calls that overlap on one GPU (batches stepped from two threads,
+ *    or on two streams whose work overlaps) race on it and must be serialised by the caller.
+ *  - PP_E_CAPACITY, with nothing enqueued and a message in pp_last_hip_error, when the
+ *    members' tables need more than PP_BATCH_NOALLOC_TABLE_BYTES (about 5 KiB per member run
+ *    with two species); PP_E_STATE if the batch's GPU has no static array; otherwise the
+ *    statuses of pp_batch_step.
+ *  - The batch must be stepped on the GPU that was current at pp_batch_create. */
+enum { PP_BATCH_NOALLOC_TABLE_BYTES = 2 * 1024 * 1024 };
+pp_status pp_batch_step_noalloc(pp_batch* batch);
 
 /* Static description of a status code. */
 const char* pp_status_str(pp_status st);

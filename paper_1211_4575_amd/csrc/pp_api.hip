@@ -17,6 +17,11 @@ void set_hip_error(hipError_t e, const char* where) {
     snprintf(g_err, sizeof(g_err), "%s: %s", where, hipGetErrorString(e));
 }
 
+void set_error_text(const char* msg) {
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    snprintf(g_err, sizeof(g_err), "%s", msg);
+}
+
 // defined in the kernel translation units
 hipError_t field_setup(pp_run* r);
 int line_setup_axis(int order, int N, double* coef_host, int* off);

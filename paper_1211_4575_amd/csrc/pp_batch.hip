@@ -5,7 +5,9 @@
 // kernels run the same per-tile / per-cell bodies as the single-run launches, and every
 // reduction in the step is exact (integer) or fixed-order, so a run's results do not depend
 // on which other runs share its launches.
+#include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -17,8 +19,12 @@ void sort_desc(const pp_run* r, int s, SortDesc* D);
 
 struct pp_batch {
     hipStream_t stream = nullptr;
+    int device = 0;  // the GPU current at pp_batch_create (its static table array is used)
     int max_runs = 0;
     std::vector<pp_run*> runs;
+    // per-step index lists, reserved for max_runs entries at creation (a step never grows them)
+    std::vector<int> line_runs;
+    std::vector<int> slot_segs[PP_MAX_SPECIES];
     unsigned char* d_buf = nullptr;  // device copy of the step's descriptor tables
     size_t d_cap = 0;
     unsigned char* h_buf[2] = {nullptr, nullptr};  // pinned staging, used alternately
@@ -27,6 +33,12 @@ struct pp_batch {
     bool ev_used[2] = {false, false};
     int which = 0;
 };
+
+// Descriptor tables of pp_batch_step_noalloc: one fixed array per GPU for the life of the
+// process, shared by every batch on that GPU.  Host code never passes its name to a kernel or
+// a copy (on the host it is only a stand-in): it uses the device address obtained once per
+// device by table_array_setup.
+static __device__ __align__(256) unsigned char scratch[PP_BATCH_NOALLOC_TABLE_BYTES];
 
 namespace {
 
@@ -43,82 +55,64 @@ struct Layout {
     }
 };
 
-pp_status grow(pp_batch* b, size_t need) {
-    if (need <= b->d_cap && need <= b->h_cap) return PP_OK;
-    size_t cap = need * 2;
+constexpr int MAX_DEVICES = 64;
+std::mutex g_table_mu;
+unsigned char* g_table_ptr[MAX_DEVICES] = {};  // device address of `scratch` per GPU
+
+// Device address of the static table array on GPU `dev`, which must be the current device.
+pp_status table_array_setup(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) return PP_E_CAPACITY;
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    if (g_table_ptr[dev]) return PP_OK;
+    void* ptr = nullptr;
+    if (!ok(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress")) return PP_E_HIP;
+    g_table_ptr[dev] = (unsigned char*)ptr;
+    return PP_OK;
+}
+
+unsigned char* table_array(int dev) {
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    return dev >= 0 && dev < MAX_DEVICES ? g_table_ptr[dev] : nullptr;
+}
+
+// Pinned staging of at least `need` bytes (both halves).
+pp_status grow_host(pp_batch* b, size_t need) {
+    if (need <= b->h_cap) return PP_OK;
+    const size_t cap = need * 2;
     for (int i = 0; i < 2; ++i) {
         if (b->ev_used[i]) (void)hipEventSynchronize(b->ev[i]);
         if (b->h_buf[i]) (void)hipHostFree(b->h_buf[i]);
         b->h_buf[i] = nullptr;
         b->ev_used[i] = false;
     }
+    b->h_cap = 0;
+    for (int i = 0; i < 2; ++i)
+        if (!ok(hipHostMalloc((void**)&b->h_buf[i], cap, hipHostMallocDefault), "hipHostMalloc")) return PP_E_HIP;
+    b->h_cap = cap;
+    return PP_OK;
+}
+
+// The batch's own device table buffer of at least `need` bytes.
+pp_status grow_device(pp_batch* b, size_t need) {
+    if (need <= b->d_cap) return PP_OK;
+    const size_t cap = need * 2;
     if (b->d_buf) {
         (void)hipStreamSynchronize(b->stream);
         (void)hipFree(b->d_buf);
     }
     b->d_buf = nullptr;
-    b->d_cap = b->h_cap = 0;
+    b->d_cap = 0;
     if (!ok(hipMalloc((void**)&b->d_buf, cap), "hipMalloc")) return PP_E_HIP;
-    for (int i = 0; i < 2; ++i)
-        if (!ok(hipHostMalloc((void**)&b->h_buf[i], cap, hipHostMallocDefault), "hipHostMalloc")) return PP_E_HIP;
-    b->d_cap = b->h_cap = cap;
+    b->d_cap = cap;
     return PP_OK;
 }
 
-}  // namespace
+enum TableTarget { TABLES_OWN = 0, TABLES_STATIC = 1 };
 
-extern "C" {
-
-pp_status pp_batch_create(int32_t max_runs, void* hip_stream, pp_batch** out) {
-    if (!out || max_runs < 1 || max_runs > 4096) return PP_E_ARG;
-    *out = nullptr;
-    pp_batch* b = new (std::nothrow) pp_batch();
-    if (!b) return PP_E_CAPACITY;
-    b->stream = (hipStream_t)hip_stream;
-    b->max_runs = max_runs;
-    for (int i = 0; i < 2; ++i)
-        if (!ok(hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming), "hipEventCreate")) {
-            delete b;
-            return PP_E_HIP;
-        }
-    *out = b;
-    return PP_OK;
-}
-
-pp_status pp_batch_add(pp_batch* b, pp_run* r) {
-    if (!b || !r) return PP_E_ARG;
-    if ((int)b->runs.size() >= b->max_runs) return PP_E_CAPACITY;
-    for (pp_run* x : b->runs)
-        if (x == r) return PP_E_STATE;
-    if (r->p.precision != PP_PREC_FP32_SPLIT || !gpd32_batchable(r)) return PP_E_ARG;
-    if (r->stream != b->stream) return PP_E_ARG;
-    if (r->p.gauss_filter_passes > 0) return PP_E_ARG;  // the filter has no batched form
-    if (r->p.time_order != 2) return PP_E_ARG;          // the batch steps leapfrog steps
-    if (!b->runs.empty() && b->runs[0]->p.shape_order != r->p.shape_order) return PP_E_ARG;
-    for (int s = 0; s < PP_MAX_SPECIES; ++s)
-        if (r->sp[s].active && !r->sp[s].sorted) return PP_E_STATE;
-    b->runs.push_back(r);
-    return PP_OK;
-}
-
-pp_status pp_batch_remove(pp_batch* b, pp_run* r) {
-    if (!b || !r) return PP_E_ARG;
-    for (size_t i = 0; i < b->runs.size(); ++i)
-        if (b->runs[i] == r) {
-            b->runs.erase(b->runs.begin() + (long)i);
-            return PP_OK;
-        }
-    return PP_E_STATE;
-}
-
-pp_status pp_batch_size(const pp_batch* b, int32_t* n) {
-    if (!b || !n) return PP_E_ARG;
-    *n = (int32_t)b->runs.size();
-    return PP_OK;
-}
-
-pp_status pp_batch_step(pp_batch* b) {
-    if (!b) return PP_E_ARG;
+// One step of every member (the body of pp_batch_step and pp_batch_step_noalloc).  With
+// TABLES_OWN the batch's buffers grow as needed; with TABLES_STATIC nothing is allocated: the
+// tables go to the GPU's static array through the pinned staging made by pp_batch_create.
+pp_status batch_step(pp_batch* b, TableTarget target) {
     const int n = (int)b->runs.size();
     if (n == 0) return PP_OK;
     for (pp_run* r : b->runs)
@@ -126,14 +120,17 @@ pp_status pp_batch_step(pp_batch* b) {
             if (r->sp[s].active && !r->sp[s].sorted) return PP_E_STATE;
 
     // ---- layout of the step's descriptor tables --------------------------------------
-    std::vector<int> line_runs;
+    std::vector<int>& line_runs = b->line_runs;
+    line_runs.clear();
     for (int i = 0; i < n; ++i)
         if (uses_line_solve(b->runs[i])) line_runs.push_back(i);
     const int nl = (int)line_runs.size();
-    std::vector<int> slot_segs[PP_MAX_SPECIES];
-    for (int s = 0; s < PP_MAX_SPECIES; ++s)
+    std::vector<int>* slot_segs = b->slot_segs;
+    for (int s = 0; s < PP_MAX_SPECIES; ++s) {
+        slot_segs[s].clear();
         for (int i = 0; i < n; ++i)
             if (b->runs[i]->sp[s].active) slot_segs[s].push_back(i);
+    }
 
     Layout L;
     const size_t o_gpd = L.take(n * gpd32_args_size());
@@ -150,13 +147,29 @@ pp_status pp_batch_step(pp_batch* b) {
     }
     const size_t o_field = L.take(n * field_desc_size());
     const size_t o_cpre = L.take((n + 1) * sizeof(int64_t));
-    if (grow(b, L.off) != PP_OK) return PP_E_HIP;
+    unsigned char* D = nullptr;
+    if (target == TABLES_OWN) {
+        if (grow_host(b, L.off) != PP_OK || grow_device(b, L.off) != PP_OK) return PP_E_HIP;
+        D = b->d_buf;
+    } else {
+        if (L.off > (size_t)PP_BATCH_NOALLOC_TABLE_BYTES || L.off > b->h_cap) {
+            char msg[160];
+            snprintf(msg, sizeof msg, "pp_batch_step_noalloc: the step's tables need %zu bytes, above the static %d",
+                     L.off, (int)PP_BATCH_NOALLOC_TABLE_BYTES);
+            set_error_text(msg);
+            return PP_E_CAPACITY;
+        }
+        D = table_array(b->device);
+        if (!D) {
+            set_error_text("pp_batch_step_noalloc: no static table array on this batch's GPU");
+            return PP_E_STATE;
+        }
+    }
 
     const int w = b->which;
     if (b->ev_used[w] && !ok(hipEventSynchronize(b->ev[w]), "hipEventSynchronize")) return PP_E_HIP;
     unsigned char* H = b->h_buf[w];
     std::memset(H, 0, L.off);
-
     // ---- fill ------------------------------------------------------------------------
     int64_t* tpre = (int64_t*)(H + o_tpre);
     int64_t* fpre = (int64_t*)(H + o_fpre);
@@ -206,11 +219,10 @@ pp_status pp_batch_step(pp_batch* b) {
     }
 
     // ---- upload and launch -------------------------------------------------------------
-    if (!ok(hipMemcpyAsync(b->d_buf, H, L.off, hipMemcpyHostToDevice, b->stream), "hipMemcpyAsync")) return PP_E_HIP;
+    if (!ok(hipMemcpyAsync(D, H, L.off, hipMemcpyHostToDevice, b->stream), "hipMemcpyAsync")) return PP_E_HIP;
     if (!ok(hipEventRecord(b->ev[w], b->stream), "hipEventRecord")) return PP_E_HIP;
     b->ev_used[w] = true;
     b->which ^= 1;
-    unsigned char* D = b->d_buf;
     hipError_t e = launch_gpd32_batch(D + o_gpd, (const int64_t*)(D + o_tpre), tpre[n], D + o_fix,
                                       (const int64_t*)(D + o_fpre), fpre[n], n, b->runs[0]->p.shape_order,
                                       gpd32_lds_bytes(b->runs[0]), b->stream);
@@ -239,6 +251,86 @@ pp_status pp_batch_step(pp_batch* b) {
     }
     // every member stepped; a member's relaxation could not reach its tolerance
     return noconv ? PP_E_NOCONV : PP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pp_status pp_batch_create(int32_t max_runs, void* hip_stream, pp_batch** out) {
+    if (!out || max_runs < 1 || max_runs > 4096) return PP_E_ARG;
+    *out = nullptr;
+    pp_batch* b = new (std::nothrow) pp_batch();
+    if (!b) return PP_E_CAPACITY;
+    b->stream = (hipStream_t)hip_stream;
+    b->max_runs = max_runs;
+    b->runs.reserve(max_runs);
+    b->line_runs.reserve(max_runs);
+    for (auto& v : b->slot_segs) v.reserve(max_runs);
+    pp_status st = PP_OK;
+    if (!ok(hipGetDevice(&b->device), "hipGetDevice")) st = PP_E_HIP;
+    for (int i = 0; i < 2 && st == PP_OK; ++i)
+        if (!ok(hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming), "hipEventCreate")) st = PP_E_HIP;
+    // pinned staging large enough for the static table array, so that pp_batch_step_noalloc
+    // never needs to allocate; pp_batch_step grows it further when its tables need more
+    for (int i = 0; i < 2 && st == PP_OK; ++i)
+        if (!ok(hipHostMalloc((void**)&b->h_buf[i], PP_BATCH_NOALLOC_TABLE_BYTES, hipHostMallocDefault),
+                "hipHostMalloc"))
+            st = PP_E_HIP;
+    if (st == PP_OK) b->h_cap = PP_BATCH_NOALLOC_TABLE_BYTES;
+    if (st == PP_OK) st = table_array_setup(b->device);
+    if (st != PP_OK) {
+        for (int i = 0; i < 2; ++i) {
+            if (b->h_buf[i]) (void)hipHostFree(b->h_buf[i]);
+            if (b->ev[i]) (void)hipEventDestroy(b->ev[i]);
+        }
+        delete b;
+        return st;
+    }
+    *out = b;
+    return PP_OK;
+}
+
+pp_status pp_batch_add(pp_batch* b, pp_run* r) {
+    if (!b || !r) return PP_E_ARG;
+    if ((int)b->runs.size() >= b->max_runs) return PP_E_CAPACITY;
+    for (pp_run* x : b->runs)
+        if (x == r) return PP_E_STATE;
+    if (r->p.precision != PP_PREC_FP32_SPLIT || !gpd32_batchable(r)) return PP_E_ARG;
+    if (r->stream != b->stream) return PP_E_ARG;
+    if (r->p.gauss_filter_passes > 0) return PP_E_ARG;  // the filter has no batched form
+    if (r->p.time_order != 2) return PP_E_ARG;          // the batch steps leapfrog steps
+    if (!b->runs.empty() && b->runs[0]->p.shape_order != r->p.shape_order) return PP_E_ARG;
+    for (int s = 0; s < PP_MAX_SPECIES; ++s)
+        if (r->sp[s].active && !r->sp[s].sorted) return PP_E_STATE;
+    b->runs.push_back(r);
+    return PP_OK;
+}
+
+pp_status pp_batch_remove(pp_batch* b, pp_run* r) {
+    if (!b || !r) return PP_E_ARG;
+    for (size_t i = 0; i < b->runs.size(); ++i)
+        if (b->runs[i] == r) {
+            b->runs.erase(b->runs.begin() + (long)i);
+            return PP_OK;
+        }
+    return PP_E_STATE;
+}
+
+pp_status pp_batch_size(const pp_batch* b, int32_t* n) {
+    if (!b || !n) return PP_E_ARG;
+    *n = (int32_t)b->runs.size();
+    return PP_OK;
+}
+
+pp_status pp_batch_step(pp_batch* b) {
+    if (!b) return PP_E_ARG;
+    return batch_step(b, TABLES_OWN);
+}
+
+pp_status pp_batch_step_noalloc(pp_batch* b) {
+    if (!b) return PP_E_ARG;
+    return batch_step(b, TABLES_STATIC);
 }
 
 pp_status pp_batch_destroy(pp_batch* b) {

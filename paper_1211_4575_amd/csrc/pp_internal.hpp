@@ -150,6 +150,7 @@ constexpr double FR_DRIFT[3] = {0.5 * (1.0 - FR_THETA), 0.5 * (1.0 - FR_THETA), 
 void use_relax_set(pp_run* r, int k);  // make relaxation set k active
 
 void set_hip_error(hipError_t e, const char* where);
+void set_error_text(const char* msg);  // a library error message for pp_last_hip_error
 inline bool ok(hipError_t e, const char* where) {
     if (e != hipSuccess) {
         set_hip_error(e, where);

@@ -26,7 +26,7 @@ EXPORTED = ("pp_workspace_size", "pp_create", "pp_init_species", "pp_gather_push
             "pp_step",
             "pp_diagnostics", "pp_get_particles", "pp_timing_enable", "pp_timing_read", "pp_destroy",
             "pp_status_str", "pp_last_hip_error", "pp_batch_create", "pp_batch_add", "pp_batch_remove",
-            "pp_batch_size", "pp_batch_step", "pp_batch_destroy")
+            "pp_batch_size", "pp_batch_step", "pp_batch_destroy", "pp_batch_step_noalloc")
 
 
 class pp_params(ctypes.Structure):
@@ -126,6 +126,7 @@ def lib():
         L.pp_batch_remove.argtypes = [vp, vp]
         L.pp_batch_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
         L.pp_batch_step.argtypes = [vp]
+        L.pp_batch_step_noalloc.argtypes = [vp]
         L.pp_batch_destroy.argtypes = [vp]
         L.pp_status_str.argtypes = [ctypes.c_int32]
         L.pp_status_str.restype = ctypes.c_char_p
@@ -227,6 +228,10 @@ def pp_batch_size(batch) -> int:
 
 def pp_batch_step(batch):
     _check("pp_batch_step", lib().pp_batch_step(batch))
+
+
+def pp_batch_step_noalloc(batch):
+    _check("pp_batch_step_noalloc", lib().pp_batch_step_noalloc(batch))
 
 
 def pp_batch_destroy(batch):
