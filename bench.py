@@ -84,22 +84,85 @@ def time_steps(run, torch, steps, warmup):
     return (t1 - t0), ms_gpd / max(launches, 1)
 
 
-def cpu_baseline(n_sample=(16, 16, 16), ppc=32, steps=4):
-    """FP64 CPU oracle (single thread, as it stands) on a bounded sample of the workload:
-    the same particles-per-cell, momenta, shapes and field order on a 16^3 box."""
+def host_cpu():
+    """CPU model (from /proc/cpuinfo) and the number of cores this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def time_oracle(wl, steps, openmp):
+    """Seconds for `steps` whole oracle steps of workload `wl` (plain scalar build, or the
+    OpenMP build with one current buffer per thread) and the threads used."""
     from oracle import orc
-    from paper_1211_4575_amd import inputs as I
     orc.build()
-    wl = I.pair_maxwell_juttner(n=n_sample, ppc=ppc, theta=1.0)
     P = orc.make_params(**wl.params())
     run = orc.Run(P, [dict(q=s.q, m=s.m, w=s.w, pos=s.pos, u=s.u) for s in wl.species])
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        run.step()
-    dt = time.perf_counter() - t0
-    return dict(value=wl.n_particles * steps / dt, unit="particle updates/s", cores=1, kind="oracle",
-                sample=f"{n_sample[0]}x{n_sample[1]}x{n_sample[2]} box of the same workload "
-                       f"({wl.n_particles} particles), {steps} full steps, {dt:.1f} s")
+    if openmp:
+        with orc.openmp():
+            threads = orc.num_threads()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                run.step()
+            dt = time.perf_counter() - t0
+    else:
+        threads = 1
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run.step()
+        dt = time.perf_counter() - t0
+    return dt, threads
+
+
+def cpu_baseline(n_sample=(24, 24, 24), ppc=32, steps_one=1, steps_all=3):
+    """The FP64 CPU oracle, as it stands, on the host cores of this machine, on a bounded
+    sample of the benchmark's workload (pair plasma, Maxwell-Juettner kT = mc^2, cubic weights,
+    6th-order fields, same particles per cell) in a smaller box: the plain scalar build on one
+    core and the OpenMP build (one current buffer per thread) on every core this process may
+    use.  `value` is the all-core rate; the one-core rate is reported beside it."""
+    from paper_1211_4575_amd import inputs as I
+    model, cores = host_cpu()
+    os.environ.setdefault("OMP_NUM_THREADS", str(cores))
+    wl = I.pair_maxwell_juttner(n=n_sample, ppc=ppc, theta=1.0)
+    t1, _ = time_oracle(wl, steps_one, openmp=False)
+    tn, threads = time_oracle(wl, steps_all, openmp=True)
+    one = wl.n_particles * steps_one / t1
+    allc = wl.n_particles * steps_all / tn
+    return dict(value=allc, unit="particle updates/s", cores=threads, kind="oracle",
+                sample=f"{n_sample[0]}x{n_sample[1]}x{n_sample[2]} box of the same workload ({wl.n_particles} particles): "
+                       f"{steps_all} whole steps on {threads} threads (OpenMP build, {tn:.1f} s) and {steps_one} on one "
+                       f"core (plain build, {t1:.1f} s)",
+                one_core=one, cpu_model=model, nproc=cores)
+
+
+def cpu_plan():
+    """The whole CPU-baseline plan (a long run, not part of the default benchmark): the plain
+    heating workload in full (16^3, 8 per cell per species, TSC, 2nd-order fields, 100 steps)
+    and the pair plasma at 64^3 (32 per cell per species, cubic, 6th order) for 20 steps, each
+    on one core (plain build) and on every core (OpenMP build)."""
+    from paper_1211_4575_amd import inputs as I
+    model, cores = host_cpu()
+    os.environ.setdefault("OMP_NUM_THREADS", str(cores))
+    out = {"cpu_model": model, "nproc": cores, "runs": []}
+    plans = [("plain heating 16^3, TSC, 2nd order, 100 steps", I.plain_heating(), 100, 100),
+             ("pair plasma 64^3, 32 ppc/species, cubic, 6th order, 20 steps (one core: 2 steps)",
+              I.pair_maxwell_juttner(n=(64, 64, 64), ppc=32, theta=1.0), 2, 20)]
+    for name, wl, s1, sn in plans:
+        t1, _ = time_oracle(wl, s1, openmp=False)
+        log(f"[cpu-plan] {name}: one core {wl.n_particles * s1 / t1:.3e} updates/s ({t1:.1f} s)")
+        tn, threads = time_oracle(wl, sn, openmp=True)
+        log(f"[cpu-plan] {name}: {threads} threads {wl.n_particles * sn / tn:.3e} updates/s ({tn:.1f} s)")
+        out["runs"].append(dict(workload=name, particles=wl.n_particles, one_core=dict(steps=s1, s=t1,
+                                updates_per_s=wl.n_particles * s1 / t1),
+                                all_cores=dict(threads=threads, steps=sn, s=tn, updates_per_s=wl.n_particles * sn / tn)))
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def flops_per_update(O=3, direct=False):
@@ -520,6 +583,66 @@ def kh_bench(args, torch, pp):
     return 0
 
 
+def serving_leg(torch, pp, count=32, rate=4.0, slots=64, mem_gib=160.0, sample=4, no_fp64=False):
+    """A bounded serving run for the default benchmark line: `count` requests of the serving
+    ensemble (two-stream runs on 32^3 / 64x32x32 / 128x16x16 grids, 8-64 particles per cell per
+    beam, 200-2000 steps) arriving as a Poisson stream at `rate` per second, served by continuous
+    batching (FP32 split form).  Beside it, the `sample` requests with the fewest updates are run
+    one at a time, each whole, in the plain FP64 form and in the FP32 split form (measured, not
+    modelled), and the per-class model of the one-at-a-time service (measured steps of each
+    grid/lattice class x the request's steps) is checked against those runs and used for the
+    FIFO latency of the whole stream."""
+    from paper_1211_4575_amd import inputs as I
+    from paper_1211_4575_amd import serve as S
+    reqs = I.serving_requests(count=count, rate=rate, seed=SEED)
+    be = S.DeviceBackend(max_slots=slots)
+    try:
+        sched = S.Scheduler(be, mem_budget=int(mem_gib * (1 << 30)), max_slots=slots)
+        res = sched.run(reqs)
+        out = {"requests": count, "rate_per_s": rate, "batched_fp32": S.summarize(res, t_first=0.0),
+               "peak_members": sched.peak_members}
+        log(f"[serve-leg] batched: {out['batched_fp32']}")
+        small = sorted(reqs, key=lambda r: r.updates)[:sample]
+        measured = []
+        for q in small:
+            row = {"rid": q.rid, "grid": list(q.n), "ppc_per_beam": q.ppc, "steps": q.steps, "updates": q.updates}
+            for key, split in (("fp32_split_s", True), ("fp64_plain_s", False)):
+                if not split and no_fp64:
+                    continue
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                run = be.make_run(q, split=split)
+                for _ in range(q.steps):
+                    run.step()
+                torch.cuda.synchronize()
+                row[key] = time.perf_counter() - t0
+                run.close()
+            batched = next(r for r in res if r.rid == q.rid)
+            row["batched_latency_s"] = batched.latency
+            measured.append(row)
+            log(f"[serve-leg] alone: {row}")
+        out["alone_measured"] = measured
+        for name, split in (("fp64_plain_one_at_a_time", False), ("fp32_split_one_at_a_time", True)):
+            if not split and no_fp64:
+                continue
+            r1, per_class = S.one_at_a_time_reference(be, reqs, split=split, steps=3)
+            s1 = S.summarize(r1, t_first=0.0)
+            model = {r.rid: (r.done - r.admitted) for r in r1}
+            key = "fp32_split_s" if split else "fp64_plain_s"
+            s1["model_over_measured"] = [round(model[m["rid"]] / m[key], 3) for m in measured]
+            s1["kind"] = ("FIFO over the same arrivals; service time = measured per-step time of the request's "
+                          "grid/lattice class x its steps + set-up")
+            out[name] = s1
+            log(f"[serve-leg] {name}: {s1}")
+        if "fp64_plain_one_at_a_time" in out and out["batched_fp32"].get("updates_per_s"):
+            out["speedup_vs_fp64_one_at_a_time"] = (out["batched_fp32"]["updates_per_s"] /
+                                                   out["fp64_plain_one_at_a_time"]["updates_per_s"])
+        return out
+    finally:
+        be.close()
+        torch.cuda.empty_cache()
+
+
 def serving_bench(args, torch, pp):
     """The serving ensemble: a Poisson stream of two-stream requests (grids 32^3, 64x32x32,
     128x16x16; 8-64 particles per cell per beam; beam speed 0.1-0.5 c; 200-2000 steps), served
@@ -587,6 +710,19 @@ def serving_bench(args, torch, pp):
     return 0
 
 
+def lds_probe():
+    """Compile bench_lds_rates.hip (beside this file) for gfx950 and run it: the clocks per
+    wavefront instruction of the LDS and VALU instructions the particle kernel's cost model uses."""
+    import subprocess
+    src = os.path.join(ROOT, "bench_lds_rates.hip")
+    exe = os.path.join(ROOT, "_build", "bench_lds_rates")
+    os.makedirs(os.path.dirname(exe), exist_ok=True)
+    subprocess.check_call([os.environ.get("HIPCC", "/opt/rocm/bin/hipcc"), "-O3", "-std=c++17", "--offload-arch=gfx950",
+                           "-munsafe-fp-atomics", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", src,
+                           "-o", exe], stderr=subprocess.DEVNULL)
+    return subprocess.call([exe])
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -597,6 +733,8 @@ def main(argv=None):
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="leave out the bounded serving leg")
+    ap.add_argument("--serving-requests", type=int, default=32, help="requests of the bounded serving leg")
     ap.add_argument("--rad-tau", type=float, default=0.0, help="radiative cooling constant (0: off)")
     ap.add_argument("--current", choices=("cc", "direct"), default="cc",
                     help="current scheme: charge-conserving (default) or direct")
@@ -624,7 +762,15 @@ def main(argv=None):
     ap.add_argument("--slots", type=int, default=64, help="serving: most runs in the batch")
     ap.add_argument("--mem-gib", type=float, default=160.0, help="serving: device memory budget for runs")
     ap.add_argument("--ref-steps", type=int, default=3, help="serving: timed steps per class for the references")
+    ap.add_argument("--cpu-plan", action="store_true",
+                    help="time the CPU oracle on the whole baseline plan (one core and all cores) and exit")
+    ap.add_argument("--lds-probe", action="store_true",
+                    help="build and run the LDS / VALU instruction-rate probe (bench_lds_rates.hip) and exit")
     args = ap.parse_args(argv)
+    if args.lds_probe:
+        return lds_probe()
+    if args.cpu_plan:
+        return cpu_plan()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): sharding the path over "
               f"GPUs (sub-boxes of whole tiles with halo exchange) is not built.", file=sys.stderr)
@@ -717,6 +863,11 @@ def main(argv=None):
                               "basis": "300 ds_add_u64 at 6.3 clk + 192 ds_read2_b32 at 4 clk per 64 particles, "
                                        "256 CU x 2.4 GHz, no bank conflicts"}}
 
+    serving = None
+    if not args.no_serving:
+        log(f"[bench] serving leg: {args.serving_requests} requests")
+        serving = serving_leg(torch, pp, count=args.serving_requests, no_fp64=args.no_fp64)
+
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU baseline (oracle, bounded sample)")
@@ -744,6 +895,7 @@ def main(argv=None):
                    "fp32_over_fp64": (value / fp64["value"]) if fp64 else None, "diagnostics": diag32},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -75,7 +75,8 @@ enum {
     PP_DIAG_FIELDS = 2,   /* field energies                                      */
     PP_DIAG_RHO = 4,      /* deposit rho^{n}; Gauss residual; CC residual        */
     PP_DIAG_DIVB = 8,     /* max |div B|                                         */
-    PP_DIAG_ALL = 15
+    PP_DIAG_RELAX = 16,   /* measured residual of the last B relaxation          */
+    PP_DIAG_ALL = 31
 };
 
 /* Run parameters (Sec. II weight order, Sec. III.A pusher, Sec. III.B alpha and
@@ -93,7 +94,7 @@ typedef struct pp_params {
     double alpha;          /* implicit de-centering, 1/2 <= alpha < 1                 */
     int32_t pusher;        /* PP_PUSH_VAY (default) or PP_PUSH_BORIS                  */
     int32_t precision;     /* PP_PREC_FP64 or PP_PREC_FP32_SPLIT                      */
-    double relax_tol;      /* target error reduction of the B relaxation, e.g. 1e-14 */
+    double relax_tol;      /* target relative residual of the B relaxation, e.g. 1e-14 */
     int32_t relax_max_iter;/* upper bound on relaxation sweeps                        */
     double rho_background; /* fixed neutralising charge density (0 if none)          */
     double rad_tau;        /* radiative cooling (Sec. "Radiative cooling", eqs. "prad",
@@ -166,10 +167,17 @@ typedef struct pp_diag {
     double cc_max;     /* max |rho^{n} - rho^{n-1} + dt div J^{n}| (NaN if no rho^{n-1}) */
     double rho_ref;    /* max_s |q_s| n_s (mean number density): normalisation       */
     double divB_max;   /* max |div B| (up-shifted divergence)                         */
-    double relax_resid;/* estimated relative error bound of the last B relaxation    */
+    double relax_resid;/* a-priori bound of the residual reduction of the last B
+                        * relaxation (Chebyshev error bound times the condition number)  */
     int32_t relax_iters;
     int32_t flags;     /* PP_FLAG_* bits accumulated since the last pp_diagnostics    */
     int64_t step;      /* number of completed pp_gather_push_deposit calls          */
+    double relax_resid_meas; /* PP_DIAG_RELAX: max |rhs - A B| / max |rhs| of the last
+                        * field step's relaxation (Sec. III.B, eq. "EllipticB": A = 1 -
+                        * alpha^2 c^2 dt^2 lap, rhs its right-hand side, B the field after
+                        * the step), computed on the device from the stored right-hand side
+                        * and the current B; NaN when not requested, before the first field
+                        * step, or after Gauss-law filter passes (they reuse its storage) */
 } pp_diag;
 
 typedef struct pp_run pp_run;
@@ -206,10 +214,11 @@ pp_status pp_gather_push_deposit(pp_run* run);
 /* Steps 4-5 of Sec. III: B^{n+1} from the elliptic equation "EllipticB" (with
  * the J term's sign derived from "bnplus1"/"enplus1") by Jacobi relaxation from
  * B^n, then E^{n+1} from "enplus1".  E and B are updated in place.  The number of
- * sweeps is the smallest whose error-reduction bound reaches relax_tol, at most
+ * sweeps is the smallest whose bound on the residual reduction (Chebyshev error
+ * bound times the condition number of the operator) reaches relax_tol, at most
  * relax_max_iter; when the cap is reached first the step is still completed with
  * relax_max_iter sweeps and PP_E_NOCONV is returned (pp_diag.relax_resid gives the
- * bound reached). */
+ * bound reached; PP_DIAG_RELAX measures the residual itself). */
 pp_status pp_field_step(pp_run* run);
 
 /* Counting sort of species s (-1 = all) by tile-major cell key (Sec. III: the

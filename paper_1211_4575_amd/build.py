@@ -17,7 +17,6 @@ OUT = os.path.join(HERE, "libpp.so")
 SRC_INPUTS = os.path.join(HERE, "csrc_inputs")
 OUT_INPUTS = os.path.join(HERE, "libpp_inputs.so")
 BUILD = os.path.join(HERE, "_build")
-PROBES = os.path.join(HERE, "probes")  # stand-alone measurement programs (one .hip each)
 ARCH = os.environ.get("PP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -50,28 +49,15 @@ def _link(objs, out):
     os.replace(tmp, out)
 
 
-def _probe(src: str) -> str:
-    exe = src[: -len(".hip")]
-    cmd = [HIPCC, "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-           "-packed-fp32-ops", src, "-o", exe]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{res.stdout}\n{res.stderr}")
-    return exe
-
-
 def build(jobs: int | None = None) -> str:
     """Compile every HIP source and link libpp.so (the method) and libpp_inputs.so (the
-    on-device input generator), and build the measurement probes; returns the path of
-    libpp.so.  Always rebuilds."""
+    on-device input generator); returns the path of libpp.so.  Always rebuilds."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(SRC, "*.hip")))
     srcs_in = sorted(glob.glob(os.path.join(SRC_INPUTS, "*.hip")))
-    probes = sorted(glob.glob(os.path.join(PROBES, "*.hip")))
     jobs = jobs or min(8, len(srcs) + len(srcs_in))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs + srcs_in))
-        list(ex.map(_probe, probes))
     _link(objs[: len(srcs)], OUT)
     _link(objs[len(srcs):], OUT_INPUTS)
     return OUT

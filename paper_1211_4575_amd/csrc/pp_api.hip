@@ -450,6 +450,8 @@ pp_status pp_diagnostics(pp_run* r, uint32_t what, pp_diag* out) {
     const bool have_prev = host[na + 1] != 0.0;
     out->cc_max = have_prev ? host[base + 4] : NAN;
     out->divB_max = host[base + 5];
+    const bool have_relax = host[na + 2] != 0.0;
+    out->relax_resid_meas = have_relax ? (host[base + 7] > 0.0 ? host[base + 6] / host[base + 7] : host[base + 6]) : NAN;
     double rref = 0.0;
     const double V = 1.0;
     (void)V;

@@ -247,6 +247,7 @@ pp_status batch_step(pp_batch* b, TableTarget target) {
         for (int s = 0; s < PP_MAX_SPECIES; ++s)
             if (r->sp[s].active) sort_enqueued(r, s);
         r->step += 1;
+        note_relax_rhs(r);
         noconv = noconv || !r->jac_converged;
     }
     // every member stepped; a member's relaxation could not reach its tolerance

@@ -27,6 +27,8 @@ enum {
     ACC_GAUSS,  // max, stored as the bits of a non-negative double
     ACC_CC,
     ACC_DIVB,
+    ACC_RELAX,      // max |rhs - A B| of the last relaxation (bits of a non-negative double)
+    ACC_RELAX_RHS,  // max |rhs|
     ACC_COUNT
 };
 // device-only slot after the copied accumulators: 2^e of the fixed-point charge density
@@ -562,6 +564,11 @@ hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out) {
                            (const double*)r->rho_prev, r->p.rho_background, 1.0 / r->p.eps0, r->dt_drift, want_rho ? 1 : 0,
                            have_prev ? 1 : 0, want_divb ? 1 : 0, r->dacc + ACC_GAUSS);
     }
+    const bool want_relax = (what & PP_DIAG_RELAX) != 0 && r->rhs_valid;
+    if (want_relax) {
+        e = launch_relax_resid(r, r->dacc + ACC_RELAX);
+        if (e != hipSuccess) return e;
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(host_out, r->dacc, ACC_COUNT * sizeof(double), hipMemcpyDeviceToHost, r->stream);
@@ -573,6 +580,7 @@ hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out) {
     if (e != hipSuccess) return e;
     host_out[ACC_COUNT] = (double)flags;
     host_out[ACC_COUNT + 1] = have_prev ? 1.0 : 0.0;
+    host_out[ACC_COUNT + 2] = want_relax ? 1.0 : 0.0;
     // clear the flags and keep rho for the next continuity check
     e = hipMemsetAsync(r->flags, 0, sizeof(int32_t), r->stream);
     if (e != hipSuccess) return e;

@@ -637,7 +637,8 @@ int64_t field_blocks(const pp_run* r) { return blocks_of(make_geom(r)); }
 // extrapolated by gamma = 2 / (2 - g0 - g1), which centres that interval on 0 with radius
 // r = (g1 - g0) / (2 - g0 - g1), and accelerated by Chebyshev semi-iteration (Golub and
 // Varga 1961): after m sweeps the error is multiplied by at most 1 / T_m(1/r) (T_m the
-// Chebyshev polynomial), and m is the smallest count for which that is <= relax_tol.
+// Chebyshev polynomial) and the residual by at most amax / T_m(1/r); m is the smallest
+// count for which that is <= relax_tol.
 static hipError_t relax_setup(pp_run* r, double dt, pp_run::RelaxSet& S);
 
 hipError_t field_setup(pp_run* r) {
@@ -712,13 +713,19 @@ static hipError_t relax_setup(pp_run* r, double dt, pp_run::RelaxSet& S) {
     S.gamma = 2.0 / (2.0 - g0 - g1);
     const double rr = (g1 - g0) / (2.0 - g0 - g1);
     S.r = rr;
+    // The paper relaxes until the residual is small (Sec. III.B).  After k sweeps the error is
+    // reduced by at most 1/cosh(k acosh(1/r)) (Chebyshev); the residual rhs - A B_k = A e_k is
+    // then reduced by at most that times the condition number of A, whose eigenvalues lie in
+    // [1, amax] (1 - al2s lap with lap <= 0; the constant mode has eigenvalue 1).  The sweep
+    // count is the smallest whose residual bound reaches relax_tol.
+    const double kappa = amax;
     int sweeps = 1;
     double bound = 0.0;
     if (rr > 1e-300) {
         const double ac = acosh(1.0 / rr);
         for (sweeps = 1; sweeps < r->p.relax_max_iter; ++sweeps)
-            if (1.0 / cosh(sweeps * ac) <= r->p.relax_tol) break;
-        bound = 1.0 / cosh(sweeps * ac);
+            if (kappa / cosh(sweeps * ac) <= r->p.relax_tol) break;
+        bound = kappa / cosh(sweeps * ac);
     }
     S.sweeps = sweeps;
     S.bound = bound;
@@ -806,12 +813,68 @@ hipError_t launch_field_step(pp_run* r) {
         hipLaunchKernelGGL(k_field, grid, dim3(bs), 0, r->stream, D, (int)PH_UPDATE_E, 0);
     else
         launch_curl_tiled<CK_UPDATE_E>(D, tb, r->stream);
+    note_relax_rhs(r);
+    return hipGetLastError();
+}
+
+void note_relax_rhs(pp_run* r) {
+    const double c2 = r->p.c * r->p.c, dt = r->dt_drift;
+    r->rhs_valid = true;
+    r->rhs_al2s = r->p.alpha * r->p.alpha * c2 * dt * dt;
+}
+
+// Residual of the relaxation actually reached (Sec. III.B: the paper relaxes to a residual):
+// per cell and component r = R - (B - al2s lap B) with R the stored right-hand side, reduced
+// to max |r| and max |R| (non-negative doubles compared as their bit patterns).
+__device__ __forceinline__ void max_bits(double v, double* acc) {
+    atomicMax((unsigned long long*)acc, (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ void __launch_bounds__(FIELD_BS) k_relax_resid(FieldGeom G, const double* __restrict__ B,
+                                                          const double* __restrict__ R, double al2s, double* acc) {
+    __shared__ double red[2][FIELD_BS / 64];
+    double rmax = 0.0, hmax = 0.0;
+    int i, j, k;
+    if (field_cell(G, blockIdx.x, threadIdx.x, i, j, k)) {
+        const int q = lin(G, i, j, k);
+        for (int c = 0; c < 3; ++c) {
+            const double* x = B + c * G.nc;
+            const double rhs = R[c * G.nc + q];
+            const double Ax = x[q] - al2s * lap(G, x, i, j, k);
+            rmax = fmax(rmax, fabs(rhs - Ax));
+            hmax = fmax(hmax, fabs(rhs));
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        rmax = fmax(rmax, __shfl_xor(rmax, o));
+        hmax = fmax(hmax, __shfl_xor(hmax, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = rmax;
+        red[1][threadIdx.x >> 6] = hmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < FIELD_BS / 64; ++w) {
+            rmax = fmax(rmax, red[0][w]);
+            hmax = fmax(hmax, red[1][w]);
+        }
+        max_bits(rmax, acc);
+        max_bits(hmax, acc + 1);
+    }
+}
+
+hipError_t launch_relax_resid(pp_run* r, double* acc) {
+    const FieldGeom G = make_geom(r);
+    hipLaunchKernelGGL(k_relax_resid, dim3((unsigned)blocks_of(G)), dim3(FIELD_BS), 0, r->stream, G,
+                       (const double*)r->mesh.B, (const double*)r->R, r->rhs_al2s, acc);
     return hipGetLastError();
 }
 
 // Gauss-law filter of a run (after its field step): rho of the current positions, then the
 // passes, each a residual launch and a correction launch.
 hipError_t launch_gauss_filter(pp_run* r) {
+    r->rhs_valid = false;  // the passes keep their residual in R
     hipError_t e = deposit_rho_all(r);
     if (e != hipSuccess) return e;
     FieldDesc D;

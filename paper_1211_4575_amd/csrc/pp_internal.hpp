@@ -109,6 +109,10 @@ struct pp_run {
     int jac_sweeps = 0;      // relaxation sweeps per field step
     double jac_bound = 0.0;  // error reduction bound after jac_sweeps sweeps
     bool jac_converged = true;  // jac_bound <= relax_tol (false: capped by relax_max_iter)
+    // the right-hand side of the last field step is still in R (for the measured residual),
+    // with the alpha^2 c^2 dt^2 of that step
+    bool rhs_valid = false;
+    double rhs_al2s = 0.0;
     double* omega = nullptr; // Chebyshev weights (device, relax_max_iter + 2)
     double gauss_kappa = 0.0; // damping of the Gauss-law filter: 1 / max |K|^2
     // time step of the particle and field kernels: kick (momentum update) and drift
@@ -176,6 +180,10 @@ hipError_t materialize(pp_run* r, int s);
 hipError_t launch_diag(pp_run* r, uint32_t what, double* host_out);
 hipError_t deposit_rho_all(pp_run* r);  // rho of the current positions into r->rho
 hipError_t launch_gauss_filter(pp_run* r);  // the run's Gauss-law filter passes on E
+void note_relax_rhs(pp_run* r);  // R holds the right-hand side of the field step just enqueued
+// max |R - A B| and max |R| of the last field step (A = 1 - al2s lap) into acc[0], acc[1]
+// (bits of non-negative doubles, combined with atomic max: acc must start at zero)
+hipError_t launch_relax_resid(pp_run* r, double* acc);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void swap_buffers(pp_particles& c);
 

@@ -20,7 +20,7 @@ PP_PUSH_VAY, PP_PUSH_BORIS = 0, 1
 PP_CURRENT_CC, PP_CURRENT_DIRECT = 0, 1
 PP_MAX_SPECIES = 8
 PP_FLAG_CFL, PP_FLAG_NONFINITE, PP_FLAG_OUT_OF_TILE = 1, 2, 4
-PP_DIAG_MOMENTS, PP_DIAG_FIELDS, PP_DIAG_RHO, PP_DIAG_DIVB, PP_DIAG_ALL = 1, 2, 4, 8, 15
+PP_DIAG_MOMENTS, PP_DIAG_FIELDS, PP_DIAG_RHO, PP_DIAG_DIVB, PP_DIAG_RELAX, PP_DIAG_ALL = 1, 2, 4, 8, 16, 31
 
 EXPORTED = ("pp_workspace_size", "pp_create", "pp_init_species", "pp_gather_push_deposit", "pp_field_step", "pp_sort_particles",
             "pp_step",
@@ -84,6 +84,7 @@ class pp_diag(ctypes.Structure):
         ("relax_iters", ctypes.c_int32),
         ("flags", ctypes.c_int32),
         ("step", ctypes.c_int64),
+        ("relax_resid_meas", ctypes.c_double),
     ]
 
 

@@ -17,6 +17,7 @@ same scheduler logic runs against a simulated device in the CPU tests.
 from __future__ import annotations
 
 import math
+import threading
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -58,7 +59,9 @@ def summarize(results, t_first=None):
     t0 = min(r.arrival for r in results) if t_first is None else t_first
     t1 = max(r.done for r in ok)
     upd = sum(r.updates for r in ok)
-    return dict(completed=len(ok), failed=len(results) - len(ok), p50_s=percentile([r.latency for r in ok], 50),
+    return dict(completed=len(ok), failed=sum(r.status == "failed" for r in results),
+                cancelled=sum(r.status == "cancelled" for r in results),
+                rejected=sum(r.status == "rejected" for r in results), p50_s=percentile([r.latency for r in ok], 50),
                 p99_s=percentile([r.latency for r in ok], 99), makespan_s=t1 - t0,
                 updates=upd, updates_per_s=upd / (t1 - t0) if t1 > t0 else math.nan)
 
@@ -78,9 +81,21 @@ class Scheduler:
         self.peak_members = 0
         self.peak_bytes = 0
         self.batch_steps = 0
+        self._cancel = set()
+        self._cancel_lock = threading.Lock()
 
-    def run(self, requests):
+    def cancel(self, rid: int):
+        """Cancel request ``rid`` (callable from any thread or from on_complete): a pending
+        request is dropped, a running one leaves the batch before the next step and is reported
+        "cancelled" once the device has finished its last step; the others are unaffected."""
+        with self._cancel_lock:
+            self._cancel.add(rid)
+
+    def run(self, requests, cancel_after=None):
+        """Serve ``requests``; ``cancel_after`` maps rid -> number of steps after which that
+        request is cancelled (a budget per request)."""
         be = self.be
+        cancel_after = dict(cancel_after or {})
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         active = {}  # rid -> [handle, request, steps left, admitted, bytes]
         inflight = deque()  # (token, entries that finished with that step)
@@ -89,16 +104,35 @@ class Scheduler:
 
         def complete(entries, t_done):
             nonlocal used
-            for h, req, _, t_adm, need in entries:
+            for h, req, left, t_adm, need in entries:
                 flags, info = be.retire(h)
                 used -= need
-                results.append(Result(req.rid, req.arrival, t_adm, t_done, req.steps, req.updates,
-                                      "ok" if flags == 0 else "failed", flags, info))
+                status = "cancelled" if left > 0 else ("ok" if flags == 0 else "failed")
+                results.append(Result(req.rid, req.arrival, t_adm, t_done, req.steps - left,
+                                      req.updates * (req.steps - left) // max(req.steps, 1), status, flags, info))
                 if self.on_complete is not None:
                     self.on_complete(results[-1], len(active))
 
+        def take_cancellations():
+            with self._cancel_lock:
+                todo, self._cancel = self._cancel, set()
+            for rid in todo:
+                for i, req in enumerate(pending):
+                    if req.rid == rid:
+                        del pending[i]
+                        results.append(Result(req.rid, req.arrival, math.nan, math.nan, 0, 0, "cancelled"))
+                        break
+                if rid in active:  # leaves now; reported when the device is past its last step
+                    e = active.pop(rid)
+                    be.leave(e[0])
+                    if inflight:
+                        inflight[-1][1].append(e)
+                    else:
+                        complete([e], be.now())
+
         be.start()
         while pending or active or inflight:
+            take_cancellations()
             now = be.now()
             while pending and pending[0].arrival <= now and len(active) < self.max_slots:
                 req = pending[0]
@@ -127,6 +161,8 @@ class Scheduler:
                         be.leave(e[0])
                         finished.append(e)
                         del active[rid]
+                    elif rid in cancel_after and e[1].steps - e[2] >= cancel_after[rid]:
+                        self.cancel(rid)
                 inflight.append((tok, finished))
                 while len(inflight) > self.max_inflight:
                     tok0, fin = inflight.popleft()

@@ -16,7 +16,7 @@ import sys
 import numpy as np
 import pytest
 
-from _state import periodic_diff, rel_inf
+from _state import periodic_diff, rel_inf, rel_l2
 from paper_1211_4575_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -156,3 +156,92 @@ def test_full_size_step_sampled_against_oracle(orc, name, split):
         if split:
             assert np.all(a["pos"] >= 0.0) and np.all(a["pos"] < 2.0)
         assert np.max(np.abs(a["u"] - b["u"])) > 0.0  # the sample did feel the fields
+
+
+def test_full_size_field_step_current_and_residual_against_oracle(orc):
+    """The benchmark's 256^3 split FP32 step, element by element where the oracle can follow
+    it: (1) the field step as the benchmark runs it (tiled kernels, relax_tol 1e-8 at most 100
+    sweeps) from the GPU's E^n, B^n and J^{n+1}, against the oracle's field step from the same
+    three arrays (the OpenMP build, bitwise the plain one for this step; relaxed to 1e-10):
+    E^{n+1} and B^{n+1} within 1e-5 (L2, relative to the change); (2) the measured relaxation
+    residual max |rhs - A B| / max |rhs| at or below 1e-8; (3) the current on an 8^3 window:
+    the GPU's field-order current J_O turned back into the second-order one with the banded
+    stencil of eqs. "jj6d"/"penta" (J_2 = T J_O along each component's axis, T = (c, b+c,
+    a+b+c, b+c, c)) against the oracle's second-order current of every particle within reach
+    of the window, within 1e-5 (L2, relative)."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import bench
+    from paper_1211_4575_amd import inputs_device as ind
+    from paper_1211_4575_amd import pp
+
+    _say("full size field step: loading")
+    run, npart, qmw, okw = _pair_mj(bench, pp, ind, torch, True)
+    n = okw["n"]
+    w0, W, reach = (100, 37, 211), 8, 4
+    try:
+        run.step()  # non-zero fields from here on
+        E0 = run.E.cpu().numpy()
+        B0 = run.B.cpu().numpy()
+        # the particles whose cell lies within `reach` cells of the window (periodic)
+        near = []
+        for s in range(len(qmw)):
+            T = run.particle_tensors(s)
+            c = T["cell"].to(torch.int64)
+            ijk = (c % n[0], (c // n[0]) % n[1], c // (n[0] * n[1]))
+            m = torch.ones_like(c, dtype=torch.bool)
+            for d in range(3):
+                rel = (ijk[d] - (w0[d] - reach)) % n[d]
+                m &= rel < W + 2 * reach
+            q = torch.nonzero(m).flatten()
+            near.append(dict(cell=T["cell"][q].cpu().numpy(), pos=np.stack([T["pos"][d][q].cpu().numpy() for d in range(3)]),
+                             u=np.stack([T["u"][d][q].cpu().numpy() for d in range(3)])))
+            del T, c, m, q, ijk
+        _say("full size field step: particles near the window", [x["cell"].size for x in near])
+        run.gather_push_deposit()
+        J = run.J.cpu().numpy()
+        run.sort()
+        run.field_step()
+        E1 = run.E.cpu().numpy()
+        B1 = run.B.cpu().numpy()
+        d = run.diagnostics(pp.PP_DIAG_RELAX)
+        _say("full size field step: measured residual", d.relax_resid_meas, "sweeps", d.relax_iters)
+        assert d.relax_resid_meas <= 1e-8, d.relax_resid_meas
+        assert d.flags == 0
+    finally:
+        run.close()
+        del run
+        torch.cuda.empty_cache()
+
+    P = orc.make_params(shape_order=3, field_order=6, alpha=0.55, relax_tol=1e-10, relax_max_iter=200, **okw)
+    Eo, Bo = E0.copy(), B0.copy()
+    with orc.openmp():
+        _say("full size field step: oracle field step on", orc.num_threads(), "threads")
+        it, res = orc.field_step(P, Eo, Bo, J)
+    _say("full size field step: oracle sweeps", it, "residual", res)
+    errE, errB = rel_l2(E1 - E0, Eo - E0), rel_l2(B1 - B0, Bo - B0)
+    _say("full size field step: dE", errE, "dB", errB)
+    assert errE < 1e-5 and errB < 1e-5
+
+    # the window's second-order current from the oracle
+    Jo = np.zeros_like(E0)
+    for s, (q, m, w) in enumerate(qmw):
+        x = near[s]
+        pos = np.ascontiguousarray(I.from_split(x["cell"], x["pos"], n))
+        u = np.ascontiguousarray(x["u"].astype(np.float64))
+        assert orc.step_species(P, q, m, w, pos, u, E0, B0, Jo) == 0
+    a = orc.fd_coeffs(6)
+    taps = {0: a[0] + a[1] + a[2], 1: a[1] + a[2], 2: a[2]}
+    sl = [np.arange(w0[d], w0[d] + W) % n[d] for d in range(3)]
+    got, want = [], []
+    for comp in range(3):
+        T2 = np.zeros((W, W, W))
+        for o in range(-2, 3):
+            idx = list(sl)
+            idx[comp] = (sl[comp] + o) % n[comp]
+            T2 += taps[abs(o)] * J[comp][np.ix_(idx[2], idx[1], idx[0])]
+        got.append(T2)
+        want.append(Jo[comp][np.ix_(sl[2], sl[1], sl[0])])
+    errJ = rel_l2(np.array(got), np.array(want))
+    _say("full size current window: J_2 error", errJ)
+    assert errJ < 1e-5

@@ -144,3 +144,43 @@ def test_fourth_order_gyration_converges_at_fourth_order():
     assert 3.5 < e2[0] / e2[1] < 4.5
     assert 14 < e4[0] / e4[1] < 18
 
+
+
+@pytest.mark.parametrize("split", [False, True], ids=["fp64", "fp32_split"])
+def test_seeded_oblique_mode_grows_at_the_linear_rate(orc, split):
+    """The fastest-growing oblique eigenmode of the cold beam-plasma system (neutral beam at
+    Lorentz factor 4 through a neutral background, ion mass 1836) at k = (2.99, 0, 0.861), 74
+    degrees from the beam, seeded in a thin 3D box of 21 x 2 x 73 cells of 0.1 (quiet lattice,
+    cubic weights, 6th-order fields): the field energy grows at twice the rate of the cold
+    two-fluid theory for finite-size particles, within 3 % (the oracle's run of the same state
+    is pinned the same way in tests/test_oracle_mmi_pin.py)."""
+    import numpy as np
+
+    import _mmi_mode as T
+    from paper_1211_4575_amd import inputs as I
+    from paper_1211_4575_amd import pp
+    n, dx = (21, 2, 73), 0.1
+    species, E, B, k, rate, fluid = T.seeded_state(n, dx)
+    kw = dict(n=n, d=(dx, dx, dx), dt=0.4 * dx, shape_order=3, field_order=6, alpha=0.55, relax_tol=1e-14,
+              relax_max_iter=200)
+    if split:
+        sp = []
+        for s in species:
+            cell, off = I.to_split(s["pos"], n, origin=I.split_origin(3))
+            sp.append(dict(q=s["q"], m=s["m"], w=s["w"], cell=cell, off=off, u=s["u"].astype(np.float32)))
+        species = sp
+    run = pp.Run(pp.make_params(precision=pp.PP_PREC_FP32_SPLIT if split else pp.PP_PREC_FP64, **kw), species,
+                 E=E, B=B, with_id=False)
+    hist = []
+    for i in range(251):
+        if i:
+            run.step()
+        d = run.diagnostics(pp.PP_DIAG_FIELDS)
+        hist.append(d.field_E + d.field_B)
+    assert run.diagnostics(pp.PP_DIAG_MOMENTS).flags == 0
+    run.close()
+    t = kw["dt"] * np.arange(len(hist))
+    got = T.energy_rate(t, hist)
+    print("oblique mode", "FP32" if split else "FP64", "rate", got, "theory", rate, "fluid", fluid, file=sys.stderr,
+          flush=True)
+    assert abs(got - rate) < 0.03 * rate, (got, rate)

@@ -145,6 +145,35 @@ def test_too_large_rejected_and_failures_isolated():
             assert r.status == "ok"
 
 
+def test_cancelled_requests_leave_and_the_others_are_untouched():
+    # request 2 cancelled while it waits, request 5 after 3 of its steps, request 9 from a
+    # completion callback: each reported "cancelled" with the steps it ran; every other request
+    # completes with its own step count, and the device ends empty
+    reqs = _requests(rate=500.0)
+    dev = FakeDevice()
+    dev._reqs = {r.rid: r for r in reqs}
+    sch = None
+
+    def on_complete(res, active):
+        if res.rid == 0:
+            sch.cancel(9)
+
+    sch = S.Scheduler(dev, mem_budget=10**9, max_slots=4, on_complete=on_complete)
+    sch.cancel(2)
+    res = sch.run(reqs, cancel_after={5: 3})
+    by = {r.rid: r for r in res}
+    assert len(res) == len(reqs)
+    assert by[2].status == "cancelled" and by[2].steps == 0
+    assert by[5].status == "cancelled" and by[5].steps == 3 and by[5].info["steps"] == 3
+    assert by[9].status == "cancelled" and by[9].steps < reqs[9].steps
+    for q in reqs:
+        if q.rid not in (2, 5, 9):
+            assert by[q.rid].status == "ok" and by[q.rid].info["steps"] == q.steps
+    assert dev.live_bytes == 0 and not dev.members
+    s = S.summarize(res)
+    assert s["cancelled"] == 3 and s["completed"] == len(reqs) - 3 and s["failed"] == 0
+
+
 def test_idle_device_waits_for_arrivals():
     reqs = _requests(count=5, rate=0.5)  # far apart: each served alone right away
     dev, sch, res = _serve(reqs)
