@@ -269,8 +269,356 @@ __device__ __forceinline__ int32_t dest_rank(const Gpd32Args& A, const Sp32& S, 
     return (int32_t)(0x80000000u | (uint32_t)atomicAdd(&S.cnt[gcell], 1));
 }
 
+// What the charge-conserving deposit of one particle needs, kept in registers between its step
+// and its deposit: the old offset, the new position relative to the old cell and the cell's
+// place in the tile (the window is built from them at deposit time).
+template <int O>
+struct Win {
+    float f[3], x1[3];
+    int loc[3];
+    bool dep;
+};
+
+// The Esirkepov window of a particle: S0 and DS = S1 - S0 on the O + 2 centred nodes per axis
+// covering the old and the new support, the window's first node in the tile's current block,
+// and which axes the supports differ on.
+template <int O, class TL>
+__device__ __forceinline__ void make_window(const TL& L, const Win<O>& W, float S0[3][O + 2], float DS[3][O + 2],
+                                            int wb[3], int& moved) {
+    const int clo[3] = {L.clox, L.cloy, L.cloz};
+    moved = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        float w0[O + 1], w1[O + 1];
+        const int a0 = centred_weights<O>(W.f[d], w0);
+        const int a1 = centred_weights<O>(W.x1[d], w1);
+        const bool lo1 = a1 < a0;  // the new support starts one node lower
+        const bool hi1 = a1 > a0;
+        const int bmin = lo1 ? a1 : a0;
+#pragma unroll
+        for (int kk = 0; kk < O + 2; ++kk) {
+            // old weights sit at window offset (a0 - bmin), new at (a1 - bmin)
+            const float s0 = lo1 ? (kk >= 1 ? w0[kk - 1 < O ? kk - 1 : O] : 0.f) : (kk <= O ? w0[kk <= O ? kk : O] : 0.f);
+            const float s1 = hi1 ? (kk >= 1 ? w1[kk - 1 < O ? kk - 1 : O] : 0.f) : (kk <= O ? w1[kk <= O ? kk : O] : 0.f);
+            S0[d][kk] = s0;
+            DS[d][kk] = s1 - s0;
+        }
+        wb[d] = W.loc[d] + clo[d] + bmin;
+        moved |= (lo1 || hi1) ? 1 << d : 0;
+    }
+}
+
+// First node of a particle's window along axis d (as make_window), without the weights.
+template <int O, class TL>
+__device__ __forceinline__ int window_start(const TL& L, const Win<O>& W, int d) {
+    const int clo[3] = {L.clox, L.cloy, L.cloz};
+    const int a0 = O == 2 ? (int)floorf(W.f[d] + 0.5f) - 1 : (int)floorf(W.f[d]) - 1;
+    const int a1 = O == 2 ? (int)floorf(W.x1[d] + 0.5f) - 1 : (int)floorf(W.x1[d]) - 1;
+    return W.loc[d] + clo[d] + (a1 < a0 ? a1 : a0);
+}
+
+// What the particle step of one tile and species needs besides the arguments.
+struct TileCtx {
+    int org[3];
+    int64_t base_cell;
+    int nxy;
+    const float* fld;
+    unsigned long long* cur;
+    int32_t* slots;
+    double facq[3];  // -q w d_c / dt, times the fixed-point scale
+    double qwq;      // q w times the fixed-point scale (direct current)
+};
+
+// The particle step of slot q (gather, push, move, renormalise, store, rank for the next sort;
+// the direct current is deposited here).  For the charge-conserving current the window is left
+// in W for the deposit (W.dep = false when the particle deposits nothing: left as it was, or
+// the direct scheme).
+template <int O, class TL>
+__device__ __forceinline__ void step_particle(const Gpd32Args& A, const Sp32& S, const TL& L, const TileCtx& C,
+                                              int32_t q, Win<O>& W, int& bad_all) {
+    W.dep = false;
+    const int n0 = A.n[0], n1 = A.n[1], n2 = A.n[2];
+    const int32_t p = S.perm ? S.perm[q] : q;
+    if (p < 0) {  // an empty slot (counts made inconsistent by flagged particles)
+        S.rank[q] = -1;
+        return;
+    }
+    const int32_t cell = S.cell[p];
+    float f[3] = {S.pos[0][p], S.pos[1][p], S.pos[2][p]};
+    V3<float> u{S.u[0][p], S.u[1][p], S.u[2][p]};
+    if (S.id) S.id_o[q] = S.id[p];
+    // a particle left as it is still moves to its slot when the kernel reorders
+    auto keep = [&](const V3<float>& uk) {
+        if (!S.perm) return;
+        S.cell_o[q] = cell;
+        S.pos_o[0][q] = f[0];
+        S.pos_o[1][q] = f[1];
+        S.pos_o[2][q] = f[2];
+        S.u_o[0][q] = uk.x;
+        S.u_o[1][q] = uk.y;
+        S.u_o[2][q] = uk.z;
+    };
+    // position inside the tile: rel = li + n0 lj + n0 n1 lk with l < t, found by
+    // comparisons (no division)
+    int64_t rel = (int64_t)cell - C.base_cell;
+    int lk = 0, lj = 0;
+    while (lk < L.tz - 1 && rel >= (int64_t)C.nxy) {
+        rel -= C.nxy;
+        ++lk;
+    }
+    while (lj < L.ty - 1 && rel >= (int64_t)n0) {
+        rel -= n0;
+        ++lj;
+    }
+    const int li = (int)rel;
+    const int loc[3] = {li, lj, lk};
+    const int* org = C.org;
+    // the particle must lie in this tile: local indices in range and the cell index
+    // rebuilt from them equal to the stored one
+    const bool inside = rel >= 0 && li < L.tx && org[0] + li < n0 && org[1] + lj < n1 && org[2] + lk < n2 &&
+                        (int64_t)(org[0] + li) + (int64_t)n0 * ((org[1] + lj) + (int64_t)n1 * (org[2] + lk)) ==
+                            (int64_t)cell;
+    if (!inside) {  // not this tile's particle: left out of the next sort
+        bad_all |= PP_FLAG_OUT_OF_TILE;
+        keep(u);
+        S.rank[q] = -1;
+        return;
+    }
+    if (!offset_ok<O>(f[0]) || !offset_ok<O>(f[1]) || !offset_ok<O>(f[2])) {  // left as it is
+        bad_all |= PP_FLAG_OUT_OF_TILE;
+        keep(u);
+        S.rank[q] = dest_rank(A, S, C.slots, loc, cell);
+        return;
+    }
+
+    // gather (eq. "pfields") from the LDS field tile
+    float wc[3][O + 1], ws[3][O + 1];
+    int fc[3], fs[3];
+    {
+        const int flo[3] = {L.flox, L.floy, L.floz};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int bc, bs;
+            split_weights<O>(f[d], wc[d], bc, ws[d], bs);
+            fc[d] = loc[d] + flo[d] + bc;
+            fs[d] = loc[d] + flo[d] + bs;
+        }
+    }
+    const float* fld = C.fld;
+    V3<float> E, B;
+    E.x = gather_comp<O>(fld + 0 * L.fvol, L, fs[0], fc[1], fc[2], ws[0], wc[1], wc[2]);
+    E.y = gather_comp<O>(fld + 1 * L.fvol, L, fc[0], fs[1], fc[2], wc[0], ws[1], wc[2]);
+    E.z = gather_comp<O>(fld + 2 * L.fvol, L, fc[0], fc[1], fs[2], wc[0], wc[1], ws[2]);
+    B.x = gather_comp<O>(fld + 3 * L.fvol, L, fc[0], fs[1], fs[2], wc[0], ws[1], ws[2]);
+    B.y = gather_comp<O>(fld + 4 * L.fvol, L, fs[0], fc[1], fs[2], ws[0], wc[1], ws[2]);
+    B.z = gather_comp<O>(fld + 5 * L.fvol, L, fs[0], fs[1], fc[2], ws[0], ws[1], wc[2]);
+
+    const V3<float> um = u;
+    if (A.pusher == PP_PUSH_BORIS)
+        push_boris<float>(S.h, A.ic, E, B, u);
+    else
+        push_vay<float>(S.h, A.ic, E, B, u);
+    if (S.krad != 0.0f) rad_cool<float>(S.krad, A.dtk, A.ic, um, u);
+
+    const float ig = rsqrtf(1.0f + dot(u, u) * A.ic * A.ic);
+    const float uu[3] = {u.x, u.y, u.z};
+    float x1[3], dxs[3];
+    int bad = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float dd = A.dt * uu[d] * ig * A.inv_d[d];
+        if (!(fabsf(dd) < 1.0f)) bad |= isfinite(dd) ? PP_FLAG_CFL : PP_FLAG_NONFINITE;
+        if (!isfinite(uu[d])) bad |= PP_FLAG_NONFINITE;
+        x1[d] = f[d] + dd;  // new position relative to the old cell's node
+        dxs[d] = dd;
+    }
+    if (bad) {  // left as it was before the push
+        bad_all |= bad;
+        keep(um);
+        S.rank[q] = dest_rank(A, S, C.slots, loc, cell);
+        return;
+    }
+
+    if (A.direct) {
+        // direct current (eq. "jj2"): q w v_c W at J_c's staggered nodes, at the
+        // time-centred offset f + dd/2 (its supports stay inside the block's halo)
+        float wcm[3][O + 1], wsm[3][O + 1];
+        int ncm[3], nsm[3];
+        const int clo[3] = {L.clox, L.cloy, L.cloz};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int bc, bs;
+            split_weights<O>(f[d] + 0.5f * dxs[d], wcm[d], bc, wsm[d], bs);
+            ncm[d] = loc[d] + clo[d] + bc;
+            nsm[d] = loc[d] + clo[d] + bs;
+        }
+        const int cst[3] = {L.csx, L.csy, L.csz};
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) {
+            unsigned long long* Jc = C.cur + comp * L.cvol;
+            const double vq = C.qwq * (double)(uu[comp] * ig);
+            const int n0x = comp == 0 ? nsm[0] : ncm[0];
+            const int n0y = comp == 1 ? nsm[1] : ncm[1];
+            const int n0z = comp == 2 ? nsm[2] : ncm[2];
+            const float* wx = comp == 0 ? wsm[0] : wcm[0];
+            const float* wy = comp == 1 ? wsm[1] : wcm[1];
+            const float* wz = comp == 2 ? wsm[2] : wcm[2];
+#pragma unroll
+            for (int c = 0; c <= O; ++c) {
+#pragma unroll
+                for (int b = 0; b <= O; ++b) {
+                    const double wzy = vq * (double)(wz[c] * wy[b]);
+                    const int rowo = n0x * cst[0] + (n0y + b) * cst[1] + (n0z + c) * cst[2];
+#pragma unroll
+                    for (int a = 0; a <= O; ++a) {
+                        const double dq = fma(wzy, (double)wx[a], ROUND_MAGIC);
+                        atomicAdd(Jc + rowo + a * cst[0], (unsigned long long)__double_as_longlong(dq));
+                    }
+                }
+            }
+        }
+    } else {
+        // the charge-conserving current is deposited later, from these
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            W.f[d] = f[d];
+            W.x1[d] = x1[d];
+            W.loc[d] = loc[d];
+        }
+        W.dep = true;
+    }
+
+    // renormalise: new cell and offset in [lo, lo + 1), or in [lo + 1, lo + 2) in the
+    // cell below when the next displacement (this one times the ratio of the next drift
+    // to this one) would cross the lower face
+    int nc3[3], shv[3];
+    float fn[3];
+    const int gc[3] = {org[0] + li, org[1] + lj, org[2] + lk};
+    const float lo = off_lo<O>();
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        float sh = floorf(x1[d] - lo);
+        float o = x1[d] - sh;
+        // rounding can land the offset just outside the range: move it back in
+        if (o < lo) {
+            o += 1.0f;
+            sh -= 1.0f;
+        } else if (o >= lo + 1.0f) {
+            o -= 1.0f;
+            sh += 1.0f;
+        }
+        const float up = o + 1.0f;
+        if (o + dxs[d] * A.pred < lo && up < lo + 2.0f) {
+            o = up;
+            sh -= 1.0f;
+        }
+        fn[d] = o;
+        shv[d] = (int)sh;
+        nc3[d] = wrap(gc[d] + (int)sh, A.n[d]);
+    }
+    const int32_t newcell = nc3[0] + n0 * (nc3[1] + n1 * nc3[2]);
+    S.cell_o[q] = newcell;
+    S.pos_o[0][q] = fn[0];
+    S.pos_o[1][q] = fn[1];
+    S.pos_o[2][q] = fn[2];
+    S.u_o[0][q] = u.x;
+    S.u_o[1][q] = u.y;
+    S.u_o[2][q] = u.z;
+    const int dst[3] = {li + shv[0], lj + shv[1], lk + shv[2]};
+    S.rank[q] = dest_rank(A, S, C.slots, dst, newcell);
+}
+
+// Charge-conserving current of one particle (W1), or of two particles whose windows start at
+// the same node of the block (W1 and W2, PAIR): per component the prefix sums of DS along the
+// component's axis times the scaled factor, P_a, and for every transverse node pair the
+// factor F = S0_1 (S0_2 + DS_2/2) + DS_1 (S0_2/2 + DS_2/3); each node then receives the bits
+// of (1.5*2^52 + round(P_a F)) in one 64-bit integer atomic.  For a pair the two patterns,
+// each rounded on its own, are added as integers before the one atomic, so the node gets the
+// same exact fixed-point sum as from two atomics.  f2 != 0 marks lanes whose second particle
+// deposits; on the others its factors are replaced by zeros.
+template <int O, class TL, bool PAIR>
+__device__ __forceinline__ void deposit_cc(const TL& L, unsigned long long* cur, const Win<O>& P1, const double* facq1,
+                                           const Win<O>& P2, const double* facq2, float f2) {
+    float S0a[3][O + 2], DSa[3][O + 2], S0b[3][O + 2], DSb[3][O + 2];
+    int wb[3], wb2[3], moved1, moved2 = 0;
+    make_window<O, TL>(L, P1, S0a, DSa, wb, moved1);
+    if (PAIR) make_window<O, TL>(L, P2, S0b, DSb, wb2, moved2);
+    struct WinF {
+        const float (*S0)[O + 2];
+        const float (*DS)[O + 2];
+    } W1{S0a, DSa}, W2{S0b, DSb};
+    const int cst[3] = {L.csx, L.csy, L.csz};
+    const bool use2 = PAIR && f2 != 0.0f;
+    const int moved = use2 ? (moved1 | moved2) : moved1;
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        const int d1 = comp == 0 ? 1 : (comp == 1 ? 2 : 0);
+        const int d2 = comp == 0 ? 2 : (comp == 1 ? 0 : 1);
+        unsigned long long* Jc = cur + comp * L.cvol;
+        const int off0 = wb[0] * L.csx + wb[1] * L.csy + wb[2] * L.csz;
+        // prefix sums of DS along the component's own axis (the last one vanishes),
+        // scaled to fixed-point units: P_a * fac * 2^e in FP64
+        // A particle whose supports coincide along the component's axis contributes nothing
+        // at the last node even when its partner's does: its last prefix sum is only the
+        // rounding residue of a vanishing sum, which the single deposit leaves out too.
+        const bool own1 = (moved1 >> comp) & 1, own2 = (moved2 >> comp) & 1;
+        double Pq1[O + 1], Pq2[O + 1];
+        float acc1 = 0.f, acc2 = 0.f;
+#pragma unroll
+        for (int a = 0; a <= O; ++a) {
+            acc1 += W1.DS[comp][a];
+            Pq1[a] = (a < O || own1) ? (double)acc1 * facq1[comp] : 0.0;
+            if (PAIR) {  // a select, not a product: the absent particle's factors may be anything
+                acc2 += W2.DS[comp][a];
+                Pq2[a] = (use2 && (a < O || own2)) ? (double)acc2 * facq2[comp] : 0.0;
+            }
+        }
+        const bool m1 = (moved >> d1) & 1, m2 = (moved >> d2) & 1, mc = (moved >> comp) & 1;
+        // Along an axis where the supports coincide the window's last node carries no
+        // weight (its transverse factors are exactly zero) and the last prefix sum is
+        // the rounding residue of a vanishing sum: those additions are left out.
+#pragma unroll
+        for (int bq = 0; bq < O + 2; ++bq) {
+            if (bq == O + 1 && !m1) continue;
+            const float g1 = W1.S0[d1][bq], h1 = W1.DS[d1][bq];
+            const float g2 = PAIR ? W2.S0[d1][bq] : 0.f, h2 = PAIR ? W2.DS[d1][bq] : 0.f;
+#pragma unroll
+            for (int e = 0; e < O + 2; ++e) {
+                if (e == O + 1 && !m2) continue;
+                const double Fd1 = (double)(g1 * (W1.S0[d2][e] + 0.5f * W1.DS[d2][e]) +
+                                            h1 * (0.5f * W1.S0[d2][e] + (1.0f / 3.0f) * W1.DS[d2][e]));
+                double Fd2 = 0.0;
+                if (PAIR) {
+                    const float F2 = g2 * (W2.S0[d2][e] + 0.5f * W2.DS[d2][e]) +
+                                     h2 * (0.5f * W2.S0[d2][e] + (1.0f / 3.0f) * W2.DS[d2][e]);
+                    Fd2 = use2 ? (double)F2 : 0.0;
+                }
+                const int rowo = off0 + bq * cst[d1] + e * cst[d2];
+#pragma unroll
+                for (int a = 0; a <= O; ++a) {
+                    if (a == O && !mc) continue;
+                    // bits of (1.5*2^52 + round(P_a F fac 2^e)): see the header.  A pair
+                    // adds its two patterns as integers: each contribution is rounded on its
+                    // own, as by two atomics (a chained FMA would round the second one
+                    // against the first, and a tie could then round the other way).
+                    unsigned long long bits = (unsigned long long)__double_as_longlong(fma(Pq1[a], Fd1, ROUND_MAGIC));
+                    if (PAIR) bits += (unsigned long long)__double_as_longlong(fma(Pq2[a], Fd2, ROUND_MAGIC));
+                    atomicAdd(Jc + rowo + a * cst[comp], bits);
+                }
+            }
+        }
+    }
+}
+
 // One tile of one run: the whole particle step of the tile's particles (the body shared by
 // the single-run kernel and the batched kernel, so both do identical arithmetic).
+// Each wavefront takes 128 consecutive slots at a time, lane l the slots l and 64 + l.  In
+// the full rounds of the round-major order (every cell of the tile present) both are a
+// particle of the same cell, whose current windows start at the same node unless one of the
+// particles crossed a face the storage did not expect; such pairs deposit together with one
+// atomic per node for both.  Where some lane's pair does not share a window, that lane's
+// second particle deposits alone in a second pass; where no lane's does (the partial rounds,
+// whose lanes change cells), each particle deposits alone.
 template <int O, class TL>
 __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, unsigned char* lds_raw) {
     const TL L(A);
@@ -279,7 +627,6 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
     const int tk = (int)(tile / ((int64_t)A.nt[0] * A.nt[1]));
     const int org[3] = {ti * L.tx, tj * L.ty, tk * L.tz};
     const int n0 = A.n[0], n1 = A.n[1], n2 = A.n[2];
-    const int nxy = n0 * n1;
 
     // fields first: the gather's LDS reads then use small immediate offsets
     float* fld = (float*)lds_raw;  // 6 * fvol
@@ -306,265 +653,47 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
     for (int q = threadIdx.x; q < A.nslots; q += GPD32_BS) slots[q] = 0;
     __syncthreads();
 
-    const int64_t base_cell = (int64_t)org[0] + (int64_t)n0 * (org[1] + (int64_t)n1 * org[2]);
+    TileCtx C;
+    for (int d = 0; d < 3; ++d) C.org[d] = org[d];
+    C.base_cell = (int64_t)org[0] + (int64_t)n0 * (org[1] + (int64_t)n1 * org[2]);
+    C.nxy = n0 * n1;
+    C.fld = fld;
+    C.cur = cur;
+    C.slots = slots;
     const double qs = *A.qscale;
     int bad_all = 0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
     for (int s = 0; s < A.nsp; ++s) {
         const Sp32& S = A.sp[s];
         const int32_t start = S.start[tile];
         const int32_t end = S.start[tile + 1];
-        const double facq[3] = {S.fac[0] * qs, S.fac[1] * qs, S.fac[2] * qs};
-        const double qwq = S.qw * qs;
-        for (int32_t q = start + threadIdx.x; q < end; q += GPD32_BS) {
-            const int32_t p = S.perm ? S.perm[q] : q;
-            if (p < 0) {  // an empty slot (counts made inconsistent by flagged particles)
-                S.rank[q] = -1;
-                continue;
-            }
-            const int32_t cell = S.cell[p];
-            float f[3] = {S.pos[0][p], S.pos[1][p], S.pos[2][p]};
-            V3<float> u{S.u[0][p], S.u[1][p], S.u[2][p]};
-            if (S.id) S.id_o[q] = S.id[p];
-            // a particle left as it is still moves to its slot when the kernel reorders
-            auto keep = [&](const V3<float>& uk) {
-                if (!S.perm) return;
-                S.cell_o[q] = cell;
-                S.pos_o[0][q] = f[0];
-                S.pos_o[1][q] = f[1];
-                S.pos_o[2][q] = f[2];
-                S.u_o[0][q] = uk.x;
-                S.u_o[1][q] = uk.y;
-                S.u_o[2][q] = uk.z;
-            };
-            // position inside the tile: rel = li + n0 lj + n0 n1 lk with l < t, found by
-            // comparisons (no division)
-            int64_t rel = (int64_t)cell - base_cell;
-            int lk = 0, lj = 0;
-            while (lk < L.tz - 1 && rel >= (int64_t)nxy) {
-                rel -= nxy;
-                ++lk;
-            }
-            while (lj < L.ty - 1 && rel >= (int64_t)n0) {
-                rel -= n0;
-                ++lj;
-            }
-            const int li = (int)rel;
-            const int loc[3] = {li, lj, lk};
-            // the particle must lie in this tile: local indices in range and the cell index
-            // rebuilt from them equal to the stored one
-            const bool inside = rel >= 0 && li < L.tx && org[0] + li < n0 && org[1] + lj < n1 && org[2] + lk < n2 &&
-                                (int64_t)(org[0] + li) + (int64_t)n0 * ((org[1] + lj) + (int64_t)n1 * (org[2] + lk)) ==
-                                    (int64_t)cell;
-            if (!inside) {  // not this tile's particle: left out of the next sort
-                bad_all |= PP_FLAG_OUT_OF_TILE;
-                keep(u);
-                S.rank[q] = -1;
-                continue;
-            }
-            if (!offset_ok<O>(f[0]) || !offset_ok<O>(f[1]) || !offset_ok<O>(f[2])) {  // left as it is
-                bad_all |= PP_FLAG_OUT_OF_TILE;
-                keep(u);
-                S.rank[q] = dest_rank(A, S, slots, loc, cell);
-                continue;
-            }
-
-            // gather (eq. "pfields") from the LDS field tile
-            float wc[3][O + 1], ws[3][O + 1];
-            int fc[3], fs[3];
-            {
-                const int flo[3] = {L.flox, L.floy, L.floz};
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    int bc, bs;
-                    split_weights<O>(f[d], wc[d], bc, ws[d], bs);
-                    fc[d] = loc[d] + flo[d] + bc;
-                    fs[d] = loc[d] + flo[d] + bs;
+        for (int d = 0; d < 3; ++d) C.facq[d] = S.fac[d] * qs;
+        C.qwq = S.qw * qs;
+        for (int32_t b = start + 128 * wave; b < end; b += 4 * 128) {
+            Win<O> W1, W2;
+            const int32_t q1 = b + lane, q2 = b + 64 + lane;
+            W1.dep = W2.dep = false;
+            if (q1 < end) step_particle<O, TL>(A, S, L, C, q1, W1, bad_all);
+            if (q2 < end) step_particle<O, TL>(A, S, L, C, q2, W2, bad_all);
+            const bool both = W1.dep && W2.dep;
+            const bool same = both && window_start<O, TL>(L, W1, 0) == window_start<O, TL>(L, W2, 0) &&
+                              window_start<O, TL>(L, W1, 1) == window_start<O, TL>(L, W2, 1) &&
+                              window_start<O, TL>(L, W1, 2) == window_start<O, TL>(L, W2, 2);
+            if (__any(same)) {
+                // the first particle of every lane (or its second, if only that one deposits),
+                // together with the second where the windows coincide
+                if (!W1.dep && W2.dep) {
+                    W1 = W2;
+                    W2.dep = false;
                 }
-            }
-            V3<float> E, B;
-            E.x = gather_comp<O>(fld + 0 * L.fvol, L, fs[0], fc[1], fc[2], ws[0], wc[1], wc[2]);
-            E.y = gather_comp<O>(fld + 1 * L.fvol, L, fc[0], fs[1], fc[2], wc[0], ws[1], wc[2]);
-            E.z = gather_comp<O>(fld + 2 * L.fvol, L, fc[0], fc[1], fs[2], wc[0], wc[1], ws[2]);
-            B.x = gather_comp<O>(fld + 3 * L.fvol, L, fc[0], fs[1], fs[2], wc[0], ws[1], ws[2]);
-            B.y = gather_comp<O>(fld + 4 * L.fvol, L, fs[0], fc[1], fs[2], ws[0], wc[1], ws[2]);
-            B.z = gather_comp<O>(fld + 5 * L.fvol, L, fs[0], fs[1], fc[2], ws[0], ws[1], wc[2]);
-
-            const V3<float> um = u;
-            if (A.pusher == PP_PUSH_BORIS)
-                push_boris<float>(S.h, A.ic, E, B, u);
-            else
-                push_vay<float>(S.h, A.ic, E, B, u);
-            if (S.krad != 0.0f) rad_cool<float>(S.krad, A.dtk, A.ic, um, u);
-
-            const float ig = rsqrtf(1.0f + dot(u, u) * A.ic * A.ic);
-            const float uu[3] = {u.x, u.y, u.z};
-            float x1[3], dxs[3];
-            int bad = 0;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const float dd = A.dt * uu[d] * ig * A.inv_d[d];
-                if (!(fabsf(dd) < 1.0f)) bad |= isfinite(dd) ? PP_FLAG_CFL : PP_FLAG_NONFINITE;
-                if (!isfinite(uu[d])) bad |= PP_FLAG_NONFINITE;
-                x1[d] = f[d] + dd;  // new position relative to the old cell's node
-                dxs[d] = dd;
-            }
-            if (bad) {  // left as it was before the push
-                bad_all |= bad;
-                keep(um);
-                S.rank[q] = dest_rank(A, S, slots, loc, cell);
-                continue;
-            }
-
-            if (A.direct) {
-                // direct current (eq. "jj2"): q w v_c W at J_c's staggered nodes, at the
-                // time-centred offset f + dd/2 (its supports stay inside the block's halo)
-                float wcm[3][O + 1], wsm[3][O + 1];
-                int ncm[3], nsm[3];
-                const int clo[3] = {L.clox, L.cloy, L.cloz};
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    int bc, bs;
-                    split_weights<O>(f[d] + 0.5f * dxs[d], wcm[d], bc, wsm[d], bs);
-                    ncm[d] = loc[d] + clo[d] + bc;
-                    nsm[d] = loc[d] + clo[d] + bs;
-                }
-                const int cst[3] = {L.csx, L.csy, L.csz};
-#pragma unroll
-                for (int comp = 0; comp < 3; ++comp) {
-                    unsigned long long* Jc = cur + comp * L.cvol;
-                    const double vq = qwq * (double)(uu[comp] * ig);
-                    const int n0x = comp == 0 ? nsm[0] : ncm[0];
-                    const int n0y = comp == 1 ? nsm[1] : ncm[1];
-                    const int n0z = comp == 2 ? nsm[2] : ncm[2];
-                    const float* wx = comp == 0 ? wsm[0] : wcm[0];
-                    const float* wy = comp == 1 ? wsm[1] : wcm[1];
-                    const float* wz = comp == 2 ? wsm[2] : wcm[2];
-#pragma unroll
-                    for (int c = 0; c <= O; ++c) {
-#pragma unroll
-                        for (int b = 0; b <= O; ++b) {
-                            const double wzy = vq * (double)(wz[c] * wy[b]);
-                            const int rowo = n0x * cst[0] + (n0y + b) * cst[1] + (n0z + c) * cst[2];
-#pragma unroll
-                            for (int a = 0; a <= O; ++a) {
-                                const double dq = fma(wzy, (double)wx[a], ROUND_MAGIC);
-                                atomicAdd(Jc + rowo + a * cst[0], (unsigned long long)__double_as_longlong(dq));
-                            }
-                        }
-                    }
-                }
+                if (W1.dep)
+                    deposit_cc<O, TL, true>(L, cur, W1, C.facq, W2, C.facq, same ? 1.0f : 0.0f);
+                if (both && !same) deposit_cc<O, TL, false>(L, cur, W2, C.facq, W2, C.facq, 0.0f);
             } else {
-            // Esirkepov current on the common window of O+2 centred nodes per axis
-            float S0[3][O + 2], DS[3][O + 2];
-            int wb[3];
-            bool moved[3];  // old and new supports differ along the axis
-            {
-                const int clo[3] = {L.clox, L.cloy, L.cloz};
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    float w0[O + 1], w1[O + 1];
-                    const int a0 = centred_weights<O>(f[d], w0);
-                    const int a1 = centred_weights<O>(x1[d], w1);
-                    const bool lo1 = a1 < a0;  // the new support starts one node lower
-                    const bool hi1 = a1 > a0;
-                    const int bmin = lo1 ? a1 : a0;
-#pragma unroll
-                    for (int kk = 0; kk < O + 2; ++kk) {
-                        // old weights sit at window offset (a0 - bmin), new at (a1 - bmin)
-                        const float s0 = lo1 ? (kk >= 1 ? w0[kk - 1 < O ? kk - 1 : O] : 0.f)
-                                             : (kk <= O ? w0[kk <= O ? kk : O] : 0.f);
-                        const float s1 = hi1 ? (kk >= 1 ? w1[kk - 1 < O ? kk - 1 : O] : 0.f)
-                                             : (kk <= O ? w1[kk <= O ? kk : O] : 0.f);
-                        S0[d][kk] = s0;
-                        DS[d][kk] = s1 - s0;
-                    }
-                    wb[d] = loc[d] + clo[d] + bmin;
-                    moved[d] = lo1 || hi1;
-                }
+                if (W1.dep) deposit_cc<O, TL, false>(L, cur, W1, C.facq, W1, C.facq, 0.0f);
+                if (W2.dep) deposit_cc<O, TL, false>(L, cur, W2, C.facq, W2, C.facq, 0.0f);
             }
-            const int cst[3] = {L.csx, L.csy, L.csz};
-#pragma unroll
-            for (int comp = 0; comp < 3; ++comp) {
-                const int d1 = comp == 0 ? 1 : (comp == 1 ? 2 : 0);
-                const int d2 = comp == 0 ? 2 : (comp == 1 ? 0 : 1);
-                unsigned long long* Jc = cur + comp * L.cvol;
-                const int off0 = wb[0] * L.csx + wb[1] * L.csy + wb[2] * L.csz;
-                // prefix sums of DS along the component's own axis (the last one vanishes),
-                // scaled to fixed-point units: P_a * fac * 2^e in FP64
-                double Pq[O + 1];
-                float acc = 0.f;
-#pragma unroll
-                for (int a = 0; a <= O; ++a) {
-                    acc += DS[comp][a];
-                    Pq[a] = (double)acc * facq[comp];
-                }
-                // Along an axis where the supports coincide the window's last node carries no
-                // weight (its transverse factors are exactly zero) and the last prefix sum is
-                // the rounding residue of a vanishing sum: those additions are left out.
-#pragma unroll
-                for (int bq = 0; bq < O + 2; ++bq) {
-                    if (bq == O + 1 && !moved[d1]) continue;
-                    // F = S0_1 (S0_2 + DS_2/2) + DS_1 (S0_2/2 + DS_2/3)
-                    const float g1 = S0[d1][bq], h1 = DS[d1][bq];
-#pragma unroll
-                    for (int e = 0; e < O + 2; ++e) {
-                        if (e == O + 1 && !moved[d2]) continue;
-                        const float Fq = g1 * (S0[d2][e] + 0.5f * DS[d2][e]) +
-                                         h1 * (0.5f * S0[d2][e] + (1.0f / 3.0f) * DS[d2][e]);
-                        const double Fd = (double)Fq;
-                        const int rowo = off0 + bq * cst[d1] + e * cst[d2];
-#pragma unroll
-                        for (int a = 0; a <= O; ++a) {
-                            if (a == O && !moved[comp]) continue;
-                            // bits of (1.5*2^52 + round(P_a F fac 2^e)): see the header
-                            const double dq = fma(Pq[a], Fd, ROUND_MAGIC);
-                            atomicAdd(Jc + rowo + a * cst[comp], (unsigned long long)__double_as_longlong(dq));
-                        }
-                    }
-                }
-            }
-
-            }
-
-            // renormalise: new cell and offset in [lo, lo + 1), or in [lo + 1, lo + 2) in the
-            // cell below when the next displacement (this one times the ratio of the next drift
-            // to this one) would cross the lower face
-            int nc3[3], shv[3];
-            float fn[3];
-            const int gc[3] = {org[0] + li, org[1] + lj, org[2] + lk};
-            const float lo = off_lo<O>();
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                float sh = floorf(x1[d] - lo);
-                float o = x1[d] - sh;
-                // rounding can land the offset just outside the range: move it back in
-                if (o < lo) {
-                    o += 1.0f;
-                    sh -= 1.0f;
-                } else if (o >= lo + 1.0f) {
-                    o -= 1.0f;
-                    sh += 1.0f;
-                }
-                const float up = o + 1.0f;
-                if (o + dxs[d] * A.pred < lo && up < lo + 2.0f) {
-                    o = up;
-                    sh -= 1.0f;
-                }
-                fn[d] = o;
-                shv[d] = (int)sh;
-                nc3[d] = wrap(gc[d] + (int)sh, A.n[d]);
-            }
-            const int32_t newcell = nc3[0] + n0 * (nc3[1] + n1 * nc3[2]);
-            S.cell_o[q] = newcell;
-            S.pos_o[0][q] = fn[0];
-            S.pos_o[1][q] = fn[1];
-            S.pos_o[2][q] = fn[2];
-            S.u_o[0][q] = u.x;
-            S.u_o[1][q] = u.y;
-            S.u_o[2][q] = u.z;
-            const int dst[3] = {li + shv[0], lj + shv[1], lk + shv[2]};
-            S.rank[q] = dest_rank(A, S, slots, dst, newcell);
         }
         // reserve the tile's range in each destination cell's count, then complete the ranks
         __syncthreads();
@@ -608,7 +737,7 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
 }
 
 template <int O, class TL>
-__global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
+__global__ void __launch_bounds__(GPD32_BS, 3) k_gpd32(Gpd32Args A) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     // XCD-aware tile order: consecutive workgroups go round-robin over the 8 XCDs, so give
     // each XCD a contiguous run of tiles (neighbouring tiles share halos in that XCD's L2).
@@ -620,7 +749,7 @@ __global__ void __launch_bounds__(GPD32_BS) k_gpd32(Gpd32Args A) {
 
 // Batched: block b of the launch is tile b - prefix[r] of run r (prefix = running tile counts).
 template <int O, class TL>
-__global__ void __launch_bounds__(GPD32_BS) k_gpd32_batch(const Gpd32Args* __restrict__ table,
+__global__ void __launch_bounds__(GPD32_BS, 3) k_gpd32_batch(const Gpd32Args* __restrict__ table,
                                                           const int64_t* __restrict__ prefix, int nruns) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int64_t b = blockIdx.x;
