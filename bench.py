@@ -26,7 +26,6 @@ if ROOT not in sys.path:
 
 SEED = 12114575
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
 def log(*a):
@@ -183,24 +182,50 @@ def flops_per_update(O=3, direct=False):
     return weights + gather + push + move + 3 * per_comp
 
 
-# LDS issue model of the tiled particle kernel (cubic weights, 4x4x4 tiles): per wavefront of
-# 64 particles it issues 300 64-bit integer atomic adds (the current) and 192 paired 32-bit
-# reads (the gather: 6 components x 64 nodes).  Measured on gfx950 with aligned addresses:
-# 6.3 clk per 64-lane 64-bit atomic add; a paired read moves 128 dwords at 32 banks per clk.
+# LDS rate measured on gfx950 by bench_lds_rates.hip (python bench.py --lds-probe): 6.3 clk
+# per CU for one 64-lane 64-bit integer atomic add with aligned, distinct addresses.
 LDS_CLK_PER_WAVE_ATOMIC = 6.3
-LDS_CLK_PER_WAVE_READ2 = 4.0
 CUS, CLOCK_HZ = 256, 2.4e9
 
 
-def lds_bound_updates_per_s(O=3):
-    """Particle updates/s at which the LDS pipe would be busy 100 % of the time with
-    conflict-free accesses (the kernel's binding resource): 256 CUs x 2.4 GHz over the LDS
-    cycles one particle needs."""
-    n1, n2 = O + 1, O + 2
-    atomics = 3 * n1 * n2 * n2
-    reads2 = 6 * n1 ** 3 // 2
-    clk = (atomics * LDS_CLK_PER_WAVE_ATOMIC + reads2 * LDS_CLK_PER_WAVE_READ2) / 64.0
-    return CUS * CLOCK_HZ / clk
+BYTES_PER_UPDATE = 56.0  # split state read + written: int32 cell + 3 FP32 offsets + 3 FP32 u
+
+
+def kernel_roofline(npart, gpd_ms, direct=False):
+    """The dominant kernel against three ceilings.  Primary: HBM, algorithmic bytes (56 per
+    particle update) over the live launch time against 8 TB/s, with the counted traffic when
+    the committed counter summary matches these kernel sources.  From the same summary: VALU,
+    counted wavefront instructions over the launch time against one per clock per CU (the
+    unpacked rate: the build turns packed FP32 off, and FP64 FMA issues at that rate too), and
+    LDS atomics, counted ds_add instructions over the launch time against the rate the LDS
+    probe measures for aligned 64-lane 64-bit adds."""
+    sec = gpd_ms * 1e-3
+    achieved_gbs = npart * BYTES_PER_UPDATE / sec / 1e9
+    traffic = measured_traffic(npart)
+    cs = read_counter_summary(npart)
+    out = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_gpd32<3>",
+           "gpd_ms": round(gpd_ms, 3), "algorithmic_bytes_per_launch": npart * BYTES_PER_UPDATE,
+           "flop_per_update_model": flops_per_update(3, direct=direct)}
+    if cs is None or "valu_insts_per_launch" not in cs:
+        out["valu"] = out["lds_atomic"] = None
+        out["counters"] = "no counter summary for these kernel sources"
+        return out
+    valu_peak = CUS * CLOCK_HZ  # wavefront instructions/s, one per clock per CU
+    v = cs["valu_insts_per_launch"] / sec
+    out["valu"] = {"bound": "alu", "achieved": v, "peak": valu_peak, "unit": "VALU wavefront instr/s",
+                   "frac": round(v / valu_peak, 4), "insts_per_64_particles": round(cs["valu_insts_per_launch"] * 64 / npart, 1)}
+    if "lds_atomic_insts_per_launch" in cs:
+        lds_peak = CUS * CLOCK_HZ / LDS_CLK_PER_WAVE_ATOMIC
+        la = cs["lds_atomic_insts_per_launch"] / sec
+        out["lds_atomic"] = {"bound": "lds", "achieved": la, "peak": lds_peak, "unit": "ds_add wavefront instr/s",
+                             "frac": round(la / lds_peak, 4),
+                             "atomics_per_64_particles": round(cs["lds_atomic_insts_per_launch"] * 64 / npart, 1),
+                             "lds_insts_per_64_particles": round(cs.get("lds_insts_per_launch", float("nan")) * 64 / npart, 1)}
+    fr = {"hbm": out["frac"], "valu": out["valu"]["frac"], "lds_atomic": out.get("lds_atomic", {}).get("frac", 0.0)}
+    out["binding"] = max(fr, key=fr.get)
+    out["counters"] = f"profiles/k_gpd32_pair_mj_256_counters.md, digest {cs.get('kernel_source_digest', '')}"
+    return out
 
 
 def kernel_source_digest():
@@ -218,6 +243,19 @@ def measured_traffic(particles):
     (FETCH_SIZE and WRITE_SIZE, each divided by what the same counter reads per byte of a plain
     copy of known size), or None when the summary is missing, for another workload, or was
     taken on other kernel sources."""
+    v = read_counter_summary(particles)
+    try:
+        f = v["fetch_kib_per_launch"] * 1024.0 / (v["copy_fetch_kib"] * 1024.0 / v["copy_bytes"])
+        w = v["write_kib_per_launch"] * 1024.0 / (v["copy_write_kib"] * 1024.0 / v["copy_bytes"])
+        return f + w
+    except (TypeError, KeyError, ZeroDivisionError):
+        return None
+
+
+def read_counter_summary(particles):
+    """Figures of the committed rocprofv3 counter summary of the dominant kernel (per launch), or
+    None when the summary is missing, for another workload, or was taken on other kernel
+    sources."""
     path = os.path.join(ROOT, "profiles", "k_gpd32_pair_mj_256_counters.md")
     if not os.path.exists(path):
         return None
@@ -228,15 +266,145 @@ def measured_traffic(particles):
             k, v = line[2:].split(": ", 1)
             vals[k.strip()] = v.strip()
     try:
-        if vals.get("kernel_source_digest") != kernel_source_digest():
+        if vals.get("kernel_source_digest") != kernel_source_digest() or int(vals["particles"]) != particles:
             return None
-        if int(vals["particles"]) != particles:
-            return None
-        f = float(vals["fetch_kib_per_launch"]) * 1024.0 / (float(vals["copy_fetch_kib"]) * 1024.0 / float(vals["copy_bytes"]))
-        w = float(vals["write_kib_per_launch"]) * 1024.0 / (float(vals["copy_write_kib"]) * 1024.0 / float(vals["copy_bytes"]))
-        return f + w
-    except (KeyError, ValueError, ZeroDivisionError):
+        out = {k: float(v) for k, v in vals.items() if k != "kernel_source_digest"}
+        out["kernel_source_digest"] = vals["kernel_source_digest"]
+        return out
+    except (KeyError, ValueError):
         return None
+
+
+def _pmc_rows(d):
+    """(kernel name, dispatch id) -> {counter: value summed over the rows of that dispatch},
+    and the same key -> kernel duration in ms, from one rocprofv3 --pmc output folder."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {d}")
+    agg, dur = {}, {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            key = (r["Kernel_Name"], int(r["Dispatch_Id"]))
+            c = agg.setdefault(key, {})
+            c[r["Counter_Name"]] = c.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            dur[key] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+    return agg, dur
+
+
+XCDS = 8  # GRBM_GUI_ACTIVE comes summed over the accelerator's XCDs
+
+
+def counter_summary(dirs, out, particles, cmds):
+    """Write the counter summary of the dominant kernel (the cubic 4x4x4-tile particle kernel,
+    launches after the first, which follows the initial sort) from rocprofv3 --pmc folders:
+    HBM bytes (FETCH_SIZE, WRITE_SIZE, calibrated on the largest device copy of the same runs)
+    and the instruction and LDS counters, per launch, with the digest of the kernel's sources."""
+    import statistics
+    per, copy, times = {}, {}, []
+    for d in dirs:
+        agg, dur = _pmc_rows(d)
+        launches = sorted((k for k in agg if "k_gpd32<3, pp::TileCT<3, 4, 4, 4, false>" in k[0]), key=lambda k: k[1])
+        for key in launches[1:]:
+            for cname, v in agg[key].items():
+                per.setdefault(cname, []).append(v)
+            times.append(dur[key])
+        copies = [k for k in agg if "copyBuffer" in k[0]]
+        if copies:
+            big = max(copies, key=lambda k: dur[k])
+            copy.update(agg[big])
+    mean = {k: statistics.fmean(v) for k, v in per.items()}
+    ms = statistics.median(times)
+    n64 = particles / 64.0
+    lines = ["# k_gpd32 — counters of the particle kernel, pair plasma 256^3, 32 ppc/species", "",
+             "Commands (one rocprofv3 pass each; every pass runs the benchmark for one warm-up and one timed step,"
+             " and the figures are means over the kernel's launches after the first):", "", "```"]
+    lines += list(cmds) + ["```", ""]
+    if "SQ_INSTS_VALU" in mean:
+        lines.append(f"Per 64 particles (one wavefront's share): {mean['SQ_INSTS_VALU'] / n64:.0f} VALU instructions; "
+                     f"{mean.get('SQ_INSTS_LDS', float('nan')) / n64:.0f} LDS instructions, of which "
+                     f"{mean.get('SQ_INSTS_LDS_ATOMIC', float('nan')) / n64:.0f} atomics.")
+    if "GRBM_GUI_ACTIVE" in mean:
+        cyc = mean["GRBM_GUI_ACTIVE"] / XCDS * CUS
+        parts = [f"{label} {100 * mean[c] / cyc:.0f} %" for c, label in
+                 (("SQ_INSTS_VALU", "VALU issue (instructions / CU cycles)"), ("SQ_ACTIVE_INST_VALU", "VALU active"),
+                  ("SQ_LDS_IDX_ACTIVE", "LDS active"), ("SQ_LDS_BANK_CONFLICT", "LDS bank-conflict cycles"),
+                  ("SQ_ACTIVE_INST_LDS", "LDS instruction active"), ("SQ_BUSY_CU_CYCLES", "CU busy"))
+                 if c in mean]
+        lines.append(f"CU cycles per launch: GRBM_GUI_ACTIVE / {XCDS} XCDs x {CUS} CUs = {cyc:.4g}; per CU cycle: "
+                     + ", ".join(parts) + ".")
+    if "FETCH_SIZE" in mean and "FETCH_SIZE" in copy:
+        cb = 4 * (1 << 30)
+        fb = mean["FETCH_SIZE"] / (copy["FETCH_SIZE"] / cb)
+        line = f"HBM traffic per launch: FETCH {fb / 1e9:.2f} GB"
+        if "WRITE_SIZE" in mean and "WRITE_SIZE" in copy:
+            wb = mean["WRITE_SIZE"] / (copy["WRITE_SIZE"] / cb)
+            line += f", WRITE {wb / 1e9:.2f} GB, total {(fb + wb) / 1e9:.2f} GB"
+        line += (f", against {BYTES_PER_UPDATE * particles / 1e9:.2f} GB algorithmic (56 B per particle update). "
+                 f"Calibration: the 4 GiB device copy (`__amd_rocclr_copyBuffer`, reads and writes 4 GiB) reads "
+                 f"FETCH_SIZE {copy['FETCH_SIZE']:.6g} KiB and WRITE_SIZE {copy.get('WRITE_SIZE', float('nan')):.6g} KiB; "
+                 f"a kernel's counter is divided by the copy's counter per byte.")
+        lines.append(line)
+    lines += ["", f"Kernel time under the profiler (median of those launches): {ms:.3f} ms.", "",
+              "Machine-read by bench.py (used only while the kernel sources are unchanged):", "",
+              f"- kernel_source_digest: {kernel_source_digest()}", f"- particles: {particles}", f"- kernel_ms: {ms:.6g}"]
+    keymap = {"FETCH_SIZE": "fetch_kib_per_launch", "WRITE_SIZE": "write_kib_per_launch",
+              "SQ_INSTS_VALU": "valu_insts_per_launch", "SQ_INSTS_LDS": "lds_insts_per_launch",
+              "SQ_INSTS_LDS_ATOMIC": "lds_atomic_insts_per_launch", "SQ_ACTIVE_INST_VALU": "valu_active_per_launch",
+              "SQ_ACTIVE_INST_LDS": "lds_inst_active_per_launch", "SQ_LDS_IDX_ACTIVE": "lds_active_per_launch",
+              "SQ_LDS_BANK_CONFLICT": "lds_conflict_per_launch", "SQ_WAVE_CYCLES": "wave_cycles_per_launch",
+              "SQ_BUSY_CYCLES": "sq_busy_cycles_per_launch", "SQ_BUSY_CU_CYCLES": "cu_busy_cycles_per_launch",
+              "GRBM_GUI_ACTIVE": "gui_active_per_launch"}
+    for cname, key in keymap.items():
+        if cname in mean:
+            lines.append(f"- {key}: {mean[cname]:.6g}")
+    if "FETCH_SIZE" in copy:
+        lines += [f"- copy_bytes: {4 * (1 << 30)}", f"- copy_fetch_kib: {copy['FETCH_SIZE']:.6g}"]
+        if "WRITE_SIZE" in copy:
+            lines.append(f"- copy_write_kib: {copy['WRITE_SIZE']:.6g}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    return out
+
+
+def stats_summary(d, out, particles, cmd):
+    """Write the kernel-time summary of one rocprofv3 --kernel-trace --stats folder: the stats
+    table, then the median duration of each kernel over the calls of the steady-state steps
+    (every call after the particle kernel's first launch)."""
+    import csv
+    import glob
+    import statistics
+    st = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    tr = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
+    if not st or not tr:
+        raise FileNotFoundError(f"no kernel_stats.csv / kernel_trace.csv under {d}")
+    lines = [f"# k_gpd32 and the step kernels — kernel times, pair plasma 256^3, 32 ppc/species ({particles:,} particles)",
+             "", "Command (on one MI355X; the benchmark's own step count):", "", "```", cmd, "```", "",
+             "rocprofv3 `--stats` summary (all calls: includes the one-time generation and first sort from random "
+             "order, the first push after it, and the diagnostics after the timed steps):", "",
+             "| Kernel | Calls | Average ms | Min ms | Max ms | % |", "|---|---|---|---|---|---|"]
+    for r in csv.DictReader(open(st[0])):
+        if float(r["Percentage"]) < 0.05:
+            continue
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) * 1e-6:.3f} | "
+                     f"{float(r['MinNs']) * 1e-6:.3f} | {float(r['MaxNs']) * 1e-6:.3f} | {float(r['Percentage']):.2f} |")
+    calls = sorted(csv.DictReader(open(tr[0])), key=lambda r: int(r["Start_Timestamp"]))
+    gpd = [i for i, r in enumerate(calls) if "k_gpd32<3, pp::TileCT<3, 4, 4, 4, false>" in r["Kernel_Name"]]
+    per = {}
+    for r in calls[gpd[0] + 1:] if gpd else []:
+        per.setdefault(r["Kernel_Name"], []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6)
+    lines += ["", "Steady state: median duration per kernel over the calls after the particle kernel's first launch "
+              "(that launch follows the initial sort from random order):", "", "| Kernel | median ms | calls |",
+              "|---|---|---|"]
+    for name, v in per.items():
+        lines.append(f"| `{name[:90]}` | {statistics.median(v):.3f} | {len(v)} |")
+    if gpd:
+        g = [(int(calls[i]["End_Timestamp"]) - int(calls[i]["Start_Timestamp"])) * 1e-6 for i in gpd]
+        lines += ["", f"k_gpd32<3> over its {len(g)} launches: first {g[0]:.3f} ms, then median "
+                      f"{statistics.median(g[1:]):.3f} ms.  bench.py times the same kernel live with HIP events on "
+                      f"its launch stream over the timed steps."]
+    open(out, "w").write("\n".join(lines) + "\n")
+    return out
 
 
 def two_stream_rate(k, v0, wb2=0.5):
@@ -346,13 +514,17 @@ def two_stream_bench(args, torch, pp):
     return 0
 
 
-def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress=250):
+def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress=250, kmax_index=16):
     """Mixed-mode two-stream run on g^3 cells of a cubic box of ``box`` skin depths, generated
     on the device (FP32 split form).  Returns (times, energies [steps + 1, 4], wall s,
-    particles, final diagnostics): per step the energy of E projected on the MMI direction
-    (74 degrees from the beam: |E_perp| sin + E_z cos), of E_z, and of the x-y mean of E_z
-    (wave vectors along the beam); every half time unit (NaN otherwise) the longitudinal field
-    energy E.k/|k| of the Fourier modes 60-80 degrees from the beam with 1 <= |k| <= 8."""
+    particles, final diagnostics, (sample times, wave-number indices, bin energies)): per step
+    the energy of E projected on the MMI direction (74 degrees from the beam: |E_perp| sin +
+    E_z cos), of E_z (the same projection at 0 degrees, the TSI direction), of the x-y mean
+    of E_z (wave vectors along the beam), and the volume integral of the projection itself
+    (the paper's formula read literally, linear in E); every half time unit (NaN otherwise) the
+    longitudinal field energy E.k/|k| of the Fourier modes 60-80 degrees from the beam with
+    1 <= |k| <= 8, and the longitudinal energy of every single Fourier mode whose indices are
+    all within kmax_index (the bin energies, for rates mode by mode)."""
     import numpy as np
 
     from paper_1211_4575_amd import inputs as I
@@ -379,7 +551,7 @@ def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress
     del cells, offs, us
     th = math.radians(74.0)
     dV = dx ** 3
-    hist = torch.zeros((steps + 1, 4), dtype=torch.float64, device=dev)
+    hist = torch.zeros((steps + 1, 5), dtype=torch.float64, device=dev)
     k1 = torch.fft.fftfreq(g, d=dx, device=dev, dtype=torch.float64) * (2 * math.pi)
     KZ, KY, KX = torch.meshgrid(k1, k1, k1, indexing="ij")
     KK = torch.sqrt(KX * KX + KY * KY + KZ * KZ)
@@ -387,6 +559,11 @@ def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress
     band = ((ang >= 60) & (ang <= 80) & (KK >= 1) & (KK <= 8)).to(torch.float64)
     KKs = torch.where(KK > 0, KK, torch.ones_like(KK))
     spec_every = max(1, int(round(0.5 / dt)))
+    # wave-number indices 0..kmax, -kmax..-1 as FFT positions (index_select takes no negatives)
+    assert 0 <= kmax_index and 2 * kmax_index < g, (kmax_index, g)
+    kneg = list(range(0, kmax_index + 1)) + list(range(-kmax_index, 0))
+    kidx = torch.tensor([m % g for m in kneg], device=dev)
+    bins, bin_t = [], []
 
     def record(i):
         Ex, Ey, Ez = run.E[0], run.E[1], run.E[2]
@@ -395,9 +572,13 @@ def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress
         hist[i, 0] = 0.5 * dV * (proj * proj).sum()
         hist[i, 1] = 0.5 * dV * (Ez * Ez).sum()
         hist[i, 2] = 0.5 * dV * n[0] * n[1] * (ezm * ezm).sum()
+        hist[i, 4] = dV * proj.sum()
         if i % spec_every == 0:
             lon = (torch.fft.fftn(Ex) * KX + torch.fft.fftn(Ey) * KY + torch.fft.fftn(Ez) * KZ) / KKs
             hist[i, 3] = 0.5 * dV / (n[0] * n[1] * n[2]) * (band * lon.abs() ** 2).sum()
+            sub = lon.index_select(0, kidx).index_select(1, kidx).index_select(2, kidx)
+            bins.append((0.5 * dV / (n[0] * n[1] * n[2]) * sub.abs() ** 2).to(torch.float32))
+            bin_t.append(i * dt)
         else:
             hist[i, 3] = float("nan")
 
@@ -415,7 +596,46 @@ def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress
     d = run.diagnostics(pp.PP_DIAG_ALL)
     run.close()
     t = np.arange(steps + 1) * dt
-    return t, hist.cpu().numpy(), wall, 4 * npart, d
+    kv = np.array(kneg)
+    return t, hist.cpu().numpy(), wall, 4 * npart, d, (np.array(bin_t), kv, torch.stack(bins).cpu().numpy())
+
+
+def mode_rates(tb, kv, W, dk, width, top=12):
+    """Growth rates mode by mode: for every Fourier bin (indices kz, ky, kx from kv, energies W
+    [samples, z, y, x]) the steepest least-squares half log slope over windows of the given
+    width, after the bin's energy first exceeds 3x its mean over t <= 2.  Returns the ``top``
+    fastest bins (one of each +-k pair) with wave vector, |k|, angle to the beam and rate."""
+    import numpy as np
+    ns = len(tb)
+    L = np.log(np.maximum(W.reshape(ns, -1).astype(np.float64), 1e-300))
+    w = max(3, int(round(width / (tb[1] - tb[0]))) + 1)
+    tt = np.asarray(tb, dtype=float)
+    # least-squares slopes of every window of w samples, all bins at once
+    ts = np.lib.stride_tricks.sliding_window_view(tt, w)
+    tm = ts - ts.mean(axis=1, keepdims=True)
+    den = (tm * tm).sum(axis=1)
+    Ls = np.lib.stride_tricks.sliding_window_view(L, w, axis=0)  # [win, bins, w]
+    slope = np.einsum("wbk,wk->wb", Ls, tm) / den[:, None]
+    early = L[tt <= 2.0].mean(axis=0)
+    started = np.maximum.accumulate(L[:len(ts)] > early + np.log(3.0), axis=0)
+    rate = np.where(started, 0.5 * slope, -np.inf).max(axis=0)
+    KZ, KY, KX = np.meshgrid(kv, kv, kv, indexing="ij")
+    KZ, KY, KX = KZ.ravel() * dk, KY.ravel() * dk, KX.ravel() * dk
+    kk = np.sqrt(KX * KX + KY * KY + KZ * KZ)
+    out, seen = [], set()
+    for b in np.argsort(-rate):
+        if kk[b] == 0 or not np.isfinite(rate[b]):
+            continue
+        key = tuple(np.round([KZ[b] / dk, KY[b] / dk, KX[b] / dk]).astype(int))
+        if tuple(-v for v in key) in seen:
+            continue
+        seen.add(key)
+        ang = math.degrees(math.atan2(math.hypot(KX[b], KY[b]), abs(KZ[b])))
+        out.append({"k": [float(KX[b]), float(KY[b]), float(KZ[b])], "abs_k": float(kk[b]), "angle_deg": ang,
+                    "rate": float(rate[b])})
+        if len(out) == top:
+            break
+    return out
 
 
 def max_growth(t, w, width):
@@ -450,10 +670,12 @@ def mmi_rates_fit(t, H, width):
     steepest-window rate and the least-squares rate over the whole growth phase."""
     import numpy as np
     out = {}
-    for k, col in (("mmi", 0), ("tsi_all_kz", 1), ("tsi", 2), ("mmi_band", 3)):
+    for k, col in (("mmi", 0), ("tsi_all_kz", 1), ("tsi", 2), ("mmi_band", 3), ("mmi_linear", 4)):
         ok = np.isfinite(H[:, col])
-        rate, window = max_growth(t[ok], H[ok, col], width)
-        _, whole, phase = growth_rate_fit(t[ok], H[ok, col], width=width)
+        # the linear measure grows at the amplitude's rate: square it to fit it as an energy
+        w = H[ok, col] ** 2 if col == 4 else H[ok, col]
+        rate, window = max_growth(t[ok], w, width)
+        _, whole, phase = growth_rate_fit(t[ok], w, width=width)
         out[k] = {"rate": rate, "window": window, "rate_whole_phase": whole, "growth_phase": phase}
     return out
 
@@ -469,22 +691,27 @@ def mmi_bench(args, torch, pp):
 
     from paper_1211_4575_amd import inputs as I
     from paper_1211_4575_amd import inputs_device as ind
-    t, H, wall, npart, d = run_mmi(torch, pp, ind, args.mmi_grid, args.mmi_ppc, args.mmi_steps, args.mmi_tb,
-                                   args.mmi_tp)
+    t, H, wall, npart, d, (tb, kv, W) = run_mmi(torch, pp, ind, args.mmi_grid, args.mmi_ppc, args.mmi_steps,
+                                                args.mmi_tb, args.mmi_tp)
     if args.save_history:
-        np.savez(f"{args.save_history}_mmi.npz", t=t, w=H)
+        np.savez(f"{args.save_history}_mmi.npz", t=t, w=H, tb=tb, kv=kv, bins=W)
     theory = I.mmi_rates()
     fits = mmi_rates_fit(t, H, args.mmi_fit_width)
     for k, v in fits.items():
         v["rate_over_theory"] = v["rate"] / (theory["tsi"] if k.startswith("tsi") else theory["mmi"])
         log(f"[mmi] {k}: {v}")
     g = args.mmi_grid
+    fits["gamma_tsi_theta0"] = fits["tsi_all_kz"]["rate"]  # the projection at theta_TSI = 0: E_z
+    modes = mode_rates(tb, kv, W, 2 * math.pi / 12.8, args.mmi_fit_width)
+    for m in modes:
+        log(f"[mmi] mode k=({m['k'][0]:+.2f},{m['k'][1]:+.2f},{m['k'][2]:+.2f}) |k|={m['abs_k']:.2f} "
+            f"angle {m['angle_deg']:.0f} deg: rate {m['rate']:.4f}")
     out = {"metric": "relativistic mixed-mode two-stream growth rates / theory and paper",
            "theory": theory, "paper_cubic_cc_6th": {"mmi": 0.205, "tsi": 0.088},
            "config": {"grid": [g, g, g], "ppc_per_species": args.mmi_ppc, "particles": npart, "dx": 12.8 / g,
                       "dt": 0.4 * 12.8 / g, "steps": args.mmi_steps, "T_b": args.mmi_tb, "T_p": args.mmi_tp},
            "updates_per_s": npart * args.mmi_steps / wall, "wall_s": wall,
-           "final_gauss_rel": d.gauss_max / d.rho_ref, "flags": d.flags, **fits}
+           "final_gauss_rel": d.gauss_max / d.rho_ref, "flags": d.flags, "fastest_modes": modes, **fits}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -764,11 +991,26 @@ def main(argv=None):
     ap.add_argument("--ref-steps", type=int, default=3, help="serving: timed steps per class for the references")
     ap.add_argument("--cpu-plan", action="store_true",
                     help="time the CPU oracle on the whole baseline plan (one core and all cores) and exit")
+    ap.add_argument("--counter-summary", nargs="+", default=None, metavar="DIR",
+                    help="write profiles/k_gpd32_pair_mj_256_counters.md from these rocprofv3 --pmc folders and exit")
+    ap.add_argument("--counter-cmd", action="append", default=[], help="command line recorded in the summary")
+    ap.add_argument("--stats-summary", default=None, metavar="DIR",
+                    help="write profiles/k_gpd32_pair_mj_256_kernel_stats.md from this rocprofv3 --stats folder and exit")
     ap.add_argument("--lds-probe", action="store_true",
                     help="build and run the LDS / VALU instruction-rate probe (bench_lds_rates.hip) and exit")
     args = ap.parse_args(argv)
     if args.lds_probe:
         return lds_probe()
+    if args.stats_summary:
+        n = args.grid
+        print(stats_summary(args.stats_summary, os.path.join(ROOT, "profiles", "k_gpd32_pair_mj_256_kernel_stats.md"),
+                            2 * n * n * n * args.ppc, " ".join(args.counter_cmd)))
+        return 0
+    if args.counter_summary:
+        n = args.grid
+        print(counter_summary(args.counter_summary, os.path.join(ROOT, "profiles", "k_gpd32_pair_mj_256_counters.md"),
+                              2 * n * n * n * args.ppc, args.counter_cmd))
+        return 0
     if args.cpu_plan:
         return cpu_plan()
     if args.gpus != 1:
@@ -846,22 +1088,7 @@ def main(argv=None):
         del run
         torch.cuda.empty_cache()
 
-    bytes_per_update = 56.0  # split state read + written: int32 cell + 3 FP32 offsets + 3 FP32 u
-    achieved_gbs = npart * bytes_per_update / (gpd_ms * 1e-3) / 1e9
-    fl = flops_per_update(3, direct=args.current == "direct")
-    achieved_tf = npart * fl / (gpd_ms * 1e-3) / 1e12
-    traffic = measured_traffic(npart)
-    roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved_tf / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": traffic, "kernel": "k_gpd32<3>", "flop_per_update": fl,
-                "algorithmic_bytes_per_launch": npart * bytes_per_update,
-                "hbm_gbs_algorithmic": round(achieved_gbs, 1), "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                "gpd_ms": round(gpd_ms, 3),
-                "lds_model": {"bound": "lds", "achieved": npart / (gpd_ms * 1e-3), "peak": lds_bound_updates_per_s(3),
-                              "unit": "particle updates/s",
-                              "frac": round(npart / (gpd_ms * 1e-3) / lds_bound_updates_per_s(3), 4),
-                              "basis": "300 ds_add_u64 at 6.3 clk + 192 ds_read2_b32 at 4 clk per 64 particles, "
-                                       "256 CU x 2.4 GHz, no bank conflicts"}}
+    roofline = kernel_roofline(npart, gpd_ms, direct=args.current == "direct")
 
     serving = None
     if not args.no_serving:

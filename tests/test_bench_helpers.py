@@ -41,14 +41,57 @@ def test_two_stream_rate_matches_the_cold_dispersion_relation():
     assert abs(g - 0.342867) < 1e-6
 
 
-def test_lds_model_bound_from_its_instruction_counts():
-    # cubic weights: 300 64-bit atomics at 6.3 clk and 192 paired reads at 4 clk per 64
-    # particles, 256 CUs at 2.4 GHz
-    clk = (300 * 6.3 + 192 * 4.0) / 64.0
-    assert bench.lds_bound_updates_per_s(3) == 256 * 2.4e9 / clk
-    # quadratic weights: 3 * 3 * 4 * 4 atomics and 6 * 27 / 2 paired reads
-    clk2 = (144 * 6.3 + 81 * 4.0) / 64.0
-    assert bench.lds_bound_updates_per_s(2) == 256 * 2.4e9 / clk2
+def test_roofline_fractions_from_a_counter_summary(monkeypatch):
+    # one launch of 1.2e9 particles in 100 ms: 56 B each against 8 TB/s; 2.4e10 counted VALU
+    # wavefront instructions against one per clock per CU; 3.0e9 ds_add against the probe rate
+    n, ms = 1_200_000_000, 100.0
+    cs = {"kernel_source_digest": "x", "particles": n, "valu_insts_per_launch": 2.4e10,
+          "lds_insts_per_launch": 5.0e9, "lds_atomic_insts_per_launch": 3.0e9}
+    monkeypatch.setattr(bench, "read_counter_summary", lambda p: cs if p == n else None)
+    monkeypatch.setattr(bench, "measured_traffic", lambda p: None)
+    r = bench.kernel_roofline(n, ms)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert abs(r["frac"] - n * 56 / 0.1 / 8e12) < 1e-4
+    assert abs(r["valu"]["frac"] - 2.4e10 / 0.1 / (256 * 2.4e9)) < 1e-4
+    assert abs(r["lds_atomic"]["frac"] - 3.0e9 / 0.1 / (256 * 2.4e9 / bench.LDS_CLK_PER_WAVE_ATOMIC)) < 1e-4
+    assert r["valu"]["insts_per_64_particles"] == round(2.4e10 * 64 / n, 1)
+    assert r["binding"] == max(("hbm", r["frac"]), ("valu", r["valu"]["frac"]),
+                               ("lds_atomic", r["lds_atomic"]["frac"]), key=lambda t: t[1])[0]
+    # no summary for these sources: only the HBM figure
+    r = bench.kernel_roofline(n + 1, ms)
+    assert r["valu"] is None and r["lds_atomic"] is None and r["frac"] > 0
+
+
+def test_counter_summary_round_trip(tmp_path, monkeypatch):
+    # a rocprofv3-style CSV of two passes (three launches of the particle kernel and one copy)
+    # gives a summary whose machine-read lines reproduce the per-launch means
+    import csv
+    k = "void pp::k_gpd32<3, pp::TileCT<3, 4, 4, 4, false> >(pp::Gpd32Args)"
+    cols = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+    passes = {"a": {"SQ_INSTS_VALU": [9e9, 1e10, 1.2e10], "GRBM_GUI_ACTIVE": [8e8, 8e8, 8e8]},
+              "b": {"FETCH_SIZE": [5e7, 6e7, 8e7]}}
+    for name, cnt in passes.items():
+        d = tmp_path / name
+        d.mkdir()
+        with open(d / "run_counter_collection.csv", "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=cols)
+            w.writeheader()
+            for i in range(3):
+                for c, v in cnt.items():
+                    w.writerow(dict(Dispatch_Id=10 + i, Kernel_Name=k, Counter_Name=c, Counter_Value=v[i],
+                                    Start_Timestamp=0, End_Timestamp=int(100e6)))
+            w.writerow(dict(Dispatch_Id=1, Kernel_Name="__amd_rocclr_copyBuffer", Counter_Name=list(cnt)[0],
+                            Counter_Value=2.0e6, Start_Timestamp=0, End_Timestamp=1000))
+    out = tmp_path / "summary.md"
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: "d" * 16)
+    bench.counter_summary([str(tmp_path / "a"), str(tmp_path / "b")], str(out), 1_000_000, ["cmd a", "cmd b"])
+    text = out.read_text()
+    monkeypatch.setattr(bench, "os", bench.os)
+    vals = dict(line[2:].split(": ", 1) for line in text.splitlines() if line.startswith("- "))
+    assert float(vals["valu_insts_per_launch"]) == 1.1e10  # launches after the first
+    assert float(vals["fetch_kib_per_launch"]) == 7e7
+    assert float(vals["kernel_ms"]) == 100.0
+    assert vals["kernel_source_digest"] == "d" * 16 and "cmd a" in text
 
 
 def test_measured_traffic_is_used_only_for_the_kernel_sources_it_was_taken_on(monkeypatch):
@@ -70,3 +113,25 @@ def test_measured_traffic_is_used_only_for_the_kernel_sources_it_was_taken_on(mo
     assert bench.measured_traffic(n + 1) is None  # another workload
     monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0" * 16)
     assert bench.measured_traffic(n) is None  # counters taken on other kernel sources
+
+
+def test_mode_rates_finds_the_growing_bins():
+    # three bins grow at 0.2, 0.15 and 0.05 from t = 5 on above a flat floor, the others stay
+    # at the floor; a +-k pair appears once, the steepest 6-unit window gives the rates
+    import math
+
+    import numpy as np
+    tb = np.arange(0, 40.01, 0.5)
+    kv = np.array([0, 1, 2, -2, -1])
+    W = np.full((len(tb), 5, 5, 5), 1e-6)
+    grow = np.exp(2 * np.maximum(tb - 5.0, 0.0))
+    W[:, 1, 2, 0] *= grow ** 0.2  # kz = 1, ky = 2, kx = 0
+    W[:, 4, 3, 0] *= grow ** 0.2  # its mirror -k
+    W[:, 2, 0, 1] *= grow ** 0.15
+    W[:, 0, 1, 1] *= grow ** 0.05
+    dk = 2 * math.pi / 12.8
+    m = bench.mode_rates(tb, kv, W, dk, 6.0, top=3)
+    assert [round(x["rate"], 6) for x in m] == [0.2, 0.15, 0.05]
+    assert np.allclose(m[0]["k"], [0.0, 2 * dk, dk]) or np.allclose(m[0]["k"], [0.0, -2 * dk, -dk])
+    assert abs(m[0]["angle_deg"] - math.degrees(math.atan2(2, 1))) < 1e-9
+    assert abs(m[2]["abs_k"] - math.sqrt(2) * dk) < 1e-12

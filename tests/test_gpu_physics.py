@@ -50,7 +50,7 @@ def test_mmi_reduced_grows_and_saturates():
     from paper_1211_4575_amd import inputs_device as ind
     from paper_1211_4575_amd import pp
     print("mmi 64^3", file=sys.stderr, flush=True)
-    t, H, wall, npart, d = bench.run_mmi(torch, pp, ind, 64, 8, 800, 1e-4, 0.01, progress=200)
+    t, H, wall, npart, d, _ = bench.run_mmi(torch, pp, ind, 64, 8, 800, 1e-4, 0.01, progress=200)
     assert d.flags == 0 and d.gauss_max / d.rho_ref < 1e-5
     fits = bench.mmi_rates_fit(t, H, 6.0)
     theory = I.mmi_rates()["mmi"]
