@@ -123,6 +123,12 @@ typedef struct pp_params {
                             * are then a drift of theta dt/2 ahead of the momenta (load
                             * x + theta dt/2 v for synchronised x, u).  Order 4 needs
                             * theta c dt < min(d) and is not accepted by pp_batch_add.   */
+    int32_t gauss_filter_every; /* cadence of the Gauss-law filter passes: 0 or 1 = after
+                            * every field step; k > 1 = only after the field step that
+                            * completes a step whose number (pp_diag.step) is a multiple
+                            * of k (Sec. "Charge conservation": in single precision the
+                            * paper filters about every fifth step).  0..2^20; values
+                            * above 1 need time_order 2.                                */
 } pp_params;
 
 /* Caller-owned FP64 mesh (device pointers, 3*ncell doubles each). */

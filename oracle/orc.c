@@ -45,6 +45,8 @@ typedef struct {
     int32_t gauss_passes; /* passes of the Gauss-law filter after the field step */
     int32_t time_order;   /* 2: leapfrog; 4: Forest-Ruth composition (whole-run  */
                           /* driver, orc.py); the kernels here take one substep */
+    int32_t gauss_every;  /* filter after the field step of every k-th step only  */
+                          /* (whole-run driver, orc.py; 0 or 1: every step)       */
 } orc_params;
 
 /* ------------------------------------------------------------------ */

@@ -57,12 +57,14 @@ class Params(ctypes.Structure):
         ("current_scheme", ctypes.c_int32),
         ("gauss_passes", ctypes.c_int32),
         ("time_order", ctypes.c_int32),
+        ("gauss_every", ctypes.c_int32),
     ]
 
 
 def make_params(n=(16, 16, 16), d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shape_order=2,
                 field_order=2, alpha=0.55, pusher=0, relax_tol=1e-14, relax_max_iter=200,
-                rho_background=0.0, rad_tau=0.0, current_scheme=0, gauss_passes=0, time_order=2) -> Params:
+                rho_background=0.0, rad_tau=0.0, current_scheme=0, gauss_passes=0, time_order=2,
+                gauss_every=1) -> Params:
     p = Params()
     p.n[:] = [int(v) for v in n]
     p.d[:] = [float(v) for v in d]
@@ -74,6 +76,7 @@ def make_params(n=(16, 16, 16), d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shap
     p.rad_tau = float(rad_tau)
     p.current_scheme, p.gauss_passes = int(current_scheme), int(gauss_passes)
     p.time_order = int(time_order)
+    p.gauss_every = int(gauss_every)
     return p
 
 
@@ -342,6 +345,7 @@ class Run:
         self.J = np.zeros(_vec(P))
         self.flags = 0
         self.relax = (0, 0.0)
+        self.nstep = 0  # completed steps
 
     def particles_step(self, P=None, kick=None):
         P = self.P if P is None else P
@@ -355,7 +359,10 @@ class Run:
     def fields_step(self, P=None):
         P = self.P if P is None else P
         self.relax = field_step(P, self.E, self.B, self.J)
-        if P.gauss_passes > 0:  # Gauss-law filter with the charge density of x^{n+1}
+        # Gauss-law filter with the charge density of x^{n+1}, after every step or (in single
+        # precision, the paper's cadence) after every k-th
+        every = max(1, P.gauss_every)
+        if P.gauss_passes > 0 and (self.nstep + (1 if P.time_order != 4 else 0)) % every == 0:
             r = np.zeros(_scal(P))
             for s in self.species:
                 deposit_rho(P, s["q"], s["w"], s["pos"], r)
@@ -370,6 +377,7 @@ class Run:
             return
         self.particles_step()
         self.fields_step()
+        self.nstep += 1
 
     def rho(self):
         r = np.zeros(_scal(self.P))

@@ -47,6 +47,8 @@ static pp_status validate(const pp_params* p) {
     if (p->current_scheme != PP_CURRENT_CC && p->current_scheme != PP_CURRENT_DIRECT) return PP_E_ARG;
     if (p->gauss_filter_passes < 0 || p->gauss_filter_passes > PP_MAX_GAUSS_PASSES) return PP_E_ARG;
     if (p->time_order != 2 && p->time_order != 4) return PP_E_ARG;
+    if (p->gauss_filter_every < 0 || p->gauss_filter_every > (1 << 20)) return PP_E_ARG;
+    if (p->gauss_filter_every > 1 && p->time_order != 2) return PP_E_ARG;
     if (!finite_pos(p->dt) || !finite_pos(p->c) || !finite_pos(p->eps0)) return PP_E_ARG;
     if (p->shape_order != 2 && p->shape_order != 3) return PP_E_ARG;
     if (p->field_order != 2 && p->field_order != 4 && p->field_order != 6) return PP_E_ARG;
@@ -379,7 +381,8 @@ pp_status pp_field_step(pp_run* r) {
     if (!r) return PP_E_ARG;
     hipError_t e = launch_field_step(r);
     if (!ok(e, "field_step")) return PP_E_HIP;
-    if (r->p.gauss_filter_passes > 0) {
+    const int every = r->p.gauss_filter_every;
+    if (r->p.gauss_filter_passes > 0 && (every <= 1 || r->step % every == 0)) {
         e = launch_gauss_filter(r);
         if (!ok(e, "gauss_filter")) return PP_E_HIP;
     }

@@ -48,6 +48,7 @@ class pp_params(ctypes.Structure):
         ("current_scheme", ctypes.c_int32),
         ("gauss_filter_passes", ctypes.c_int32),
         ("time_order", ctypes.c_int32),
+        ("gauss_filter_every", ctypes.c_int32),
     ]
 
 
@@ -242,7 +243,7 @@ def pp_batch_destroy(batch):
 # ---- convenience owner of the torch tensors ---------------------------------------------
 def make_params(n, d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shape_order=2, field_order=2, alpha=0.55,
                 pusher=0, precision=PP_PREC_FP64, relax_tol=1e-14, relax_max_iter=200, rho_background=0.0,
-                rad_tau=0.0, current_scheme=0, gauss_filter_passes=0, time_order=2):
+                rad_tau=0.0, current_scheme=0, gauss_filter_passes=0, time_order=2, gauss_filter_every=1):
     p = pp_params()
     p.n[:] = [int(v) for v in n]
     p.d[:] = [float(v) for v in d]
@@ -254,6 +255,7 @@ def make_params(n, d=(1.0, 1.0, 1.0), dt=0.4, c=1.0, eps0=1.0, shape_order=2, fi
     p.rad_tau = float(rad_tau)
     p.current_scheme, p.gauss_filter_passes = int(current_scheme), int(gauss_filter_passes)
     p.time_order = int(time_order)
+    p.gauss_filter_every = int(gauss_filter_every)
     return p
 
 

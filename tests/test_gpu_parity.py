@@ -3,8 +3,9 @@
 FP64 form: one step, max-norm error relative to the oracle's max <= 1e-12 for u, J, E, B and
 |dX| <= 1e-12 cell.  Split FP32 form: one step from the FP32-rounded state, fields within 1e-5
 (L2, relative to the oracle's change of the field), normalised Gauss residual <= 1e-6,
-offsets within 1e-6 cell, u within 1e-5 relative.  Grids span several tiles with ragged
-edges and single-cell axes."""
+offsets within 1e-6 cell, u within 1e-5 relative; the cases of two to five steps keep the
+same particle bars (measured: offsets within 2e-7 cell, u within 4e-7 after three steps in
+strong fields).  Grids span several tiles with ragged edges and single-cell axes."""
 import sys
 
 import numpy as np
@@ -220,8 +221,10 @@ def test_radiative_cooling_steps_match_oracle(ppm, orc, split):
             g = _by_id(run.particles(s))
             if split:
                 X = I.from_split(g["cell"], g["pos"], n)
-                assert np.max(np.abs(periodic_diff(X, sp["pos"], n))) < 1e-5, (step, s)
-                assert rel_inf(g["u"].astype(np.float64), sp["u"]) < 2e-5, (step, s)
+                ex, eu = np.max(np.abs(periodic_diff(X, sp["pos"], n))), rel_inf(g["u"].astype(np.float64), sp["u"])
+                _say("[err] radiative cooling", step, s, f"x {ex:.3g} u {eu:.3g}")
+                assert ex < 1e-6, (step, s)
+                assert eu < 1e-5, (step, s)
             else:
                 assert np.max(np.abs(periodic_diff(g["pos"], sp["pos"], n))) < 1e-12, (step, s)
                 assert rel_inf(g["u"], sp["u"]) < 1e-12, (step, s)
@@ -268,7 +271,10 @@ def test_direct_current_and_gauss_filter_match_oracle(ppm, orc, ci):
             g = _by_id(run.particles(s))
             if split:
                 X = I.from_split(g["cell"], g["pos"], n)
-                assert np.max(np.abs(periodic_diff(X, sp["pos"], n))) < 1e-5, (step, s)
+                ex, eu = np.max(np.abs(periodic_diff(X, sp["pos"], n))), rel_inf(g["u"].astype(np.float64), sp["u"])
+                _say("[err] direct current", ci, step, s, f"x {ex:.3g} u {eu:.3g}")
+                assert ex < 1e-6, (step, s)
+                assert eu < 1e-5, (step, s)
             else:
                 assert np.max(np.abs(periodic_diff(g["pos"], sp["pos"], n))) < 1e-12, (step, s)
     d = run.diagnostics(ppm.PP_DIAG_RHO)
@@ -280,8 +286,48 @@ def test_direct_current_and_gauss_filter_match_oracle(ppm, orc, ci):
     run.close()
 
 
+@pytest.mark.parametrize("split", [False, True], ids=["fp64", "fp32_split"])
+def test_periodic_gauss_filter_matches_oracle(ppm, orc, split):
+    # the filter only after every third step (the paper's single-precision practice is about
+    # every fifth): five steps of the direct current against the oracle with the same cadence
+    n, O, fo, passes, every = (10, 8, 6), 3, 6, 3, 3
+    _say("periodic gauss filter", "split" if split else "fp64")
+    species, E, B = random_state(orc, n, 3, seed=331, uth=0.3, nspecies=3, pair=False)
+    kw = dict(n=n, dt=0.4, shape_order=O, field_order=fo, relax_tol=1e-14, relax_max_iter=200)
+    P = orc.make_params(**kw)
+    if split:
+        species = _split_species(species, n, O)
+        ref_species = [dict(s, u=s["u64"]) for s in species]
+    else:
+        ref_species = species
+    ref = _orc_run(orc, orc.make_params(current_scheme=1, gauss_passes=passes, gauss_every=every, **kw), ref_species,
+                   E, B)
+    prec = ppm.PP_PREC_FP32_SPLIT if split else ppm.PP_PREC_FP64
+    run = ppm.Run(ppm.make_params(precision=prec, current_scheme=ppm.PP_CURRENT_DIRECT, gauss_filter_passes=passes,
+                                  gauss_filter_every=every, **kw), species, E=E, B=B)
+    unfiltered = _orc_run(orc, orc.make_params(current_scheme=1, **kw), ref_species, E, B)
+    gauss, gauss0 = [], []
+    for step in range(5):
+        ref.step()
+        unfiltered.step()
+        run.step()
+        Eg, Bg, _ = run.fields()
+        if split:
+            assert rel_l2(Eg - E, ref.E - E) < 1e-5 and rel_l2(Bg - B, ref.B - B) < 1e-5, step
+        else:
+            assert rel_inf(Eg, ref.E) < 1e-12 and rel_inf(Bg, ref.B) < 1e-12, step
+        gauss.append(np.max(np.abs(orc.div_down(P, ref.E) - ref.rho())))
+        gauss0.append(np.max(np.abs(orc.div_down(P, unfiltered.E) - unfiltered.rho())))
+    # steps 1-2 unfiltered (the same fields as without the filter), step 3 filtered
+    assert gauss[0] == gauss0[0] and gauss[1] == gauss0[1]
+    assert gauss[2] < gauss[1] and gauss[2] < 0.8 * gauss0[2]
+    assert run.diagnostics(ppm.PP_DIAG_MOMENTS).flags == 0
+    run.close()
+
+
 def test_scheme_and_filter_parameters_are_validated(ppm):
-    for kw in (dict(current_scheme=2), dict(gauss_filter_passes=-1), dict(gauss_filter_passes=65)):
+    for kw in (dict(current_scheme=2), dict(gauss_filter_passes=-1), dict(gauss_filter_passes=65),
+               dict(gauss_filter_every=-1), dict(gauss_filter_every=2, time_order=4, dt=0.3)):
         with pytest.raises(ppm.PPError):
             ppm.Run(ppm.make_params(n=(4, 4, 4), **kw), [])
 
@@ -307,6 +353,8 @@ def test_fourth_order_steps_match_oracle(ppm, orc, split):
         run.step()
         Eg, Bg, Jg = run.fields()
         if split:
+            _say("[err] fourth order J", step, f"{rel_l2(Jg, ref.J):.3g}")
+            assert rel_l2(Jg, ref.J) < 1e-5, step
             assert rel_l2(Eg - E, ref.E - E) < 1e-5 and rel_l2(Bg - B, ref.B - B) < 1e-5, step
         else:
             assert rel_inf(Jg, ref.J) < 1e-12, step
@@ -315,8 +363,10 @@ def test_fourth_order_steps_match_oracle(ppm, orc, split):
             g = _by_id(run.particles(s))
             if split:
                 X = I.from_split(g["cell"], g["pos"], n)
-                assert np.max(np.abs(periodic_diff(X, sp["pos"], n))) < 1e-5, (step, s)
-                assert rel_inf(g["u"].astype(np.float64), sp["u"]) < 2e-5, (step, s)
+                ex, eu = np.max(np.abs(periodic_diff(X, sp["pos"], n))), rel_inf(g["u"].astype(np.float64), sp["u"])
+                _say("[err] fourth order", step, s, f"x {ex:.3g} u {eu:.3g}")
+                assert ex < 1e-6, (step, s)
+                assert eu < 1e-5, (step, s)
             else:
                 assert np.max(np.abs(periodic_diff(g["pos"], sp["pos"], n))) < 1e-12, (step, s)
                 assert rel_inf(g["u"], sp["u"]) < 1e-12, (step, s)

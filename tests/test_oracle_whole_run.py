@@ -222,3 +222,24 @@ def test_direct_current_breaks_gauss_and_the_filter_restores_it(orc):
     assert res["direct"] > 1e-3
     assert res["filtered"] < 0.05 * res["direct"]
     assert res["cc"] < 1e-12
+
+
+def test_gauss_filter_cadence(orc):
+    # the filter after every third step only: the Gauss error after a filtered step is the one
+    # of filtering every step from the same state, and between filtered steps it grows back
+    from paper_1211_4575_amd import inputs as I
+    wl = I.plain_heating(n=(8, 8, 8), ppc=8)
+    sp = [dict(q=s.q, m=s.m, w=s.w, pos=s.pos, u=s.u) for s in wl.species]
+    P3 = orc.make_params(**{**wl.params(), "current_scheme": 1, "gauss_passes": 5, "gauss_every": 3})
+    P1 = orc.make_params(**{**wl.params(), "current_scheme": 1, "gauss_passes": 5})
+    r3, r1 = orc.Run(P3, sp), orc.Run(P1, sp)
+    err = []
+    for step in range(6):
+        r3.step()
+        r1.step()
+        err.append(np.max(np.abs(orc.div_down(P3, r3.E) - r3.rho())))
+        if step == 2:  # the first filtered step of the cadence: the state differs from r1 only
+            # by the unfiltered steps 1 and 2, so its error is of the same order as r1's
+            e1 = np.max(np.abs(orc.div_down(P1, r1.E) - r1.rho()))
+            assert err[2] < 3 * e1
+    assert err[1] > err[0] and err[2] < 0.5 * err[1] and err[3] > err[2] and err[5] < 0.5 * err[4]
