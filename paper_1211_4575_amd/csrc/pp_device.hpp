@@ -50,12 +50,14 @@ __device__ __forceinline__ void weights_frac<3, double>(double t, double* w) {
 }
 template <>
 __device__ __forceinline__ void weights_frac<3, float>(float t, float* w) {
-    float s = 1.0f - t;
+    // the same polynomials with the powers shared: (4 - 6t^2 + 3t^3)/6 = 2/3 + t^2 (t/2 - 1)
+    const float s = 1.0f - t;
+    const float t2 = t * t, s2 = s * s;
     const float k6 = 1.0f / 6.0f;
-    w[0] = k6 * s * s * s;
-    w[1] = k6 * (4.0f - 6.0f * t * t + 3.0f * t * t * t);
-    w[2] = k6 * (4.0f - 6.0f * s * s + 3.0f * s * s * s);
-    w[3] = k6 * t * t * t;
+    w[0] = (k6 * s) * s2;
+    w[1] = fmaf(t2, fmaf(0.5f, t, -1.0f), 2.0f / 3.0f);
+    w[2] = fmaf(s2, fmaf(0.5f, s, -1.0f), 2.0f / 3.0f);
+    w[3] = (k6 * t) * t2;
 }
 
 // First node and weights for an absolute coordinate y (FP64 form).

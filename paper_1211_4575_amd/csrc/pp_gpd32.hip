@@ -225,19 +225,25 @@ __device__ __forceinline__ int centred_weights(float x, float* w) {
     }
 }
 
+typedef __attribute__((address_space(3))) const float lds_cfloat;
+
 template <int O, class TL>
 __device__ __forceinline__ float gather_comp(const float* __restrict__ F, const TL& L, int bx, int by, int bz,
                                              const float* wx, const float* wy, const float* wz) {
+    lds_cfloat* base = (lds_cfloat*)(F + bz * L.fsz + by * L.fsy + bx * L.fsx);
     float acc = 0.f;
 #pragma unroll
     for (int c = 0; c <= O; ++c) {
+        // one address per plane, kept opaque: the plane's nodes are then small immediate
+        // offsets of it (LDS paired reads reach 255 words; the stencil spans more than that)
+        lds_cfloat* plane = base + c * L.fsz;
+        asm volatile("" : "+v"(plane));
         float accy = 0.f;
 #pragma unroll
         for (int b = 0; b <= O; ++b) {
-            const float* row = F + (bz + c) * L.fsz + (by + b) * L.fsy + bx * L.fsx;
             float s = 0.f;
 #pragma unroll
-            for (int a = 0; a <= O; ++a) s += row[a * L.fsx] * wx[a];
+            for (int a = 0; a <= O; ++a) s += plane[b * L.fsy + a * L.fsx] * wx[a];
             accy += s * wy[b];
         }
         acc += accy * wz[c];
