@@ -96,25 +96,42 @@ def host_cpu():
     return model, len(os.sched_getaffinity(0))
 
 
-def time_oracle(wl, steps, openmp):
+def time_oracle(wl, steps, openmp, progress=None):
     """Seconds for `steps` whole oracle steps of workload `wl` (plain scalar build, or the
-    OpenMP build with one current buffer per thread) and the threads used."""
+    OpenMP build with one current buffer per thread) and the threads used.  With `progress`,
+    the step is taken species by species as the oracle's own step does (particles of every
+    species, high-order current, field step; leapfrog order only) and progress(text) is
+    called after each species."""
     from oracle import orc
     orc.build()
     P = orc.make_params(**wl.params())
     run = orc.Run(P, [dict(q=s.q, m=s.m, w=s.w, pos=s.pos, u=s.u) for s in wl.species])
+
+    def one_step(k):
+        if progress is None or P.time_order == 4:
+            run.step()
+            return
+        run.J[:] = 0.0
+        for i, s in enumerate(run.species):
+            run.flags |= orc.step_species_kd(P, P.dt, s["q"], s["m"], s["w"], s["pos"], s["u"], run.E, run.B, run.J)
+            progress(f"step {k + 1}/{steps}, species {i + 1}/{len(run.species)}")
+        if P.current_scheme == 0:
+            orc.current_high_order(P, run.J)
+        run.fields_step()
+        run.nstep += 1
+
     if openmp:
         with orc.openmp():
             threads = orc.num_threads()
             t0 = time.perf_counter()
-            for _ in range(steps):
-                run.step()
+            for k in range(steps):
+                one_step(k)
             dt = time.perf_counter() - t0
     else:
         threads = 1
         t0 = time.perf_counter()
-        for _ in range(steps):
-            run.step()
+        for k in range(steps):
+            one_step(k)
         dt = time.perf_counter() - t0
     return dt, threads
 
@@ -150,12 +167,14 @@ def cpu_plan():
     os.environ.setdefault("OMP_NUM_THREADS", str(cores))
     out = {"cpu_model": model, "nproc": cores, "runs": []}
     plans = [("plain heating 16^3, TSC, 2nd order, 100 steps", I.plain_heating(), 100, 100),
-             ("pair plasma 64^3, 32 ppc/species, cubic, 6th order, 20 steps (one core: 2 steps)",
-              I.pair_maxwell_juttner(n=(64, 64, 64), ppc=32, theta=1.0), 2, 20)]
+             ("pair plasma 64^3, 32 ppc/species, cubic, 6th order, 20 steps (one core: 1 step)",
+              I.pair_maxwell_juttner(n=(64, 64, 64), ppc=32, theta=1.0), 1, 20)]
     for name, wl, s1, sn in plans:
-        t1, _ = time_oracle(wl, s1, openmp=False)
+        def progress(text, name=name):
+            log(f"[cpu-plan] {name}: {text}")
+        t1, _ = time_oracle(wl, s1, openmp=False, progress=progress)
         log(f"[cpu-plan] {name}: one core {wl.n_particles * s1 / t1:.3e} updates/s ({t1:.1f} s)")
-        tn, threads = time_oracle(wl, sn, openmp=True)
+        tn, threads = time_oracle(wl, sn, openmp=True, progress=progress)
         log(f"[cpu-plan] {name}: {threads} threads {wl.n_particles * sn / tn:.3e} updates/s ({tn:.1f} s)")
         out["runs"].append(dict(workload=name, particles=wl.n_particles, one_core=dict(steps=s1, s=t1,
                                 updates_per_s=wl.n_particles * s1 / t1),
@@ -600,31 +619,35 @@ def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress
     return t, hist.cpu().numpy(), wall, 4 * npart, d, (np.array(bin_t), kv, torch.stack(bins).cpu().numpy())
 
 
-def mode_rates(tb, kv, W, dk, width, top=12):
-    """Growth rates mode by mode: for every Fourier bin (indices kz, ky, kx from kv, energies W
-    [samples, z, y, x]) the steepest least-squares half log slope over windows of the given
-    width, after the bin's energy first exceeds 3x its mean over t <= 2.  Returns the ``top``
-    fastest bins (one of each +-k pair) with wave vector, |k|, angle to the beam and rate."""
+def mode_rates(tb, kv, W, dk, t_end, top=12, min_samples=12):
+    """Linear growth rates mode by mode.  For every Fourier bin (indices kz, ky, kx from kv,
+    energies W [samples, z, y, x] at times tb) the least-squares half log slope of its energy
+    over the samples up to t_end (the end of the linear phase) that lie above 30x the bin's
+    mean over 1 <= t <= 8 (its noise floor) and below a tenth of its largest value up to
+    t_end; bins with fewer than min_samples such samples are left out.  Returns the ``top``
+    fastest (one of each +-k pair) with wave vector, |k|, angle to the beam and rate."""
     import numpy as np
-    ns = len(tb)
-    L = np.log(np.maximum(W.reshape(ns, -1).astype(np.float64), 1e-300))
-    w = max(3, int(round(width / (tb[1] - tb[0]))) + 1)
-    tt = np.asarray(tb, dtype=float)
-    # least-squares slopes of every window of w samples, all bins at once
-    ts = np.lib.stride_tricks.sliding_window_view(tt, w)
-    tm = ts - ts.mean(axis=1, keepdims=True)
-    den = (tm * tm).sum(axis=1)
-    Ls = np.lib.stride_tricks.sliding_window_view(L, w, axis=0)  # [win, bins, w]
-    slope = np.einsum("wbk,wk->wb", Ls, tm) / den[:, None]
-    early = L[tt <= 2.0].mean(axis=0)
-    started = np.maximum.accumulate(L[:len(ts)] > early + np.log(3.0), axis=0)
-    rate = np.where(started, 0.5 * slope, -np.inf).max(axis=0)
+    tb = np.asarray(tb, dtype=float)
+    L = np.log(np.maximum(W.reshape(len(tb), -1).astype(np.float64), 1e-300))
+    floor = L[(tb >= 1.0) & (tb <= 8.0)].mean(axis=0)
+    lin = tb <= t_end
+    Lmax = np.where(lin[:, None], L, -np.inf).max(axis=0)
+    m = lin[:, None] & (L > floor + math.log(30.0)) & (L < Lmax - math.log(10.0))
+    n = m.sum(axis=0).astype(float)
+    T = tb[:, None]
+    St, SL = (m * T).sum(axis=0), (m * L).sum(axis=0)
+    Stt, StL = (m * T * T).sum(axis=0), (m * T * L).sum(axis=0)
+    den = n * Stt - St * St
+    ok = (n >= min_samples) & (den > 0)
+    rate = np.where(ok, 0.5 * (n * StL - St * SL) / np.where(ok, den, 1.0), -np.inf)
     KZ, KY, KX = np.meshgrid(kv, kv, kv, indexing="ij")
     KZ, KY, KX = KZ.ravel() * dk, KY.ravel() * dk, KX.ravel() * dk
     kk = np.sqrt(KX * KX + KY * KY + KZ * KZ)
     out, seen = [], set()
     for b in np.argsort(-rate):
-        if kk[b] == 0 or not np.isfinite(rate[b]):
+        if not np.isfinite(rate[b]):
+            break
+        if kk[b] == 0:
             continue
         key = tuple(np.round([KZ[b] / dk, KY[b] / dk, KX[b] / dk]).astype(int))
         if tuple(-v for v in key) in seen:
@@ -632,7 +655,7 @@ def mode_rates(tb, kv, W, dk, width, top=12):
         seen.add(key)
         ang = math.degrees(math.atan2(math.hypot(KX[b], KY[b]), abs(KZ[b])))
         out.append({"k": [float(KX[b]), float(KY[b]), float(KZ[b])], "abs_k": float(kk[b]), "angle_deg": ang,
-                    "rate": float(rate[b])})
+                    "rate": float(rate[b]), "samples": int(n[b])})
         if len(out) == top:
             break
     return out
@@ -702,7 +725,9 @@ def mmi_bench(args, torch, pp):
         log(f"[mmi] {k}: {v}")
     g = args.mmi_grid
     fits["gamma_tsi_theta0"] = fits["tsi_all_kz"]["rate"]  # the projection at theta_TSI = 0: E_z
-    modes = mode_rates(tb, kv, W, 2 * math.pi / 12.8, args.mmi_fit_width)
+    # the linear phase ends when the projected energy reaches 5 % of its largest value
+    t_end = float(t[int(np.argmax(H[:, 0] > 0.05 * np.max(H[:, 0])))])
+    modes = mode_rates(tb, kv, W, 2 * math.pi / 12.8, t_end)
     for m in modes:
         log(f"[mmi] mode k=({m['k'][0]:+.2f},{m['k'][1]:+.2f},{m['k'][2]:+.2f}) |k|={m['abs_k']:.2f} "
             f"angle {m['angle_deg']:.0f} deg: rate {m['rate']:.4f}")
@@ -711,7 +736,8 @@ def mmi_bench(args, torch, pp):
            "config": {"grid": [g, g, g], "ppc_per_species": args.mmi_ppc, "particles": npart, "dx": 12.8 / g,
                       "dt": 0.4 * 12.8 / g, "steps": args.mmi_steps, "T_b": args.mmi_tb, "T_p": args.mmi_tp},
            "updates_per_s": npart * args.mmi_steps / wall, "wall_s": wall,
-           "final_gauss_rel": d.gauss_max / d.rho_ref, "flags": d.flags, "fastest_modes": modes, **fits}
+           "final_gauss_rel": d.gauss_max / d.rho_ref, "flags": d.flags, "linear_phase_end": t_end,
+           "fastest_modes": modes, **fits}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -116,22 +116,26 @@ def test_measured_traffic_is_used_only_for_the_kernel_sources_it_was_taken_on(mo
 
 
 def test_mode_rates_finds_the_growing_bins():
-    # three bins grow at 0.2, 0.15 and 0.05 from t = 5 on above a flat floor, the others stay
-    # at the floor; a +-k pair appears once, the steepest 6-unit window gives the rates
+    # three bins grow at 0.2, 0.15 and 0.1 from t = 10 on over a flat floor and stop at 50
+    # (saturation); the others stay at the floor; a +-k pair appears once; the linear phase
+    # ends at t = 55
     import math
 
     import numpy as np
-    tb = np.arange(0, 40.01, 0.5)
+    tb = np.arange(0, 70.01, 0.5)
     kv = np.array([0, 1, 2, -2, -1])
     W = np.full((len(tb), 5, 5, 5), 1e-6)
-    grow = np.exp(2 * np.maximum(tb - 5.0, 0.0))
+    grow = np.exp(2 * np.clip(tb - 10.0, 0.0, 40.0))
     W[:, 1, 2, 0] *= grow ** 0.2  # kz = 1, ky = 2, kx = 0
     W[:, 4, 3, 0] *= grow ** 0.2  # its mirror -k
     W[:, 2, 0, 1] *= grow ** 0.15
-    W[:, 0, 1, 1] *= grow ** 0.05
+    W[:, 0, 1, 1] *= grow ** 0.1
     dk = 2 * math.pi / 12.8
-    m = bench.mode_rates(tb, kv, W, dk, 6.0, top=3)
-    assert [round(x["rate"], 6) for x in m] == [0.2, 0.15, 0.05]
+    m = bench.mode_rates(tb, kv, W, dk, 55.0, top=5)
+    assert len(m) == 3  # the floor bins never leave their noise
+    assert [round(x["rate"], 9) for x in m] == [0.2, 0.15, 0.1]
     assert np.allclose(m[0]["k"], [0.0, 2 * dk, dk]) or np.allclose(m[0]["k"], [0.0, -2 * dk, -dk])
     assert abs(m[0]["angle_deg"] - math.degrees(math.atan2(2, 1))) < 1e-9
     assert abs(m[2]["abs_k"] - math.sqrt(2) * dk) < 1e-12
+    # a linear phase ending before the bins leave their floor leaves nothing to fit
+    assert bench.mode_rates(tb, kv, W, dk, 12.0) == []

@@ -8,6 +8,7 @@ fundamental wave vector of a thin 3D box (cubic weights, 6th-order fields, the i
 step at alpha = 0.55), must grow at the rate of that theory for finite-size particles within
 3 %."""
 import math
+import sys
 import os
 
 import numpy as np
@@ -70,5 +71,6 @@ def test_oblique_mode_grows_at_the_linear_rate_oracle(orc):
             hist.append(sum(orc.field_energy(P, run.E, run.B)[:2]))
     t = P.dt * np.arange(len(hist))
     got = T.energy_rate(t, hist)
+    print("oblique mode, oracle: rate", got, "theory", rate, "fluid", fluid, file=sys.stderr, flush=True)
     assert abs(got - rate) < 0.03 * rate, (got, rate, fluid)
     assert run.flags == 0
