@@ -533,7 +533,15 @@ def two_stream_bench(args, torch, pp):
     return 0
 
 
-def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress=250, kmax_index=16):
+# The six schemes of the paper's mixed-mode comparison (its table of orders): field order,
+# weight order (TSC = quadratic), charge-conserving current, time order.  The runs without
+# charge conservation use the direct current with the Gauss-law filter of the original code,
+# five passes per step (the paper runs it 5 to 10 times).
+MMI_SCHEMES = {1: (2, 2, False, 2), 2: (2, 3, False, 2), 3: (6, 2, False, 2), 4: (6, 3, False, 2),
+               5: (6, 3, True, 2), 6: (6, 3, True, 4)}
+
+
+def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress=250, kmax_index=16, scheme=5):
     """Mixed-mode two-stream run on g^3 cells of a cubic box of ``box`` skin depths, generated
     on the device (FP32 split form).  Returns (times, energies [steps + 1, 4], wall s,
     particles, final diagnostics, (sample times, wave-number indices, bin energies)): per step
@@ -550,6 +558,7 @@ def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress
     n, dx = (g, g, g), box / g
     dt = cfl * dx
     npart = n[0] * n[1] * n[2] * ppc
+    fo, O, cc, torder = MMI_SCHEMES[scheme]
     dev = torch.device("cuda:0")
     cells = [torch.empty(npart, dtype=torch.int32, device=dev) for _ in range(4)]
     offs = [torch.empty((3, npart), dtype=torch.float32, device=dev) for _ in range(4)]
@@ -558,14 +567,16 @@ def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress
     chunk = 1 << 25
     for start in range(0, npart, chunk):
         cnt = min(chunk, npart - start)
-        ind.mmi(SEED, n, start, cnt, 4.0, T_b, T_p, 1836.0, ind.split_mode(True, 3), [c[start:] for c in cells],
+        ind.mmi(SEED, n, start, cnt, 4.0, T_b, T_p, 1836.0, ind.split_mode(True, O), [c[start:] for c in cells],
                 [[o[d, start:] for d in range(3)] for o in offs], [[u[d, start:] for d in range(3)] for u in us], st)
     species = []
     for s, (nm, q, ion, beam) in enumerate(I.MMI_SPECIES):
         species.append(dict(q=q, m=1836.0 if ion else 1.0, w=(0.1 if beam else 0.9) / ppc, u=us[s], cell=cells[s],
                             off=offs[s]))
-    P = pp.make_params(n, d=(dx, dx, dx), dt=dt, shape_order=3, field_order=6, alpha=0.55,
-                       precision=pp.PP_PREC_FP32_SPLIT, relax_tol=1e-8, relax_max_iter=100)
+    P = pp.make_params(n, d=(dx, dx, dx), dt=dt, shape_order=O, field_order=fo, alpha=0.55,
+                       precision=pp.PP_PREC_FP32_SPLIT, relax_tol=1e-8, relax_max_iter=100,
+                       current_scheme=pp.PP_CURRENT_CC if cc else pp.PP_CURRENT_DIRECT,
+                       gauss_filter_passes=0 if cc else 5, time_order=torder)
     run = pp.Run(P, species, with_id=False)
     del cells, offs, us
     th = math.radians(74.0)
@@ -715,7 +726,7 @@ def mmi_bench(args, torch, pp):
     from paper_1211_4575_amd import inputs as I
     from paper_1211_4575_amd import inputs_device as ind
     t, H, wall, npart, d, (tb, kv, W) = run_mmi(torch, pp, ind, args.mmi_grid, args.mmi_ppc, args.mmi_steps,
-                                                args.mmi_tb, args.mmi_tp)
+                                                args.mmi_tb, args.mmi_tp, scheme=args.mmi_run)
     if args.save_history:
         np.savez(f"{args.save_history}_mmi.npz", t=t, w=H, tb=tb, kv=kv, bins=W)
     theory = I.mmi_rates()
@@ -734,7 +745,10 @@ def mmi_bench(args, torch, pp):
     out = {"metric": "relativistic mixed-mode two-stream growth rates / theory and paper",
            "theory": theory, "paper_cubic_cc_6th": {"mmi": 0.205, "tsi": 0.088},
            "config": {"grid": [g, g, g], "ppc_per_species": args.mmi_ppc, "particles": npart, "dx": 12.8 / g,
-                      "dt": 0.4 * 12.8 / g, "steps": args.mmi_steps, "T_b": args.mmi_tb, "T_p": args.mmi_tp},
+                      "dt": 0.4 * 12.8 / g, "steps": args.mmi_steps, "T_b": args.mmi_tb, "T_p": args.mmi_tp,
+                      "run": args.mmi_run, "field_order": MMI_SCHEMES[args.mmi_run][0],
+                      "shape_order": MMI_SCHEMES[args.mmi_run][1], "charge_conserving": MMI_SCHEMES[args.mmi_run][2],
+                      "time_order": MMI_SCHEMES[args.mmi_run][3]},
            "updates_per_s": npart * args.mmi_steps / wall, "wall_s": wall,
            "final_gauss_rel": d.gauss_max / d.rho_ref, "flags": d.flags, "linear_phase_end": t_end,
            "fastest_modes": modes, **fits}
@@ -1001,6 +1015,9 @@ def main(argv=None):
     ap.add_argument("--mmi-ppc", type=int, default=20, help="mmi: particles per cell per species")
     ap.add_argument("--mmi-steps", type=int, default=1500, help="mmi: steps")
     ap.add_argument("--mmi-fit-width", type=float, default=6.0, help="mmi: fit window (1/w_pe)")
+    ap.add_argument("--mmi-run", type=int, choices=sorted(MMI_SCHEMES), default=5,
+                    help="mmi: scheme of the paper's comparison (1-4 direct current + filter, 5 charge-conserving, "
+                         "6 with fourth-order time integration)")
     ap.add_argument("--mmi-tb", type=float, default=1e-4,
                     help="mmi: beam temperature (m_e c^2); the default reads the paper's 0.01 as u_th")
     ap.add_argument("--mmi-tp", type=float, default=0.01,
@@ -1102,7 +1119,9 @@ def main(argv=None):
                                   current_scheme=scheme, gauss_passes=args.gauss_passes, time_order=args.time_order)
         log(f"[bench] FP64 plain: warmup 1, timing {args.fp64_steps} steps")
         wall64, gpd64_ms = time_steps(run, torch, args.fp64_steps, 1)
-        fp64 = dict(value=npart * args.fp64_steps / wall64, ms_per_step=1e3 * wall64 / args.fp64_steps,
+        fp64 = dict(form="plain FP64: untiled, one thread per particle, every current contribution a global "
+                         "FP64 atomic (the ratio measures the tiled split design, not the precision alone)",
+                    value=npart * args.fp64_steps / wall64, ms_per_step=1e3 * wall64 / args.fp64_steps,
                     gpd_updates_per_s=npart / (gpd64_ms * 1e-3), gpd_ms=gpd64_ms)
         # per-step charge conservation and Gauss residual of the FP64 form, outside the timed region
         run.diagnostics(pp.PP_DIAG_RHO)
