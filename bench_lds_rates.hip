@@ -431,6 +431,8 @@ int main() {
                 int row, plane, copies, copy_stride;
             };
             for (const Layout& L : {Layout{"deposit, rows 12, planes 128", true, 12, 128, 1, 0},
+                                    Layout{"deposit, rows 12, planes 144", true, 12, 144, 1, 0},
+                                    Layout{"deposit, rows 12, planes 136", true, 12, 136, 1, 0},
                                     Layout{"deposit, rows 8, planes 64", true, 8, 64, 1, 0},
                                     Layout{"deposit, rows 12, planes 128, 2 copies by round", true, 12, 128, 2, 1024},
                                     Layout{"deposit, rows 8, planes 64, 2 copies by round", true, 8, 64, 2, 512},
