@@ -241,7 +241,14 @@ def kernel_roofline(npart, gpd_ms, direct=False):
                              "frac": round(la / lds_peak, 4),
                              "atomics_per_64_particles": round(cs["lds_atomic_insts_per_launch"] * 64 / npart, 1),
                              "lds_insts_per_64_particles": round(cs.get("lds_insts_per_launch", float("nan")) * 64 / npart, 1)}
-    fr = {"hbm": out["frac"], "valu": out["valu"]["frac"], "lds_atomic": out.get("lds_atomic", {}).get("frac", 0.0)}
+    if "lds_active_per_launch" in cs and "gui_active_per_launch" in cs:
+        # fraction of the kernel's CU cycles in which the LDS pipe was busy (all LDS instructions,
+        # bank conflicts included), from the same counter runs
+        busy = cs["lds_active_per_launch"] / (cs["gui_active_per_launch"] / XCDS * CUS)
+        if out.get("lds_atomic"):
+            out["lds_atomic"]["lds_pipe_busy"] = round(busy, 4)
+    fr = {"hbm": out["frac"], "valu": out["valu"]["frac"],
+          "lds": (out.get("lds_atomic") or {}).get("lds_pipe_busy", (out.get("lds_atomic") or {}).get("frac", 0.0))}
     out["binding"] = max(fr, key=fr.get)
     out["counters"] = f"profiles/k_gpd32_pair_mj_256_counters.md, digest {cs.get('kernel_source_digest', '')}"
     return out

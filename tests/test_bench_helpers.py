@@ -56,7 +56,11 @@ def test_roofline_fractions_from_a_counter_summary(monkeypatch):
     assert abs(r["lds_atomic"]["frac"] - 3.0e9 / 0.1 / (256 * 2.4e9 / bench.LDS_CLK_PER_WAVE_ATOMIC)) < 1e-4
     assert r["valu"]["insts_per_64_particles"] == round(2.4e10 * 64 / n, 1)
     assert r["binding"] == max(("hbm", r["frac"]), ("valu", r["valu"]["frac"]),
-                               ("lds_atomic", r["lds_atomic"]["frac"]), key=lambda t: t[1])[0]
+                               ("lds", r["lds_atomic"]["frac"]), key=lambda t: t[1])[0]
+    # with the LDS-active counter the LDS pipe's busy fraction decides for the LDS
+    cs.update(lds_active_per_launch=0.9 * 8e8 / 8 * 256, gui_active_per_launch=8e8)
+    r = bench.kernel_roofline(n, ms)
+    assert abs(r["lds_atomic"]["lds_pipe_busy"] - 0.9) < 1e-9 and r["binding"] == "lds"
     # no summary for these sources: only the HBM figure
     r = bench.kernel_roofline(n + 1, ms)
     assert r["valu"] is None and r["lds_atomic"] is None and r["frac"] > 0
