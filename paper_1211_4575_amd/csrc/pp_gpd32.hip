@@ -137,10 +137,16 @@ struct TileCT {
     static constexpr int csx = 1, csy = crow, csz = CZ ? 0 : cplane;
     static_assert(frow >= fex && fplane >= frow * fey, "field tile padding");
     static constexpr int fvol = fplane * fez, cvol = cplane * cez;
+    // two particles per lane (the paired deposit) on cubic tiles; flat tiles keep one per
+    // lane, whose smaller register set leaves room for more resident wavefronts
+    static constexpr bool pairs = t444;
+    static constexpr bool flat = CZ;  // one field plane: the gather's z taps read the same nodes
     __device__ TileCT(const Gpd32Args&) {}
 };
 
 struct TileRT {
+    static constexpr bool pairs = false;
+    static constexpr bool flat = false;
     int tx, ty, tz;
     int flox, floy, floz, clox, cloy, cloz;
     int fex, fey, fez, cex, cey, cez;
@@ -235,9 +241,10 @@ __device__ __forceinline__ float gather_comp(const float* __restrict__ F, const 
 #pragma unroll
     for (int c = 0; c <= O; ++c) {
         // one address per plane, kept opaque: the plane's nodes are then small immediate
-        // offsets of it (LDS paired reads reach 255 words; the stencil spans more than that)
+        // offsets of it (LDS paired reads reach 255 words; the stencil spans more than that).
+        // A flat tile has one plane, whose reads the compiler shares between the z taps.
         lds_cfloat* plane = base + c * L.fsz;
-        asm volatile("" : "+v"(plane));
+        if constexpr (!TL::flat) asm volatile("" : "+v"(plane));
         float accy = 0.f;
 #pragma unroll
         for (int b = 0; b <= O; ++b) {
@@ -624,7 +631,8 @@ __device__ __forceinline__ void deposit_cc(const TL& L, unsigned long long* cur,
 // particles crossed a face the storage did not expect; such pairs deposit together with one
 // atomic per node for both.  Where some lane's pair does not share a window, that lane's
 // second particle deposits alone in a second pass; where no lane's does (the partial rounds,
-// whose lanes change cells), each particle deposits alone.
+// whose lanes change cells), each particle deposits alone.  Flat (8x8x1) and runtime-shaped
+// tiles take one particle per lane and slot (64 consecutive slots per wavefront).
 template <int O, class TL>
 __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, unsigned char* lds_raw) {
     const TL L(A);
@@ -676,29 +684,37 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
         const int32_t end = S.start[tile + 1];
         for (int d = 0; d < 3; ++d) C.facq[d] = S.fac[d] * qs;
         C.qwq = S.qw * qs;
-        for (int32_t b = start + 128 * wave; b < end; b += 4 * 128) {
-            Win<O> W1, W2;
-            const int32_t q1 = b + lane, q2 = b + 64 + lane;
-            W1.dep = W2.dep = false;
-            if (q1 < end) step_particle<O, TL>(A, S, L, C, q1, W1, bad_all);
-            if (q2 < end) step_particle<O, TL>(A, S, L, C, q2, W2, bad_all);
-            const bool both = W1.dep && W2.dep;
-            const bool same = both && window_start<O, TL>(L, W1, 0) == window_start<O, TL>(L, W2, 0) &&
-                              window_start<O, TL>(L, W1, 1) == window_start<O, TL>(L, W2, 1) &&
-                              window_start<O, TL>(L, W1, 2) == window_start<O, TL>(L, W2, 2);
-            if (__any(same)) {
-                // the first particle of every lane (or its second, if only that one deposits),
-                // together with the second where the windows coincide
-                if (!W1.dep && W2.dep) {
-                    W1 = W2;
-                    W2.dep = false;
+        if constexpr (!TL::pairs) {
+            for (int32_t q = start + threadIdx.x; q < end; q += GPD32_BS) {
+                Win<O> W;
+                step_particle<O, TL>(A, S, L, C, q, W, bad_all);
+                if (W.dep) deposit_cc<O, TL, false>(L, cur, W, C.facq, W, C.facq, 0.0f);
+            }
+        } else {
+            for (int32_t b = start + 128 * wave; b < end; b += 4 * 128) {
+                Win<O> W1, W2;
+                const int32_t q1 = b + lane, q2 = b + 64 + lane;
+                W1.dep = W2.dep = false;
+                if (q1 < end) step_particle<O, TL>(A, S, L, C, q1, W1, bad_all);
+                if (q2 < end) step_particle<O, TL>(A, S, L, C, q2, W2, bad_all);
+                const bool both = W1.dep && W2.dep;
+                const bool same = both && window_start<O, TL>(L, W1, 0) == window_start<O, TL>(L, W2, 0) &&
+                                  window_start<O, TL>(L, W1, 1) == window_start<O, TL>(L, W2, 1) &&
+                                  window_start<O, TL>(L, W1, 2) == window_start<O, TL>(L, W2, 2);
+                if (__any(same)) {
+                    // the first particle of every lane (or its second, if only that one deposits),
+                    // together with the second where the windows coincide
+                    if (!W1.dep && W2.dep) {
+                        W1 = W2;
+                        W2.dep = false;
+                    }
+                    if (W1.dep)
+                        deposit_cc<O, TL, true>(L, cur, W1, C.facq, W2, C.facq, same ? 1.0f : 0.0f);
+                    if (both && !same) deposit_cc<O, TL, false>(L, cur, W2, C.facq, W2, C.facq, 0.0f);
+                } else {
+                    if (W1.dep) deposit_cc<O, TL, false>(L, cur, W1, C.facq, W1, C.facq, 0.0f);
+                    if (W2.dep) deposit_cc<O, TL, false>(L, cur, W2, C.facq, W2, C.facq, 0.0f);
                 }
-                if (W1.dep)
-                    deposit_cc<O, TL, true>(L, cur, W1, C.facq, W2, C.facq, same ? 1.0f : 0.0f);
-                if (both && !same) deposit_cc<O, TL, false>(L, cur, W2, C.facq, W2, C.facq, 0.0f);
-            } else {
-                if (W1.dep) deposit_cc<O, TL, false>(L, cur, W1, C.facq, W1, C.facq, 0.0f);
-                if (W2.dep) deposit_cc<O, TL, false>(L, cur, W2, C.facq, W2, C.facq, 0.0f);
             }
         }
         // reserve the tile's range in each destination cell's count, then complete the ranks
@@ -743,7 +759,7 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
 }
 
 template <int O, class TL>
-__global__ void __launch_bounds__(GPD32_BS, 3) k_gpd32(Gpd32Args A) {
+__global__ void __launch_bounds__(GPD32_BS, TL::pairs ? 3 : 1) k_gpd32(Gpd32Args A) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     // XCD-aware tile order: consecutive workgroups go round-robin over the 8 XCDs, so give
     // each XCD a contiguous run of tiles (neighbouring tiles share halos in that XCD's L2).
@@ -755,7 +771,7 @@ __global__ void __launch_bounds__(GPD32_BS, 3) k_gpd32(Gpd32Args A) {
 
 // Batched: block b of the launch is tile b - prefix[r] of run r (prefix = running tile counts).
 template <int O, class TL>
-__global__ void __launch_bounds__(GPD32_BS, 3) k_gpd32_batch(const Gpd32Args* __restrict__ table,
+__global__ void __launch_bounds__(GPD32_BS, TL::pairs ? 3 : 1) k_gpd32_batch(const Gpd32Args* __restrict__ table,
                                                           const int64_t* __restrict__ prefix, int nruns) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int64_t b = blockIdx.x;
