@@ -7,9 +7,10 @@
 // composed step), would take it across the lower face of its cell is kept in the cell
 // below with its offset in [lo + 1, lo + 2).  Then the current window of the next step
 // (old and new support) starts 2 nodes below the cell for almost every particle.
-// Particles are stored per tile in round-major order (see pp_sort.hip): 64 consecutive
-// particles sit in 64 different cells of the tile, so the 64 lanes of a wavefront touch 64
-// aligned stencils, which the padded LDS layout spreads over all banks.
+// Particles are stored per tile in pairs of ranks, 64 pairs to a chunk of 128 slots (see
+// pp_sort.hip): the 64 first and the 64 second particles of a chunk each sit in different
+// cells of the tile, in a full round all 64 cells in order, so the 64 lanes of a wavefront
+// touch 64 aligned stencils, which the padded LDS layout spreads over all banks.
 //
 // One workgroup (4 wavefronts) per tile of 64 cells:
 //   1. stage E and B of the tile plus a 2-node halo from the FP64 mesh into LDS as FP32;
@@ -626,13 +627,13 @@ __device__ __forceinline__ void deposit_cc(const TL& L, unsigned long long* cur,
 // One tile of one run: the whole particle step of the tile's particles (the body shared by
 // the single-run kernel and the batched kernel, so both do identical arithmetic).
 // Each wavefront takes 128 consecutive slots at a time, lane l the slots l and 64 + l.  In
-// the full rounds of the round-major order (every cell of the tile present) both are a
-// particle of the same cell, whose current windows start at the same node unless one of the
-// particles crossed a face the storage did not expect; such pairs deposit together with one
-// atomic per node for both.  Where some lane's pair does not share a window, that lane's
-// second particle deposits alone in a second pass; where no lane's does (the partial rounds,
-// whose lanes change cells), each particle deposits alone.  Flat (8x8x1) and runtime-shaped
-// tiles take one particle per lane and slot (64 consecutive slots per wavefront).
+// the chunks of pairs of the tile order both are a particle of the same cell, whose current
+// windows start at the same node unless one of the particles crossed a face the storage did
+// not expect; such pairs deposit together with one atomic per node for both.  Where some
+// lane's pair does not share a window, that lane's second particle deposits alone in a second
+// pass; where no lane's does (the single particles after the chunks), each particle deposits
+// alone.  Flat (8x8x1) and runtime-shaped tiles take one particle per lane and slot (64
+// consecutive slots per wavefront).
 template <int O, class TL>
 __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, unsigned char* lds_raw) {
     const TL L(A);

@@ -39,7 +39,7 @@ struct Species {
     pp_particles cur{};  // buffers read by the next push
     bool sorted = false;
     // FP64 form: nbins + 1 cell-bin starts.  Split form: ntiles + 1 tile starts of the
-    // round-major order (valid when sorted).
+    // tile order of pp_sort.hip (valid when sorted).
     int32_t* offsets = nullptr;
     // split form, filled by the particle kernel for the next sort: particles per cell of the
     // new positions (ncell, zero between steps), each particle's rank among the particles of
@@ -55,14 +55,17 @@ struct Species {
     bool pending = false;
 };
 
-// Round table of a tile (split-form sort): in round r, the cells holding more than r
-// particles (bit lc of mask), and the number of particles placed in rounds before r.
+// Round table of a tile (split-form sort), entry r for the particles of rank r in their cell
+// (see pp_sort.hip for the order it encodes): pmask, the cells holding a pair of ranks
+// 2R, 2R + 1 (R = r / 2), and pbefore, the pairs of rounds before R; smask, the cells whose
+// rank-r particle is laid out singly, and sbefore, the single particles of ranks before r.
 struct RoundEntry {
-    uint64_t mask;
-    int32_t before;
-    int32_t pad;
+    uint64_t pmask;
+    uint64_t smask;
+    int32_t pbefore;
+    int32_t sbefore;
 };
-constexpr int SORT_RCAP = 96;  // rounds per tile table; ranks beyond go to an overflow tail
+constexpr int SORT_RCAP = 96;  // ranks per tile table (even); ranks beyond go to an overflow tail
 
 // Line-solve stencil of one axis: out[i] = sum_j coef[j] * in[(i + off + j) mod n].
 struct LineStencil {
@@ -90,7 +93,7 @@ struct pp_run {
     int32_t* sort_cursor = nullptr;   // nbins: scatter cursors (cell bins or tiles)
     pp::RoundEntry* rounds = nullptr; // split form: ntiles * SORT_RCAP round tables
     int32_t* scan_tmp = nullptr;      // block sums of the scan
-    int32_t* sort_scratch = nullptr;  // split form: rank and permutation of the round-major rebuild
+    int32_t* sort_scratch = nullptr;  // split form: rank and permutation of the tile-order rebuild
     int64_t sort_scratch_n = 0;       // particles per half of sort_scratch
     long long* Jq = nullptr;          // split form: current in 64-bit fixed point (3*ncell)
     int32_t* tile_max = nullptr;      // split form: largest particle count of a tile, per species
@@ -169,9 +172,10 @@ hipError_t launch_gpd32(pp_run* r, double* J);
 hipError_t launch_line_solve(pp_run* r, const double* J2, double* J);
 hipError_t launch_field_step(pp_run* r);
 int64_t field_blocks(const pp_run* r);  // blocks of one field launch of this run
-// Sort species s: FP64 form, counting sort by cell; split form, round-major order per tile,
-// from the particle kernel's counts and ranks when it has run since the last sort, otherwise
-// (first sort, arbitrary order) by bucketing and a per-tile rebuild.
+// Sort species s: FP64 form, counting sort by cell; split form, the tile order (pairs of
+// ranks in chunks of 64) per tile, from the particle kernel's counts and ranks when it has
+// run since the last sort, otherwise (first sort, arbitrary order) by bucketing and a
+// per-tile rebuild.
 hipError_t launch_sort(pp_run* r, int s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 void sort_enqueued(pp_run* r, int s);  // host bookkeeping after a ranked sort was enqueued

@@ -4,10 +4,15 @@
 // FP64 form: counting sort by tile-major cell key (histogram -> exclusive scan -> scatter
 // with atomic cursors; order inside a cell unspecified).
 //
-// Split form: particles are laid out tile by tile (64 cells) in "round-major" order: every
-// particle has a rank r inside its cell, and a tile's particles are laid out round by round
-// (the rank-0 particles of the tile's cells, then the rank-1 particles, ...), cells
-// ascending inside a round, so that 64 consecutive particles sit in 64 different cells.
+// Split form: particles are laid out tile by tile (64 cells).  Every particle has a rank r
+// inside its cell; a tile's particles are laid out in pairs of ranks (see pair_table below):
+// pair round R holds, for every cell with at least 2R + 2 particles, its particles of ranks
+// 2R and 2R + 1, and the pairs, numbered round by round with cells ascending, come in chunks
+// of 64 -- 128 slots, the first particles of the chunk's pairs, then their second particles
+// in the same order -- so that a wavefront taking 128 slots holds in lanes l and 64 + l two
+// particles of one cell, and in a full round its 64 lanes hold the tile's 64 cells in order.
+// The pairs past the last whole chunk and the last particle of a cell with an odd count
+// follow singly, rank by rank, cells ascending; ranks of SORT_RCAP and beyond come last.
 // After a push the particle kernel has already counted the particles of every new cell and
 // ranked each particle inside it, so the sort is a per-tile round table, a scan over tiles
 // and the destination slot of every particle, kept as a permutation (ranked sort): the next
@@ -15,8 +20,8 @@
 // use of the order) applies the permutation first; batched runs do the same, with every
 // phase one launch over all members.  The first sort of a
 // species (arbitrary order) buckets by tile -- a count per tile, a scan, and a scatter whose
-// positions come from block-aggregated atomics -- and then rebuilds the round-major order
-// tile by tile.
+// positions come from block-aggregated atomics -- and then rebuilds the tile order tile by
+// tile.
 #include "pp_device.hpp"
 #include "pp_internal.hpp"
 
@@ -258,7 +263,53 @@ __global__ void __launch_bounds__(256) k_tile_max(const int32_t* __restrict__ st
     if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
 
-// Round-major rebuild of one tile (one workgroup per tile): ranks inside cells from LDS
+// The round table of one tile, built by one wavefront with lane = local cell, k = the
+// particles the lane's cell holds in the table (min(count, SORT_RCAP)), rmax = the largest k:
+// entry r (r < rmax) goes to put(r, entry), called by lane r - base in the pass over ranks
+// base .. base + 63.  nchunk = whole chunks of 64 pairs, intable = particles in the table.
+template <class Put>
+__device__ __forceinline__ void pair_table(int k, int rmax, Put put, int32_t& nchunk, int32_t& intable) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = lane == 0 ? 0ull : ((1ull << lane) - 1ull);
+    int pairs = k >> 1;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) pairs += __shfl_xor(pairs, o, 64);
+    nchunk = pairs >> 6;
+    int32_t pb = 0, sb = 0;  // pairs of the rounds before, single particles of the ranks before
+    for (int base = 0; base < rmax; base += 64) {
+        const int nr = rmax - base < 64 ? rmax - base : 64;
+        RoundEntry mine{0ull, 0ull, 0, 0};
+        for (int rr = 0; rr < nr; ++rr) {
+            const int r = base + rr;
+            const uint64_t pm = __ballot(k >= (r | 1) + 1);  // cells with a pair of ranks 2R, 2R + 1
+            const int32_t g = pb + (int32_t)__popcll(pm & below);
+            const bool chunked = ((pm >> lane) & 1ull) && g < (nchunk << 6);
+            const uint64_t sm = __ballot(k > r && !chunked);
+            if (lane == rr) {
+                mine.pmask = pm;
+                mine.smask = sm;
+                mine.pbefore = pb;
+                mine.sbefore = sb;
+            }
+            sb += (int32_t)__popcll(sm);
+            if (r & 1) pb += (int32_t)__popcll(pm);
+        }
+        if (lane < nr) put(base + lane, mine);
+    }
+    intable = (nchunk << 7) + sb;
+}
+
+// Slot inside its tile of the rank-r particle (r < SORT_RCAP) of local cell lc.
+__device__ __forceinline__ int32_t pair_slot(const RoundEntry& e, int32_t nchunk, int r, int lc) {
+    const uint64_t below = lc == 0 ? 0ull : ((1ull << lc) - 1ull);
+    if ((e.pmask >> lc) & 1ull) {
+        const int32_t g = e.pbefore + (int32_t)__popcll(e.pmask & below);
+        if (g < (nchunk << 6)) return ((g >> 6) << 7) + ((r & 1) << 6) + (g & 63);
+    }
+    return (nchunk << 7) + e.sbefore + (int32_t)__popcll(e.smask & below);
+}
+
+// Rebuild of one tile in the tile order (one workgroup per tile): ranks inside cells from LDS
 // atomics, the round table from ballots over the 64 cells, then a gather copy so the
 // writes are coalesced (the reads stay inside the tile's segment).
 constexpr int REORDER_RMAX = 1024;
@@ -283,8 +334,8 @@ struct ReorderArgs {
 template <typename T>
 __device__ __forceinline__ void tile_reorder_tile(const ReorderArgs<T>& A, int64_t tile) {
     __shared__ int32_t cnt[TILE_CELLS];
-    __shared__ int32_t Tr[REORDER_RMAX + 1];
-    __shared__ uint64_t Mr[REORDER_RMAX];
+    __shared__ RoundEntry tab[SORT_RCAP];
+    __shared__ int32_t nch, intab;
     __shared__ int32_t ovf;
     if (tile >= A.ntiles) return;
     const int32_t s = A.start[tile], e = A.start[tile + 1];
@@ -300,37 +351,26 @@ __device__ __forceinline__ void tile_reorder_tile(const ReorderArgs<T>& A, int64
     __syncthreads();
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
-        const int c = cnt[lane];
-        int mx = c;
+        const int k = cnt[lane] < SORT_RCAP ? cnt[lane] : SORT_RCAP;
+        int mx = k;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             const int other = __shfl_xor(mx, o, 64);
             mx = other > mx ? other : mx;
         }
-        const int rmax = mx < REORDER_RMAX ? mx : REORDER_RMAX;
-        int run = 0;
-        for (int r = 0; r < rmax; ++r) {
-            const uint64_t m = __ballot(c > r);
-            if (lane == 0) {
-                Tr[r] = run;
-                Mr[r] = m;
-            }
-            run += (int)__popcll(m);
+        int32_t nc, it;
+        pair_table(k, mx, [&](int r, const RoundEntry& en) { tab[r] = en; }, nc, it);
+        if (lane == 0) {
+            nch = nc;
+            intab = it;
         }
-        if (lane == 0) Tr[REORDER_RMAX] = run;
     }
     __syncthreads();
     for (int32_t i = s + threadIdx.x; i < e; i += 256) {
         const int32_t rk = A.rank[i];
         const int lc = rk >> 24;
         const int r = rk & 0xFFFFFF;
-        int32_t pos;
-        if (r < REORDER_RMAX) {
-            const uint64_t m = Mr[r];
-            pos = Tr[r] + (int32_t)__popcll(lc == 0 ? 0ull : (m & ((1ull << lc) - 1ull)));
-        } else {
-            pos = Tr[REORDER_RMAX] + atomicAdd(&ovf, 1);
-        }
+        const int32_t pos = r < SORT_RCAP ? pair_slot(tab[r], nch, r, lc) : intab + atomicAdd(&ovf, 1);
         A.perm[s + pos] = i;
     }
     __threadfence_block();
@@ -368,6 +408,7 @@ struct RankedArgs {
     RoundEntry* rounds;     // ntiles * SORT_RCAP
     int32_t* tot;           // ntiles + 1: tile totals, scanned into the next tile starts
     int32_t* rtot;          // ntiles: particles in the table's rounds
+    int32_t* nchunk;        // ntiles: whole chunks of 64 pairs
     int32_t* ovf;           // ntiles: overflow cursors
     int32_t* tile_max;      // largest tile population
     const int32_t* start;   // current tile starts (source order)
@@ -405,35 +446,13 @@ __device__ __forceinline__ void round_table_tile(const RankedArgs& A, int64_t t)
         mx = other > mx ? other : mx;
     }
     const int rmax = mx < SORT_RCAP ? mx : SORT_RCAP;
-    // rounds base .. base + 63: lane l keeps the mask of round base + l, a scan over the lanes
-    // gives the counts before it, and the entries are stored together
-    int run = 0;
-    for (int base = 0; base < rmax; base += 64) {
-        const int nr = rmax - base < 64 ? rmax - base : 64;
-        uint64_t mine = 0;
-        for (int r = 0; r < nr; ++r) {
-            const uint64_t m = __ballot(c > base + r);
-            mine = lane == r ? m : mine;
-        }
-        const int pc = (int)__popcll(mine);  // 0 for lanes past the last round
-        int incl = pc;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int up = __shfl_up(incl, o, 64);
-            incl += lane >= o ? up : 0;
-        }
-        if (lane < nr) {
-            RoundEntry e;
-            e.mask = mine;
-            e.before = run + incl - pc;
-            e.pad = 0;
-            A.rounds[t * SORT_RCAP + base + lane] = e;
-        }
-        run += __shfl(incl, 63, 64);
-    }
+    const int kc = c < SORT_RCAP ? c : SORT_RCAP;
+    int32_t nchunk, intable;
+    pair_table(kc, rmax, [&](int r, const RoundEntry& e) { A.rounds[t * SORT_RCAP + r] = e; }, nchunk, intable);
     if (lane == 0) {
         A.tot[t] = tot;
-        A.rtot[t] = run;
+        A.rtot[t] = intable;
+        A.nchunk[t] = nchunk;
         A.ovf[t] = 0;
         // one address for every tile: read first (the value only grows, so a stale read
         // can only cause an unneeded atomic), so that few of the atomics are issued
@@ -476,9 +495,8 @@ __device__ __forceinline__ void ranked_slots(const RankedArgs& A, int64_t p0, in
         lim[k] = A.tot[t[k] + 1];
         pos[k] = A.tot[t[k]];
         if (r[k] < SORT_RCAP) {
-            const int lc = key % TILE_CELLS;
             const RoundEntry e = A.rounds[(int64_t)t[k] * SORT_RCAP + r[k]];
-            pos[k] += e.before + (int32_t)__popcll(lc == 0 ? 0ull : (e.mask & ((1ull << lc) - 1ull)));
+            pos[k] += pair_slot(e, A.nchunk[t[k]], r[k], key % TILE_CELLS);
         } else {
             pos[k] += A.rtot[t[k]];
         }
@@ -695,6 +713,7 @@ static void ranked_args(const pp_run* r, int s, RankedArgs* A) {
     A->tot = S.offsets_next;
     A->rtot = r->sort_cursor;
     A->ovf = r->sort_cursor + nt;
+    A->nchunk = r->sort_cursor + 2 * nt;
     A->tile_max = r->tile_max + s;
     A->start = S.offsets;
     A->rank = S.rank;

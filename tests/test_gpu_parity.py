@@ -520,9 +520,31 @@ def test_first_sort_of_an_arbitrary_order_many_tiles(ppm, orc):
     run.close()
 
 
+def tile_order(counts, cap=96):
+    """Local cells, slot by slot, of a tile whose cells hold `counts` particles in the sort's
+    tile order: pair round R holds, for every cell with at least 2R + 2 of its first `cap`
+    ranks, its ranks 2R and 2R + 1; numbered round by round with cells ascending, whole chunks
+    of 64 pairs take 128 slots each (the chunk's first particles, then its second ones in the
+    same order); the rest of the first `cap` ranks follow singly, rank by rank, cells
+    ascending.  (Ranks from `cap` on come last, in any order, and are not listed.)"""
+    k = np.minimum(np.asarray(counts), cap)
+    pairs = [c for R in range(int(k.max(initial=0)) // 2) for c in range(64) if k[c] >= 2 * R + 2]
+    nchunk = len(pairs) // 64
+    order = []
+    for j in range(nchunk):
+        chunk = pairs[64 * j:64 * j + 64]
+        order += chunk + chunk
+    done = np.zeros(64, dtype=int)  # pairs of each cell placed in chunks
+    for c in pairs[:64 * nchunk]:
+        done[c] += 1
+    for r in range(int(k.max(initial=0))):
+        order += [c for c in range(64) if k[c] > r and r >= 2 * done[c]]
+    return order
+
+
 def _assert_round_major(cells, n, t):
-    """Tiles in order; inside a tile round r holds one particle of every cell with more than r
-    particles, local cells ascending (ranks beyond the round table may come last in any order)."""
+    """Tiles in order; inside a tile the sort's tile order (see tile_order); ranks beyond the
+    table come last in any order."""
     i, j, k = cells % n[0], (cells // n[0]) % n[1], cells // (n[0] * n[1])
     nt = [-(-n[d] // t[d]) for d in range(3)]
     tile = i // t[0] + nt[0] * (j // t[1] + nt[1] * (k // t[2]))
@@ -531,12 +553,9 @@ def _assert_round_major(cells, n, t):
     for tt in np.unique(tile):
         seg = lc[tile == tt]
         counts = np.bincount(seg, minlength=64)
-        pos = 0
-        for r in range(min(int(counts.max()), 96)):
-            want = np.flatnonzero(counts > r)
-            assert np.array_equal(seg[pos:pos + len(want)], want), (tt, r)
-            pos += len(want)
-        rest = seg[pos:]
+        want = tile_order(counts)
+        assert np.array_equal(seg[:len(want)], want), tt
+        rest = seg[len(want):]
         assert np.array_equal(np.sort(rest), np.sort(np.repeat(np.arange(64), np.maximum(counts - 96, 0))))
 
 
