@@ -472,8 +472,8 @@ def test_fp64_whole_run_plain_heating(ppm, orc):
 
 
 def test_sort_is_a_permutation_by_cell(ppm, orc):
-    # FP64 form: every cell's particles contiguous.  Split form: round-major order inside
-    # each tile (neighbouring particles sit in different cells); both are permutations.
+    # FP64 form: every cell's particles contiguous.  Split form: the tile order inside each
+    # tile (pairs of ranks in chunks of 64, see tile_order); both are permutations.
     n = (12, 8, 4)
     _say("sort", n)
     species, E, B = random_state(orc, n, 5, seed=11)
@@ -495,7 +495,7 @@ def test_sort_is_a_permutation_by_cell(ppm, orc):
         for s in range(2):
             g = run.particles(s)
             assert np.array_equal(np.sort(g["id"]), np.arange(len(g["id"])))
-            _assert_round_major(g["cell"], n, (4, 4, 4))
+            _assert_tile_order(g["cell"], n, (4, 4, 4))
     run.close()
 
 
@@ -514,7 +514,7 @@ def test_first_sort_of_an_arbitrary_order_many_tiles(ppm, orc):
             assert np.array_equal(np.sort(g["id"]), np.arange(len(g["id"])))
             if step == 0:  # the loaded particles, only reordered
                 assert np.array_equal(g["cell"][np.argsort(g["id"])], sp32[s]["cell"])
-            _assert_round_major(g["cell"], n, (4, 4, 4))
+            _assert_tile_order(g["cell"], n, (4, 4, 4))
         run.step()
     assert run.diagnostics().flags == 0
     run.close()
@@ -542,7 +542,7 @@ def tile_order(counts, cap=96):
     return order
 
 
-def _assert_round_major(cells, n, t):
+def _assert_tile_order(cells, n, t):
     """Tiles in order; inside a tile the sort's tile order (see tile_order); ranks beyond the
     table come last in any order."""
     i, j, k = cells % n[0], (cells // n[0]) % n[1], cells // (n[0] * n[1])
@@ -583,7 +583,7 @@ def test_fp32_crowded_cells_overflow_round_table(ppm, orc, extra):
         for s in range(2):
             g = run.particles(s)
             assert np.array_equal(np.sort(g["id"]), np.arange(len(g["id"])))
-            _assert_round_major(g["cell"], n, (4, 4, 4))
+            _assert_tile_order(g["cell"], n, (4, 4, 4))
         Eg, Bg, Jg = run.fields()
         assert rel_l2(Jg, ref.J) < 1e-5, step
         assert rel_l2(Eg - E, ref.E - E) < 1e-5, step
