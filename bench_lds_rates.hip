@@ -15,6 +15,7 @@
 // Every LDS index is checked on the host against the array size before any launch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <random>
@@ -417,7 +418,26 @@ int main() {
             const char* name;
             std::vector<std::pair<int, int>> seq;
         };
+        // the same order with every 64-slot chunk permuted class-major: a cell's class is its
+        // (x, y) place (16 classes, the bank pair of its window); the chunk's cells are sorted by
+        // (index among the chunk's cells of the same class, class), so that each group of 16
+        // lanes holds distinct classes where the chunk allows it (full rounds are unchanged)
+        auto class_major = [&](std::vector<std::pair<int, int>> seq) {
+            for (size_t b = 0; b + 64 <= seq.size(); b += 64) {
+                std::vector<std::pair<int, std::pair<int, int>>> key;
+                int seen[16] = {0};
+                for (int l = 0; l < 64; ++l) {
+                    const int c = seq[b + l].first, cls = c % 16;
+                    key.push_back({seen[cls]++ * 16 + cls, seq[b + l]});
+                }
+                std::stable_sort(key.begin(), key.end(),
+                                 [](const auto& x, const auto& y) { return x.first < y.first; });
+                for (int l = 0; l < 64; ++l) seq[b + l] = key[l].second;
+            }
+            return seq;
+        };
         std::vector<Pat> pats = {{"cell rounds, Poisson(32) tile", cell_rounds(cnt)},
+                                 {"cell rounds class-major, Poisson(32) tile", class_major(cell_rounds(cnt))},
                                  {"column rounds, Poisson(32) tile", column_rounds(cnt)},
                                  {"cell rounds, 32 in every cell", cell_rounds(full)}};
         int* dchunks = nullptr;
