@@ -549,7 +549,8 @@ __device__ __forceinline__ void step_particle(const Gpd32Args& A, const Sp32& S,
 // of (1.5*2^52 + round(P_a F)) in one 64-bit integer atomic.  For a pair the two patterns,
 // each rounded on its own, are added as integers before the one atomic, so the node gets the
 // same exact fixed-point sum as from two atomics.  f2 != 0 marks lanes whose second particle
-// deposits; on the others its factors are replaced by zeros.
+// deposits; on the others its prefix sums are zeros, so that its patterns are 1.5*2^52 itself,
+// whose low 51 bits are zero (the caller keeps that particle's window state finite).
 template <int O, class TL, bool PAIR>
 __device__ __forceinline__ void deposit_cc(const TL& L, unsigned long long* cur, const Win<O>& P1, const double* facq1,
                                            const Win<O>& P2, const double* facq2, float f2) {
@@ -582,7 +583,7 @@ __device__ __forceinline__ void deposit_cc(const TL& L, unsigned long long* cur,
         for (int a = 0; a <= O; ++a) {
             acc1 += W1.DS[comp][a];
             Pq1[a] = (a < O || own1) ? (double)acc1 * facq1[comp] : 0.0;
-            if (PAIR) {  // a select, not a product: the absent particle's factors may be anything
+            if (PAIR) {  // zero for a second particle that deposits nothing
                 acc2 += W2.DS[comp][a];
                 Pq2[a] = (use2 && (a < O || own2)) ? (double)acc2 * facq2[comp] : 0.0;
             }
@@ -602,11 +603,9 @@ __device__ __forceinline__ void deposit_cc(const TL& L, unsigned long long* cur,
                 const double Fd1 = (double)(g1 * (W1.S0[d2][e] + 0.5f * W1.DS[d2][e]) +
                                             h1 * (0.5f * W1.S0[d2][e] + (1.0f / 3.0f) * W1.DS[d2][e]));
                 double Fd2 = 0.0;
-                if (PAIR) {
-                    const float F2 = g2 * (W2.S0[d2][e] + 0.5f * W2.DS[d2][e]) +
-                                     h2 * (0.5f * W2.S0[d2][e] + (1.0f / 3.0f) * W2.DS[d2][e]);
-                    Fd2 = use2 ? (double)F2 : 0.0;
-                }
+                if (PAIR)
+                    Fd2 = (double)(g2 * (W2.S0[d2][e] + 0.5f * W2.DS[d2][e]) +
+                                   h2 * (0.5f * W2.S0[d2][e] + (1.0f / 3.0f) * W2.DS[d2][e]));
                 const int rowo = off0 + bq * cst[d1] + e * cst[d2];
 #pragma unroll
                 for (int a = 0; a <= O; ++a) {
@@ -696,6 +695,13 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
                 Win<O> W1, W2;
                 const int32_t q1 = b + lane, q2 = b + 64 + lane;
                 W1.dep = W2.dep = false;
+                // a second particle that deposits nothing still enters the paired deposit with
+                // zero prefix sums: its window state must then be finite
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    W2.f[d] = W2.x1[d] = 0.5f;
+                    W2.loc[d] = 0;
+                }
                 if (q1 < end) step_particle<O, TL>(A, S, L, C, q1, W1, bad_all);
                 if (q2 < end) step_particle<O, TL>(A, S, L, C, q2, W2, bad_all);
                 const bool both = W1.dep && W2.dep;
