@@ -15,6 +15,13 @@ __device__ __forceinline__ int wrap(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
+// The same for i within one period of [0, n) (a compare and an add; no division), falling
+// back to the general form farther away (grids smaller than a tile's halo).
+__device__ __forceinline__ int wrap_near(int i, int n) {
+    const int j = i < 0 ? i + n : (i >= n ? i - n : i);
+    return (j >= 0 && j < n) ? j : wrap(i, n);
+}
+
 // Weights of order O (Sec. II: TSC for O = 2, PCS for O = 3) of the O+1 nodes
 // i0, i0+1, ..., i0+O nearest to coordinate y (node positions are integers).
 //   O = 2: c = floor(y + 1/2), t = y - c in [-1/2, 1/2), i0 = c - 1,

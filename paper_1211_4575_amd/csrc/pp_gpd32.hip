@@ -89,6 +89,7 @@ struct Gpd32Args {
 };
 
 constexpr int GPD32_BS = 256;
+constexpr int STAGE_BATCH = 8;  // field loads / current reads a thread issues before the first wait
 constexpr double ROUND_MAGIC = 6755399441055744.0;  // 1.5 * 2^52
 constexpr unsigned long long LOW51 = (1ull << 51) - 1ull;
 constexpr long long BIT50 = 1ll << 50;
@@ -528,7 +529,7 @@ __device__ __forceinline__ void step_particle(const Gpd32Args& A, const Sp32& S,
         }
         fn[d] = o;
         shv[d] = (int)sh;
-        nc3[d] = wrap(gc[d] + (int)sh, A.n[d]);
+        nc3[d] = wrap_near(gc[d] + (int)sh, A.n[d]);
     }
     const int32_t newcell = nc3[0] + n0 * (nc3[1] + n1 * nc3[2]);
     S.cell_o[q] = newcell;
@@ -646,21 +647,34 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
     float* fld = (float*)lds_raw;  // 6 * fvol
     unsigned long long* cur = (unsigned long long*)(lds_raw + ((6 * L.fvol * sizeof(float) + 15) & ~(size_t)15));
 
-    // 1. stage fields, clear the current block
-    for (int q = threadIdx.x; q < 6 * L.fvol; q += GPD32_BS) {
-        const int comp = q / L.fvol;
-        const int r = q - comp * L.fvol;
-        const int c = r / L.fplane;
-        const int rr = r - c * L.fplane;
-        const int bb = rr / L.frow;
-        const int a = rr - bb * L.frow;
-        if (a >= L.fex || bb >= L.fey) continue;  // padding
-        const int gi = wrap(org[0] - L.flox + a, n0);
-        const int gj = wrap(org[1] - L.floy + bb, n1);
-        const int gk = wrap(org[2] - L.floz + c, n2);
-        const int64_t gq = (int64_t)gi + (int64_t)n0 * (gj + (int64_t)n1 * gk);
-        const double* src = comp < 3 ? A.E + comp * A.nc : A.B + (comp - 3) * A.nc;
-        fld[q] = (float)src[gq];
+    // 1. stage fields (each thread has STAGE_BATCH loads in flight before it waits for the
+    // first), clear the current block
+    for (int q0 = threadIdx.x; q0 < 6 * L.fvol; q0 += STAGE_BATCH * GPD32_BS) {
+        double v[STAGE_BATCH];
+        int dst[STAGE_BATCH];  // LDS entry, or -1 (past the end, or padding)
+#pragma unroll
+        for (int k = 0; k < STAGE_BATCH; ++k) {
+            // every lane loads (an entry past the end or in the padding reads a node of the
+            // tile instead and writes nothing), so that no load waits at a branch
+            const int q = q0 + k * GPD32_BS;
+            const int qc = q < 6 * L.fvol ? q : 0;
+            const int comp = qc / L.fvol;
+            const int r = qc - comp * L.fvol;
+            const int c = r / L.fplane;
+            const int rr = r - c * L.fplane;
+            const int bb = rr / L.frow;
+            const int a = rr - bb * L.frow;
+            dst[k] = (q < 6 * L.fvol && a < L.fex && bb < L.fey) ? q : -1;
+            const int gi = wrap_near(org[0] - L.flox + (a < L.fex ? a : 0), n0);
+            const int gj = wrap_near(org[1] - L.floy + (bb < L.fey ? bb : 0), n1);
+            const int gk = wrap_near(org[2] - L.floz + c, n2);
+            const int64_t gq = (int64_t)gi + (int64_t)n0 * (gj + (int64_t)n1 * gk);
+            const double* src = comp < 3 ? A.E + comp * A.nc : A.B + (comp - 3) * A.nc;
+            v[k] = src[gq];
+        }
+#pragma unroll
+        for (int k = 0; k < STAGE_BATCH; ++k)
+            if (dst[k] >= 0) fld[dst[k]] = (float)v[k];
     }
     for (int q = threadIdx.x; q < 3 * L.cvol; q += GPD32_BS) cur[q] = 0ull;
     int32_t* slots = (int32_t*)(cur + 3 * L.cvol);  // A.nslots destination-cell counters
@@ -747,21 +761,33 @@ __device__ __forceinline__ void gpd32_tile(const Gpd32Args& A, int64_t tile, uns
     }
     if (bad_all) atomic_or_flag(A.flags, bad_all);
 
-    // 3. flush the current block (integer adds commute: the sum is order-independent)
-    for (int q = threadIdx.x; q < 3 * L.cvol; q += GPD32_BS) {
-        const long long v = fixed_sum(cur[q]);
-        if (v == 0) continue;
-        const int comp = q / L.cvol;
-        const int r = q - comp * L.cvol;
-        const int c = r / L.cplane;
-        const int rr = r - c * L.cplane;
-        const int bb = rr / L.crow;
-        const int a = rr - bb * L.crow;
-        if (bb >= L.cey) continue;  // padding
-        const int gi = wrap(org[0] - L.clox + a, n0);
-        const int gj = wrap(org[1] - L.cloy + bb, n1);
-        const int gk = wrap(org[2] - L.cloz + c, n2);
-        atomicAdd(A.Jq + comp * A.nc + (int64_t)gi + (int64_t)n0 * (gj + (int64_t)n1 * gk), (unsigned long long)v);
+    // 3. flush the current block (integer adds commute: the sum is order-independent); each
+    // thread reads STAGE_BATCH entries before it waits for the first
+    for (int q0 = threadIdx.x; q0 < 3 * L.cvol; q0 += STAGE_BATCH * GPD32_BS) {
+        unsigned long long raw[STAGE_BATCH];
+#pragma unroll
+        for (int k = 0; k < STAGE_BATCH; ++k) {
+            const int q = q0 + k * GPD32_BS;
+            raw[k] = q < 3 * L.cvol ? cur[q] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < STAGE_BATCH; ++k) {
+            const int q = q0 + k * GPD32_BS;
+            const long long v = fixed_sum(raw[k]);
+            if (v == 0) continue;  // also every entry past the end
+            const int comp = q / L.cvol;
+            const int r = q - comp * L.cvol;
+            const int c = r / L.cplane;
+            const int rr = r - c * L.cplane;
+            const int bb = rr / L.crow;
+            const int a = rr - bb * L.crow;
+            if (bb >= L.cey) continue;  // padding
+            const int gi = wrap_near(org[0] - L.clox + a, n0);
+            const int gj = wrap_near(org[1] - L.cloy + bb, n1);
+            const int gk = wrap_near(org[2] - L.cloz + c, n2);
+            atomicAdd(A.Jq + comp * A.nc + (int64_t)gi + (int64_t)n0 * (gj + (int64_t)n1 * gk),
+                      (unsigned long long)v);
+        }
     }
 }
 
