@@ -484,22 +484,30 @@ __device__ __forceinline__ void ranked_slots(const RankedArgs& A, int64_t p0, in
         r[k] = v ? A.rank[p] : -1;
         c[k] = v ? A.cell[p] : 0;
     }
+    // the table reads of every particle, issued together and unconditionally (a particle
+    // without a slot reads its tile's first entries and ignores them), then the slots
+    int32_t lc[PERM_PER], base[PERM_PER], nch[PERM_PER], rt[PERM_PER];
+    RoundEntry e[PERM_PER];
 #pragma unroll
     for (int k = 0; k < PERM_PER; ++k) {
-        t[k] = 0;
-        pos[k] = -1;
-        lim[k] = 0;
-        if (r[k] < 0) continue;
-        const int32_t key = key_cell(A.G, c[k]);
+        const int32_t key = key_cell(A.G, r[k] < 0 ? 0 : c[k]);
         t[k] = key / TILE_CELLS;
+        lc[k] = key % TILE_CELLS;
+    }
+#pragma unroll
+    for (int k = 0; k < PERM_PER; ++k) {
+        base[k] = A.tot[t[k]];
         lim[k] = A.tot[t[k] + 1];
-        pos[k] = A.tot[t[k]];
-        if (r[k] < SORT_RCAP) {
-            const RoundEntry e = A.rounds[(int64_t)t[k] * SORT_RCAP + r[k]];
-            pos[k] += pair_slot(e, A.nchunk[t[k]], r[k], key % TILE_CELLS);
-        } else {
-            pos[k] += A.rtot[t[k]];
-        }
+        nch[k] = A.nchunk[t[k]];
+        rt[k] = A.rtot[t[k]];
+        e[k] = A.rounds[(int64_t)t[k] * SORT_RCAP + (r[k] >= 0 && r[k] < SORT_RCAP ? r[k] : 0)];
+    }
+#pragma unroll
+    for (int k = 0; k < PERM_PER; ++k) {
+        // computed for every particle and selected (no branch the table reads could sink into)
+        const bool in_table = r[k] >= 0 && r[k] < SORT_RCAP;
+        const int32_t ps = pair_slot(e[k], nch[k], in_table ? r[k] : 0, lc[k]);
+        pos[k] = r[k] < 0 ? -1 : base[k] + (in_table ? ps : rt[k]);
     }
     const int lane = threadIdx.x & 63;
 #pragma unroll
