@@ -250,6 +250,7 @@ struct MMIArgs {
     int64_t start, count;
     double gamma_b, sig[4];  // beam Lorentz factor, thermal spread per species
     int split;
+    int quiet;  // pairs 2k, 2k+1 at one position with opposite rest-frame thermal velocities
     int32_t* cell[4];
     void* off[4][3];
     void* u[4][3];
@@ -261,7 +262,9 @@ struct MMIArgs {
 __global__ void __launch_bounds__(256) k_mmi(MMIArgs A) {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= A.count) return;
-    const uint64_t idx = (uint64_t)(A.start + l);
+    const uint64_t pidx = (uint64_t)(A.start + l);
+    const uint64_t idx = A.quiet ? (pidx & ~1ull) : pidx;  // the index whose draws are used
+    const double sgn = A.quiet && (pidx & 1ull) ? -1.0 : 1.0;
     const double beta = sqrt(1.0 - 1.0 / (A.gamma_b * A.gamma_b));
     for (int pop = 0; pop < 2; ++pop) {
         double U[4];
@@ -282,7 +285,8 @@ __global__ void __launch_bounds__(256) k_mmi(MMIArgs A) {
             uniform_pair(A.seed, idx, 1, stream_id(5, s, 1), V[2], V[3]);
             const double r0 = sqrt(-2.0 * log(V[0])), t0 = 2.0 * M_PI * V[1];
             const double r1 = sqrt(-2.0 * log(V[2])), t1 = 2.0 * M_PI * V[3];
-            double uv[3] = {A.sig[s] * r0 * cos(t0), A.sig[s] * r0 * sin(t0), A.sig[s] * r1 * cos(t1)};
+            double uv[3] = {sgn * (A.sig[s] * r0 * cos(t0)), sgn * (A.sig[s] * r0 * sin(t0)),
+                            sgn * (A.sig[s] * r1 * cos(t1))};
             if (pop == 0 && A.gamma_b != 1.0) {
                 const double g = sqrt(1.0 + uv[0] * uv[0] + uv[1] * uv[1] + uv[2] * uv[2]);
                 uv[2] = A.gamma_b * (uv[2] + beta * g);
@@ -413,15 +417,16 @@ int ppi_kelvin_helmholtz(uint64_t seed, const int32_t n[3], int64_t start, int64
 }
 
 int ppi_mmi(uint64_t seed, const int32_t n[3], int64_t start, int64_t count, double gamma_b, double T_b, double T_p,
-            double mass_ratio, int32_t split, int32_t* const cell[4], void* const off[4][3], void* const u[4][3],
-            void* hip_stream) {
+            double mass_ratio, int32_t quiet, int32_t split, int32_t* const cell[4], void* const off[4][3],
+            void* const u[4][3], void* hip_stream) {
     if (!n || start < 0 || count < 0 || !(gamma_b >= 1.0) || !(T_b >= 0.0) || !(T_p >= 0.0) || !(mass_ratio > 0.0))
         return -1;
     for (int d = 0; d < 3; ++d)
         if (n[d] < 1) return -1;
-    if (split < 0 || split > 2) return -1;
+    if (split < 0 || split > 2 || quiet < 0 || quiet > 1) return -1;
     if (count == 0) return 0;
     MMIArgs A;
+    A.quiet = quiet;
     A.seed = seed;
     for (int d = 0; d < 3; ++d) A.n[d] = n[d];
     A.start = start;

@@ -294,7 +294,7 @@ MMI_SPECIES = (("beam electron", -1.0, False, True), ("beam ion", 1.0, True, Tru
 
 
 def mmi(seed=SEED_BASE, n=(128, 128, 128), ppc=20, gamma_b=4.0, n_b=0.1, n_p=0.9, T_b=0.01, T_p=0.1,
-        mass_ratio=1836.0, dx=0.1, cfl=0.4, shape_order=3, field_order=6, index_range=None):
+        mass_ratio=1836.0, dx=0.1, cfl=0.4, shape_order=3, field_order=6, index_range=None, quiet=False):
     """Relativistic mixed-mode two-stream set-up (Sec. VI, relativistic two-stream test): a cold
     thin neutral beam (electrons and ions, density n_b, Lorentz factor gamma_b along +z) through
     a warm thick neutral background at rest (density n_p); each population's electrons and ions
@@ -302,19 +302,24 @@ def mmi(seed=SEED_BASE, n=(128, 128, 128), ppc=20, gamma_b=4.0, n_b=0.1, n_p=0.9
     field is loaded.  Thermal proper velocities are Gaussian with variance T/m per component in
     the population's rest frame (temperatures in units of m_e c^2), then boosted.  ppc particles
     per cell per species; species order: beam electron, beam ion, background electron,
-    background ion.  ``index_range`` = (start, stop) loads that slice of every species."""
+    background ion.  ``index_range`` = (start, stop) loads that slice of every species.
+    ``quiet``: a quiet start, particles 2k and 2k+1 of a species at the same position (the
+    draws of index 2k) with opposite rest-frame thermal velocities, so that the thermal
+    current of each pair cancels at the start and the fields grow from a lower noise floor."""
     npart = n[0] * n[1] * n[2] * ppc
     lo, hi = (0, npart) if index_range is None else index_range
     idx = np.arange(lo, hi, dtype=np.uint64)
+    draw = idx & ~np.uint64(1) if quiet else idx
+    sign = np.where(idx & np.uint64(1), -1.0, 1.0) if quiet else np.ones(len(idx))
     pos = {}
     for pop in (0, 1):  # 0 beam, 1 background
-        U = uniforms(seed, _stream(5, 2 * pop, 0), idx, 3)
+        U = uniforms(seed, _stream(5, 2 * pop, 0), draw, 3)
         pos[pop] = np.stack([np.where(U[d] * n[d] >= n[d], 0.0, U[d] * n[d]) for d in range(3)])
     sp = []
     for s, (nm, q, ion, beam) in enumerate(MMI_SPECIES):
         m = mass_ratio if ion else 1.0
         T = T_b if beam else T_p
-        G = normals(seed, _stream(5, s, 1), idx, 3)
+        G = normals(seed, _stream(5, s, 1), draw, 3) * sign
         u = boost_z(math.sqrt(T / m) * G, gamma_b if beam else 1.0)
         dens = n_b if beam else n_p
         sp.append(Species(nm, q, m, dens / ppc, pos[0 if beam else 1].copy(), u))

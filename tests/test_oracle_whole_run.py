@@ -203,6 +203,30 @@ def test_mmi_loader_is_neutral_and_boosted():
     assert round(r["mmi"], 3) == 0.201 and round(r["fi"], 3) == 0.153 and round(r["tsi"], 3) == 0.080
 
 
+def test_mmi_quiet_start_pairs_cancel_the_thermal_current():
+    # quiet start: particles 2k and 2k+1 of every species sit at one position with opposite
+    # rest-frame thermal velocities, so each pair of the background (no boost) carries no
+    # current and the set-up is the noisy one's even particles, mirrored
+    from paper_1211_4575_amd import inputs as I
+    wl = I.mmi(n=(6, 5, 4), ppc=40, quiet=True)
+    noisy = I.mmi(n=(6, 5, 4), ppc=40)
+    for sp, sn in zip(wl.species, noisy.species):
+        assert np.array_equal(sp.pos[:, 0::2], sp.pos[:, 1::2])
+        assert np.array_equal(sp.pos[:, 0::2], sn.pos[:, 0::2])
+        assert np.array_equal(sp.u[:, 0::2], sn.u[:, 0::2])
+    for sp in wl.species[2:]:  # background: at rest, so the pair's proper velocities cancel
+        assert np.array_equal(sp.u[:, 0::2], -sp.u[:, 1::2])
+    # the beam's pairs: opposite rest-frame velocities, then the boost G = 4 along z, so the
+    # transverse parts are opposite and the z parts average to G beta gamma', gamma' the shared
+    # rest-frame Lorentz factor (recovered from the even member: gamma' = G (gamma - beta u_z))
+    G, beta = 4.0, np.sqrt(1 - 1 / 16.0)
+    for e_b in wl.species[:2]:
+        assert np.array_equal(e_b.u[:2, 0::2], -e_b.u[:2, 1::2])
+        ue = e_b.u[:, 0::2]
+        gam_rest = G * (np.sqrt(1.0 + (ue ** 2).sum(axis=0)) - beta * ue[2])
+        np.testing.assert_allclose(0.5 * (e_b.u[2, 0::2] + e_b.u[2, 1::2]), G * beta * gam_rest, rtol=1e-12)
+
+
 def test_direct_current_breaks_gauss_and_the_filter_restores_it(orc):
     # the plain-heating workload with the direct current (eq. "jj2"): Gauss's law drifts away
     # from its initial zero; five filter passes per step keep it orders of magnitude lower,
