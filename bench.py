@@ -599,7 +599,7 @@ MMI_SCHEMES = {1: (2, 2, False, 2), 2: (2, 3, False, 2), 3: (6, 2, False, 2), 4:
 
 
 def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress=250, kmax_index=16, scheme=5,
-            quiet=False):
+            quiet=False, lattice=None):
     """Mixed-mode two-stream run on g^3 cells of a cubic box of ``box`` skin depths, generated
     on the device (FP32 split form).  Returns (times, energies [steps + 1, 4], wall s,
     particles, final diagnostics, (sample times, wave-number indices, bin energies)): per step
@@ -610,7 +610,8 @@ def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress
     longitudinal field energy E.k/|k| of the Fourier modes 60-80 degrees from the beam with
     1 <= |k| <= 8, and the longitudinal energy of every single Fourier mode whose indices are
     all within kmax_index (the bin energies, for rates mode by mode).  ``quiet``: the loader's
-    quiet start (pairs of particles with opposite thermal velocities)."""
+    quiet start (pairs of particles with opposite thermal velocities); ``lattice``: its lattice
+    positions (points per cell and axis)."""
     import numpy as np
 
     from paper_1211_4575_amd import inputs as I
@@ -628,7 +629,7 @@ def run_mmi(torch, pp, ind, g, ppc, steps, T_b, T_p, box=12.8, cfl=0.4, progress
         cnt = min(chunk, npart - start)
         ind.mmi(SEED, n, start, cnt, 4.0, T_b, T_p, 1836.0, ind.split_mode(True, O), [c[start:] for c in cells],
                 [[o[d, start:] for d in range(3)] for o in offs], [[u[d, start:] for d in range(3)] for u in us], st,
-                quiet=quiet)
+                quiet=quiet, lattice=lattice)
     species = []
     for s, (nm, q, ion, beam) in enumerate(I.MMI_SPECIES):
         species.append(dict(q=q, m=1836.0 if ion else 1.0, w=(0.1 if beam else 0.9) / ppc, u=us[s], cell=cells[s],
@@ -786,7 +787,8 @@ def mmi_bench(args, torch, pp):
     from paper_1211_4575_amd import inputs as I
     from paper_1211_4575_amd import inputs_device as ind
     t, H, wall, npart, d, (tb, kv, W) = run_mmi(torch, pp, ind, args.mmi_grid, args.mmi_ppc, args.mmi_steps,
-                                                args.mmi_tb, args.mmi_tp, scheme=args.mmi_run, quiet=args.mmi_quiet)
+                                                args.mmi_tb, args.mmi_tp, scheme=args.mmi_run, quiet=args.mmi_quiet,
+                                                lattice=args.mmi_lattice)
     if args.save_history:
         np.savez(f"{args.save_history}_mmi.npz", t=t, w=H, tb=tb, kv=kv, bins=W)
     theory = I.mmi_rates()
@@ -808,7 +810,8 @@ def mmi_bench(args, torch, pp):
                       "dt": 0.4 * 12.8 / g, "steps": args.mmi_steps, "T_b": args.mmi_tb, "T_p": args.mmi_tp,
                       "run": args.mmi_run, "field_order": MMI_SCHEMES[args.mmi_run][0],
                       "shape_order": MMI_SCHEMES[args.mmi_run][1], "charge_conserving": MMI_SCHEMES[args.mmi_run][2],
-                      "time_order": MMI_SCHEMES[args.mmi_run][3], "quiet_start": bool(args.mmi_quiet)},
+                      "time_order": MMI_SCHEMES[args.mmi_run][3], "quiet_start": bool(args.mmi_quiet),
+                      "lattice": args.mmi_lattice},
            "updates_per_s": npart * args.mmi_steps / wall, "wall_s": wall,
            "final_gauss_rel": d.gauss_max / d.rho_ref, "flags": d.flags, "linear_phase_end": t_end,
            "fastest_modes": modes, **fits}
@@ -1077,6 +1080,8 @@ def main(argv=None):
     ap.add_argument("--mmi-fit-width", type=float, default=6.0, help="mmi: fit window (1/w_pe)")
     ap.add_argument("--mmi-quiet", action="store_true",
                     help="mmi: quiet start (particle pairs with opposite thermal velocities)")
+    ap.add_argument("--mmi-lattice", type=int, nargs=3, default=None, metavar=("PX", "PY", "PZ"),
+                    help="mmi: positions on a regular lattice of PX*PY*PZ (= ppc) points per cell")
     ap.add_argument("--mmi-run", type=int, choices=sorted(MMI_SCHEMES), default=5,
                     help="mmi: scheme of the paper's comparison (1-4 direct current + filter, 5 charge-conserving, "
                          "6 with fourth-order time integration)")

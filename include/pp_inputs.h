@@ -65,11 +65,15 @@ int ppi_kelvin_helmholtz(uint64_t seed, const int32_t n[3], int64_t start, int64
  * per component (T_b for the beam, T_p for the background, in units of m_e c^2, ion mass
  * mass_ratio), the beam then boosted along +z with Lorentz factor gamma_b.  quiet = 1: a quiet
  * start, particles 2k and 2k+1 of a species at one position (the draws of index 2k) with
- * opposite rest-frame thermal velocities (0: independent draws).  Output layout and split
- * modes as above, for four species; -1 for a quiet flag other than 0 or 1. */
+ * opposite rest-frame thermal velocities (0: independent draws).  lattice (NULL: uniform
+ * random positions) = (px, py, pz): both populations on a regular lattice of px py pz points
+ * per cell, particle i at point i mod (px py pz) of cell i div (px py pz) (x fastest), the
+ * points at ((a + 1/2) / px, (b + 1/2) / py, (c + 1/2) / pz) of the cell.  Output layout and
+ * split modes as above, for four species; -1 for a quiet flag other than 0 or 1 or a lattice
+ * extent below 1. */
 int ppi_mmi(uint64_t seed, const int32_t n[3], int64_t start, int64_t count, double gamma_b, double T_b, double T_p,
-            double mass_ratio, int32_t quiet, int32_t split, int32_t* const cell[4], void* const off[4][3],
-            void* const u[4][3], void* hip_stream);
+            double mass_ratio, int32_t quiet, const int32_t lattice[3], int32_t split, int32_t* const cell[4],
+            void* const off[4][3], void* const u[4][3], void* hip_stream);
 
 #ifdef __cplusplus
 }

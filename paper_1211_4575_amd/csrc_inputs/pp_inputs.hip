@@ -251,6 +251,7 @@ struct MMIArgs {
     double gamma_b, sig[4];  // beam Lorentz factor, thermal spread per species
     int split;
     int quiet;  // pairs 2k, 2k+1 at one position with opposite rest-frame thermal velocities
+    int lat[3];  // sub-lattice points per cell and axis (0: uniform random positions)
     int32_t* cell[4];
     void* off[4][3];
     void* u[4][3];
@@ -267,13 +268,21 @@ __global__ void __launch_bounds__(256) k_mmi(MMIArgs A) {
     const double sgn = A.quiet && (pidx & 1ull) ? -1.0 : 1.0;
     const double beta = sqrt(1.0 - 1.0 / (A.gamma_b * A.gamma_b));
     for (int pop = 0; pop < 2; ++pop) {
-        double U[4];
-        uniform_pair(A.seed, idx, 0, stream_id(5, 2 * pop, 0), U[0], U[1]);
-        uniform_pair(A.seed, idx, 1, stream_id(5, 2 * pop, 0), U[2], U[3]);
         double pos[3];
-        for (int d = 0; d < 3; ++d) {
-            const double x = U[d] * A.n[d];
-            pos[d] = x >= A.n[d] ? 0.0 : x;
+        if (A.lat[0] > 0) {  // regular lattice: point pidx mod ppc of cell pidx div ppc
+            const int64_t ppc = (int64_t)A.lat[0] * A.lat[1] * A.lat[2];
+            const int64_t c = (int64_t)pidx / ppc, sub = (int64_t)pidx % ppc;
+            const int64_t cell[3] = {c % A.n[0], (c / A.n[0]) % A.n[1], c / ((int64_t)A.n[0] * A.n[1])};
+            const int64_t pt[3] = {sub % A.lat[0], (sub / A.lat[0]) % A.lat[1], sub / ((int64_t)A.lat[0] * A.lat[1])};
+            for (int d = 0; d < 3; ++d) pos[d] = (double)cell[d] + ((double)pt[d] + 0.5) / (double)A.lat[d];
+        } else {
+            double U[4];
+            uniform_pair(A.seed, idx, 0, stream_id(5, 2 * pop, 0), U[0], U[1]);
+            uniform_pair(A.seed, idx, 1, stream_id(5, 2 * pop, 0), U[2], U[3]);
+            for (int d = 0; d < 3; ++d) {
+                const double x = U[d] * A.n[d];
+                pos[d] = x >= A.n[d] ? 0.0 : x;
+            }
         }
         int32_t cellv = 0;
         float offf[3];
@@ -417,16 +426,18 @@ int ppi_kelvin_helmholtz(uint64_t seed, const int32_t n[3], int64_t start, int64
 }
 
 int ppi_mmi(uint64_t seed, const int32_t n[3], int64_t start, int64_t count, double gamma_b, double T_b, double T_p,
-            double mass_ratio, int32_t quiet, int32_t split, int32_t* const cell[4], void* const off[4][3],
-            void* const u[4][3], void* hip_stream) {
+            double mass_ratio, int32_t quiet, const int32_t lattice[3], int32_t split, int32_t* const cell[4],
+            void* const off[4][3], void* const u[4][3], void* hip_stream) {
     if (!n || start < 0 || count < 0 || !(gamma_b >= 1.0) || !(T_b >= 0.0) || !(T_p >= 0.0) || !(mass_ratio > 0.0))
         return -1;
+    if (lattice && (lattice[0] < 1 || lattice[1] < 1 || lattice[2] < 1)) return -1;
     for (int d = 0; d < 3; ++d)
         if (n[d] < 1) return -1;
     if (split < 0 || split > 2 || quiet < 0 || quiet > 1) return -1;
     if (count == 0) return 0;
     MMIArgs A;
     A.quiet = quiet;
+    for (int d = 0; d < 3; ++d) A.lat[d] = lattice ? lattice[d] : 0;
     A.seed = seed;
     for (int d = 0; d < 3; ++d) A.n[d] = n[d];
     A.start = start;

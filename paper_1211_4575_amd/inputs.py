@@ -294,7 +294,8 @@ MMI_SPECIES = (("beam electron", -1.0, False, True), ("beam ion", 1.0, True, Tru
 
 
 def mmi(seed=SEED_BASE, n=(128, 128, 128), ppc=20, gamma_b=4.0, n_b=0.1, n_p=0.9, T_b=0.01, T_p=0.1,
-        mass_ratio=1836.0, dx=0.1, cfl=0.4, shape_order=3, field_order=6, index_range=None, quiet=False):
+        mass_ratio=1836.0, dx=0.1, cfl=0.4, shape_order=3, field_order=6, index_range=None, quiet=False,
+        lattice=None):
     """Relativistic mixed-mode two-stream set-up (Sec. VI, relativistic two-stream test): a cold
     thin neutral beam (electrons and ions, density n_b, Lorentz factor gamma_b along +z) through
     a warm thick neutral background at rest (density n_p); each population's electrons and ions
@@ -305,16 +306,30 @@ def mmi(seed=SEED_BASE, n=(128, 128, 128), ppc=20, gamma_b=4.0, n_b=0.1, n_p=0.9
     background ion.  ``index_range`` = (start, stop) loads that slice of every species.
     ``quiet``: a quiet start, particles 2k and 2k+1 of a species at the same position (the
     draws of index 2k) with opposite rest-frame thermal velocities, so that the thermal
-    current of each pair cancels at the start and the fields grow from a lower noise floor."""
+    current of each pair cancels at the start and the fields grow from a lower noise floor.
+    ``lattice`` = (px, py, pz) with px py pz = ppc: every population on a regular lattice
+    instead, particle i at sub-lattice point i mod ppc of cell i div ppc (cells and points x
+    fastest), points at ((a + 1/2) / px, (b + 1/2) / py, (c + 1/2) / pz) of the cell."""
     npart = n[0] * n[1] * n[2] * ppc
     lo, hi = (0, npart) if index_range is None else index_range
     idx = np.arange(lo, hi, dtype=np.uint64)
     draw = idx & ~np.uint64(1) if quiet else idx
     sign = np.where(idx & np.uint64(1), -1.0, 1.0) if quiet else np.ones(len(idx))
     pos = {}
-    for pop in (0, 1):  # 0 beam, 1 background
-        U = uniforms(seed, _stream(5, 2 * pop, 0), draw, 3)
-        pos[pop] = np.stack([np.where(U[d] * n[d] >= n[d], 0.0, U[d] * n[d]) for d in range(3)])
+    if lattice is not None:
+        px, py, pz = lattice
+        if px * py * pz != ppc:
+            raise ValueError("lattice must hold ppc points per cell")
+        i = idx.astype(np.int64)
+        c, sub = i // ppc, i % ppc
+        cell = (c % n[0], (c // n[0]) % n[1], c // (n[0] * n[1]))
+        frac = ((sub % px + 0.5) / px, ((sub // px) % py + 0.5) / py, (sub // (px * py) + 0.5) / pz)
+        lat = np.stack([cell[d] + frac[d] for d in range(3)]).astype(np.float64)
+        pos = {0: lat, 1: lat}
+    else:
+        for pop in (0, 1):  # 0 beam, 1 background
+            U = uniforms(seed, _stream(5, 2 * pop, 0), draw, 3)
+            pos[pop] = np.stack([np.where(U[d] * n[d] >= n[d], 0.0, U[d] * n[d]) for d in range(3)])
     sp = []
     for s, (nm, q, ion, beam) in enumerate(MMI_SPECIES):
         m = mass_ratio if ion else 1.0

@@ -46,7 +46,8 @@ def lib():
         L.ppi_kelvin_helmholtz.restype = ctypes.c_int
         L.ppi_mmi.argtypes = [ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, ctypes.c_int64,
                               ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
-                              ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+                              ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(vp),
+                              ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         L.ppi_mmi.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -101,16 +102,18 @@ def kelvin_helmholtz(seed, n, start, count, v0, width, uth, split, cells, offs, 
         raise RuntimeError(f"ppi_kelvin_helmholtz failed ({rc})")
 
 
-def mmi(seed, n, start, count, gamma_b, T_b, T_p, mass_ratio, split, cells, offs, us, hip_stream, quiet=False):
+def mmi(seed, n, start, count, gamma_b, T_b, T_p, mass_ratio, split, cells, offs, us, hip_stream, quiet=False,
+        lattice=None):
     """Mixed-mode two-stream load of particle indices [start, start+count) of four species
-    (see inputs.mmi, ``quiet`` its quiet start) into device tensors: cells [4] int32 (split)
-    or None, offs/us [[3] x 4]."""
+    (see inputs.mmi, ``quiet`` and ``lattice`` its quiet start and lattice positions) into
+    device tensors: cells [4] int32 (split) or None, offs/us [[3] x 4]."""
     vp = ctypes.c_void_p
     n_arr = (ctypes.c_int32 * 3)(*[int(v) for v in n])
     cell_arr = (vp * 4)(*([c.data_ptr() for c in cells] if cells is not None else [None] * 4))
     off_arr = (vp * 12)(*[offs[s][d].data_ptr() for s in range(4) for d in range(3)])
     u_arr = (vp * 12)(*[us[s][d].data_ptr() for s in range(4) for d in range(3)])
-    rc = lib().ppi_mmi(seed, n_arr, start, count, gamma_b, T_b, T_p, mass_ratio, int(bool(quiet)), int(split),
+    lat = (ctypes.c_int32 * 3)(*[int(v) for v in lattice]) if lattice is not None else None
+    rc = lib().ppi_mmi(seed, n_arr, start, count, gamma_b, T_b, T_p, mass_ratio, int(bool(quiet)), lat, int(split),
                        cell_arr, off_arr, u_arr, hip_stream)
     if rc:
         raise RuntimeError(f"ppi_mmi failed ({rc})")

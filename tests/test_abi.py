@@ -65,3 +65,19 @@ int main(void) {
         if "." in key:
             T, F = key.split(".")
             assert int(v) == getattr(getattr(pp, T), F).offset, key
+
+
+def test_mmi_generator_binding_marshals_every_argument():
+    # an empty range returns before any device work, after the argument checks: the ctypes
+    # signature of the loader (quiet flag, lattice pointer, split mode, the pointer tables)
+    # reaches the library intact, and a lattice extent below 1 is refused
+    import torch
+    from paper_1211_4575_amd import inputs_device as ind
+    n = (8, 6, 5)
+    cells = [torch.empty(1, dtype=torch.int32) for _ in range(4)]
+    offs = [[torch.empty(1, dtype=torch.float32) for _ in range(3)] for _ in range(4)]
+    us = [[torch.empty(1, dtype=torch.float32) for _ in range(3)] for _ in range(4)]
+    for quiet, lattice in ((False, None), (True, None), (True, (2, 2, 5))):
+        ind.mmi(1, n, 0, 0, 4.0, 0.01, 0.1, 1836.0, 2, cells, offs, us, None, quiet=quiet, lattice=lattice)
+    with pytest.raises(RuntimeError):
+        ind.mmi(1, n, 0, 0, 4.0, 0.01, 0.1, 1836.0, 2, cells, offs, us, None, lattice=(0, 2, 5))

@@ -105,20 +105,22 @@ def test_device_kelvin_helmholtz_matches_host(split):
             assert np.max(np.abs(u - uref)) <= 1e-14 * np.max(np.abs(uref))
 
 
-@pytest.mark.parametrize("split,quiet", [(0, False), (2, False), (0, True), (2, True)])
-def test_device_mmi_matches_host(split, quiet):
+@pytest.mark.parametrize("split,quiet,lattice", [(0, False, None), (2, False, None), (0, True, None),
+                                                 (2, True, None), (0, True, (1, 1, 3)), (2, False, (3, 1, 1))])
+def test_device_mmi_matches_host(split, quiet, lattice):
     import torch
     from paper_1211_4575_amd import inputs_device as ind
     n, ppc = (8, 6, 5), 3
     start, stop = 37, 8 * 6 * 5 * 3
-    wl = I.mmi(n=n, ppc=ppc, index_range=(start, stop), quiet=quiet)
+    wl = I.mmi(n=n, ppc=ppc, index_range=(start, stop), quiet=quiet, lattice=lattice)
     cnt = stop - start
     rt = torch.float32 if split else torch.float64
     cells = [torch.empty(cnt, dtype=torch.int32, device="cuda") for _ in range(4)] if split else None
     offs = [torch.empty((3, cnt), dtype=rt, device="cuda") for _ in range(4)]
     us = [torch.empty((3, cnt), dtype=rt, device="cuda") for _ in range(4)]
     ind.mmi(I.SEED_BASE, n, start, cnt, 4.0, 0.01, 0.1, 1836.0, split, cells, [[o[d] for d in range(3)] for o in offs],
-            [[u[d] for d in range(3)] for u in us], torch.cuda.current_stream().cuda_stream, quiet=quiet)
+            [[u[d] for d in range(3)] for u in us], torch.cuda.current_stream().cuda_stream, quiet=quiet,
+            lattice=lattice)
     torch.cuda.synchronize()
     for s in range(4):
         sp = wl.species[s]

@@ -203,6 +203,27 @@ def test_mmi_loader_is_neutral_and_boosted():
     assert round(r["mmi"], 3) == 0.201 and round(r["fi"], 3) == 0.153 and round(r["tsi"], 3) == 0.080
 
 
+def test_mmi_lattice_positions_fill_every_cell_evenly():
+    # lattice loading: ppc points per cell on a regular sub-lattice, every cell holding exactly
+    # ppc particles of each species, at the same points in every cell; velocities unchanged
+    from paper_1211_4575_amd import inputs as I
+    n, ppc = (6, 5, 4), 12
+    wl = I.mmi(n=n, ppc=ppc, lattice=(2, 2, 3))
+    noisy = I.mmi(n=n, ppc=ppc)
+    for sp, sn in zip(wl.species, noisy.species):
+        cell = np.floor(sp.pos).astype(np.int64)
+        lin = cell[0] + n[0] * (cell[1] + n[1] * cell[2])
+        assert np.array_equal(np.bincount(lin, minlength=n[0] * n[1] * n[2]), np.full(n[0] * n[1] * n[2], ppc))
+        frac = sp.pos - cell
+        assert set(np.round(frac[0], 12)) == {0.25, 0.75} and set(np.round(frac[1], 12)) == {0.25, 0.75}
+        assert set(np.round(frac[2], 12)) == {round(1 / 6, 12), 0.5, round(5 / 6, 12)}
+        assert np.array_equal(sp.u, sn.u)
+        # the mean position of a cell's points is its centre
+        np.testing.assert_allclose(frac.reshape(3, -1, ppc).mean(axis=2), 0.5, atol=1e-12)
+    with pytest.raises(ValueError):
+        I.mmi(n=n, ppc=ppc, lattice=(2, 2, 2))
+
+
 def test_mmi_quiet_start_pairs_cancel_the_thermal_current():
     # quiet start: particles 2k and 2k+1 of every species sit at one position with opposite
     # rest-frame thermal velocities, so each pair of the background (no boost) carries no
