@@ -952,6 +952,7 @@ __device__ __forceinline__ void line_body(const LineArgs& A, int64_t b) {
 // x at a time (stored with the W lines interleaved, x fastest), so loads and stores move
 // whole rows or W-wide row segments.
 constexpr int LINE_LDS_DOUBLES = 4608;  // 36 KiB: 16 lines of 256 cells plus the wrap-around
+constexpr int LINE_BATCH = 8;           // loads per thread in flight while a block fills its lines
 
 __device__ __forceinline__ void line_lds_body(const LineArgs& A, int64_t b, double* e) {
     const FieldGeom& G = A.G;
@@ -992,18 +993,35 @@ __device__ __forceinline__ void line_lds_body(const LineArgs& A, int64_t b, doub
     // line w starts at base0 + w * (x lines: n0, else 1)
     const int64_t lstep = c == 0 ? n0 : 1;
     const int total = ext * W;
-    for (int q = threadIdx.x; q < total; q += FIELD_BS) {
-        int w, jj;
-        if (c == 0) {
-            w = q / ext;
-            jj = q - w * ext;
-        } else {
-            jj = q / W;
-            w = q - jj * W;
+    // global memory (not generic) loads, which the LDS stores need not wait behind
+    const __attribute__((address_space(1))) double* gsrc = (const __attribute__((address_space(1))) double*)src;
+    // LINE_BATCH loads per thread in flight before the first is stored; every lane loads (an
+    // entry past the end or of a line past the last reads the block's first value and stores
+    // nothing or zero), so that no load waits at a branch
+    for (int q0 = threadIdx.x; q0 < total; q0 += LINE_BATCH * FIELD_BS) {
+        double v[LINE_BATCH];
+        int dst[LINE_BATCH];  // LDS entry, or -1 past the end
+        bool live[LINE_BATCH];
+#pragma unroll
+        for (int t = 0; t < LINE_BATCH; ++t) {
+            const int q = q0 + t * FIELD_BS;
+            const int qc = q < total ? q : 0;
+            int w, jj;
+            if (c == 0) {
+                w = qc / ext;
+                jj = qc - w * ext;
+            } else {
+                jj = qc / W;
+                w = qc - jj * W;
+            }
+            const int sidx = wrap_near(off + jj, N);
+            live[t] = w < nlines;
+            v[t] = gsrc[base0 + (live[t] ? w : 0) * lstep + (int64_t)sidx * stride];
+            dst[t] = q < total ? q : -1;
         }
-        int sidx = (off + jj) % N;
-        if (sidx < 0) sidx += N;
-        e[q] = w < nlines ? src[base0 + w * lstep + (int64_t)sidx * stride] : 0.0;
+#pragma unroll
+        for (int t = 0; t < LINE_BATCH; ++t)
+            if (dst[t] >= 0) e[dst[t]] = live[t] ? v[t] : 0.0;
     }
     __syncthreads();
     const int outs = N * W;
@@ -1021,7 +1039,8 @@ __device__ __forceinline__ void line_lds_body(const LineArgs& A, int64_t b, doub
             es = W;
         }
         if (w >= nlines) continue;
-        const double* cf = A.coef[c];
+        // the coefficients are the same for the whole block: read-only, uniform (scalar) loads
+        const __attribute__((address_space(4))) double* cf = (const __attribute__((address_space(4))) double*)A.coef[c];
         double s = 0.0;
         for (int t = 0; t < len; ++t) s += cf[t] * e[eb + t * es];
         dst[base0 + w * lstep + (int64_t)j * stride] = s;
