@@ -296,17 +296,15 @@ __global__ void __launch_bounds__(RX_BS) k_relax_tiled(FieldDesc D, int k) {
                 if (hl[e] >= 0) pl[hl[e]] = hv[e];
             __syncthreads();
             const bool more = kz + 1 < z1;
-            double qn = 0.0, rn = 0.0, pn = 0.0;
-            if (more) {
-                qn = x[lin(G, iw, jw, nbw(kz + 1, R, n2, G.small))];
+            // the next plane's loads, unconditional (the last plane reloads its own plane, a lane
+            // off the ring or the box reads the entries hg = 0 / own = 0) so that none waits at
+            // a branch: they are first used by the next plane
+            const int kn = more ? kz + 1 : kz;
+            const double qn = x[lin(G, iw, jw, nbw(kn, R, n2, G.small))];
 #pragma unroll
-                for (int e = 0; e < NH; ++e)
-                    if (hl[e] >= 0) hv[e] = x[hg[e] + (kz + 1) * nxy];
-                if (valid) {
-                    rn = rhs[own + (kz + 1) * nxy];
-                    pn = pv[own + (kz + 1) * nxy];
-                }
-            }
+            for (int e = 0; e < NH; ++e) hv[e] = x[hg[e] + kn * nxy];
+            const double rn = rhs[own + kn * nxy];
+            const double pn = pv[own + kn * nxy];
             if (valid) {
                 double sl = 0.0;
 #pragma unroll
