@@ -279,20 +279,24 @@ __device__ __forceinline__ void pair_table(int k, int rmax, Put put, int32_t& nc
     for (int base = 0; base < rmax; base += 64) {
         const int nr = rmax - base < 64 ? rmax - base : 64;
         RoundEntry mine{0ull, 0ull, 0, 0};
-        for (int rr = 0; rr < nr; ++rr) {
+        // the two ranks 2R, 2R + 1 of a pair round share its pair mask (base is even)
+        for (int rr = 0; rr < nr; rr += 2) {
             const int r = base + rr;
-            const uint64_t pm = __ballot(k >= (r | 1) + 1);  // cells with a pair of ranks 2R, 2R + 1
+            const uint64_t pm = __ballot(k >= r + 2);  // cells with a pair of ranks r, r + 1
             const int32_t g = pb + (int32_t)__popcll(pm & below);
             const bool chunked = ((pm >> lane) & 1ull) && g < (nchunk << 6);
-            const uint64_t sm = __ballot(k > r && !chunked);
-            if (lane == rr) {
+            const uint64_t sm0 = __ballot(k > r && !chunked);
+            const uint64_t sm1 = __ballot(k > r + 1 && !chunked);
+            const int32_t sb1 = sb + (int32_t)__popcll(sm0);
+            if (lane == rr || lane == rr + 1) {
                 mine.pmask = pm;
-                mine.smask = sm;
+                mine.smask = lane == rr ? sm0 : sm1;
                 mine.pbefore = pb;
-                mine.sbefore = sb;
+                mine.sbefore = lane == rr ? sb : sb1;
             }
-            sb += (int32_t)__popcll(sm);
-            if (r & 1) pb += (int32_t)__popcll(pm);
+            // a last rank without its partner (nr odd) counts only its own single particles
+            sb = rr + 1 < nr ? sb1 + (int32_t)__popcll(sm1) : sb1;
+            pb += (int32_t)__popcll(pm);
         }
         if (lane < nr) put(base + lane, mine);
     }
