@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+import pytest
 
 import bench
 
@@ -96,6 +97,49 @@ def test_counter_summary_round_trip(tmp_path, monkeypatch):
     assert float(vals["fetch_kib_per_launch"]) == 7e7
     assert float(vals["kernel_ms"]) == 100.0
     assert vals["kernel_source_digest"] == "d" * 16 and "cmd a" in text
+
+
+def test_counter_summary_sums_the_split_elementwise_pass(tmp_path, monkeypatch):
+    # the elementwise calibration pass over 4 GiB comes as several dispatches (torch splits a
+    # tensor this large): their counters and durations are summed, so the factors per byte and
+    # the stream rate refer to the whole 4 GiB; the fastest plain stream becomes the roofline's
+    # stream reference
+    import csv
+    k = "void pp::k_gpd32<3, pp::TileCT<3, 4, 4, 4, false> >(pp::Gpd32Args)"
+    ew = "void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel_cuda(...)>"
+    cols = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+    gib4_kib = 4 * (1 << 30) / 1024.0
+    d = tmp_path / "p"
+    d.mkdir()
+    with open(d / "run_counter_collection.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=cols)
+        w.writeheader()
+        for i in range(2):  # two launches of the particle kernel, 80 ms each
+            w.writerow(dict(Dispatch_Id=10 + i, Kernel_Name=k, Counter_Name="FETCH_SIZE", Counter_Value=4e7,
+                            Start_Timestamp=0, End_Timestamp=int(80e6)))
+        # the copy: 2 ms, counter half the bytes read
+        w.writerow(dict(Dispatch_Id=1, Kernel_Name="__amd_rocclr_copyBuffer", Counter_Name="FETCH_SIZE",
+                        Counter_Value=0.5 * gib4_kib, Start_Timestamp=0, End_Timestamp=int(2e6)))
+        # the elementwise pass: two dispatches of 0.7 ms, each reading 2 GiB (counter: half of it)
+        for i in range(2):
+            w.writerow(dict(Dispatch_Id=2 + i, Kernel_Name=ew, Counter_Name="FETCH_SIZE",
+                            Counter_Value=0.25 * gib4_kib, Start_Timestamp=0, End_Timestamp=int(0.7e6)))
+    out = tmp_path / "summary.md"
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: "e" * 16)
+    bench.counter_summary([str(d)], str(out), 1_000_000, ["cmd"])
+    text = out.read_text()
+    vals = dict(line[2:].split(": ", 1) for line in text.splitlines() if line.startswith("- "))
+    assert float(vals["ew_fetch_kib"]) == pytest.approx(0.5 * gib4_kib)  # both dispatches
+    assert float(vals["ew_gbs"]) == pytest.approx(8 * (1 << 30) / 1.4e-3 / 1e9)  # 8 GiB in 1.4 ms
+    assert float(vals["copy_gbs"]) == pytest.approx(8 * (1 << 30) / 2e-3 / 1e9)
+    assert "2 dispatches" in text and "(factor 0.500)" in text
+    # the roofline takes the faster stream as its reference
+    cs = {k: float(v) for k, v in vals.items() if k != "kernel_source_digest"}
+    monkeypatch.setattr(bench, "read_counter_summary", lambda n: cs)
+    monkeypatch.setattr(bench, "measured_traffic", lambda n: None)
+    r = bench.kernel_roofline(1_000_000, 80.0)
+    assert r["stream_peak_gbs"] == pytest.approx(cs["ew_gbs"], abs=0.05)  # reported to 0.1 GB/s
+    assert r["frac_of_stream"] == pytest.approx(r["achieved"] / cs["ew_gbs"], rel=1e-3)
 
 
 def test_measured_traffic_is_used_only_for_the_kernel_sources_it_was_taken_on(monkeypatch):
