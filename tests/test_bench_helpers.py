@@ -137,7 +137,7 @@ def test_counter_summary_sums_the_split_elementwise_pass(tmp_path, monkeypatch):
     cs = {k: float(v) for k, v in vals.items() if k != "kernel_source_digest"}
     monkeypatch.setattr(bench, "read_counter_summary", lambda n: cs)
     monkeypatch.setattr(bench, "measured_traffic", lambda n: None)
-    r = bench.kernel_roofline(1_000_000, 80.0)
+    r = bench.kernel_roofline(1_000_000_000, 80.0)  # 700 GB/s algorithmic
     assert r["stream_peak_gbs"] == pytest.approx(cs["ew_gbs"], abs=0.05)  # reported to 0.1 GB/s
     assert r["frac_of_stream"] == pytest.approx(r["achieved"] / cs["ew_gbs"], rel=1e-3)
 
